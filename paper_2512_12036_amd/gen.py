@@ -1,0 +1,306 @@
+"""Seeded synthetic inputs for the SpGEMM path.
+
+This module only *builds inputs*: sparsity patterns and the values stored in
+them.  It holds none of the product's arithmetic and is shared by the CPU
+oracle tests and the GPU path alike.  Every generator is deterministic in its
+seed (numpy PCG64).
+
+Workload recipes (shapes follow the paper's evaluation workloads, see the
+paper's Table II for the self-product matrices, Algorithms 6/7 for the graph
+applications and Eq. 1-2 for the pruned GNN aggregation):
+
+* ``er``: Erdos-Renyi G(n, M) with exactly M distinct positions (diagonal
+  allowed), FP32 values uniform in [-1, 1].
+* ``rmat``: recursive-matrix graph, directed, one quadrant draw per level with
+  probabilities (a, b, c, d), no noise, no vertex permutation, self loops kept,
+  duplicate edges merged before values are drawn; FP32 values in (0, 1].
+* ``planted_partition``: undirected community graph with self loops,
+  column-stochastic (unit weights divided by the column sum).  Stored
+  transposed (row-stochastic), so that column operations become row
+  operations.
+* ``contraction_labels``: one uniform cluster id per vertex, and the n x k
+  selector matrix S with a single 1.0 per row.
+* ``gnn_request``: symmetric-normalised adjacency D^-1/2 (A + I) D^-1/2 of an
+  undirected G(n, M = n d / 2) graph and a structurally pruned feature matrix
+  X whose kept columns K are dense with values in (0, 1].
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Csr:
+    """Host CSR matrix: int64 row pointers, int32 columns, FP32 values."""
+
+    nrows: int
+    ncols: int
+    rpt: np.ndarray  # int64 [nrows + 1]
+    col: np.ndarray  # int32 [nnz]
+    val: np.ndarray  # float32 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rpt[-1])
+
+    def row(self, i: int):
+        s, e = int(self.rpt[i]), int(self.rpt[i + 1])
+        return self.col[s:e], self.val[s:e]
+
+    def with_values(self, val: np.ndarray) -> "Csr":
+        return Csr(self.nrows, self.ncols, self.rpt, self.col,
+                   np.ascontiguousarray(val, dtype=np.float32))
+
+
+def from_coo(nrows: int, ncols: int, rows: np.ndarray, cols: np.ndarray,
+             vals: np.ndarray | None = None, merge: bool = True) -> Csr:
+    """Build a row-sorted CSR from coordinates.  With ``merge`` duplicate
+    coordinates are collapsed to one entry (keeping the first value)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    key = rows * np.int64(ncols) + cols
+    if merge:
+        key, first = np.unique(key, return_index=True)
+        if vals is not None:
+            vals = np.asarray(vals)[first]
+    else:
+        order = np.argsort(key, kind="stable")
+        key = key[order]
+        if vals is not None:
+            vals = np.asarray(vals)[order]
+    r = key // ncols
+    c = key - r * ncols
+    rpt = np.zeros(nrows + 1, dtype=np.int64)
+    np.add.at(rpt, r + 1, 1)
+    rpt = np.cumsum(rpt)
+    if vals is None:
+        vals = np.ones(key.shape[0], dtype=np.float32)
+    return Csr(nrows, ncols, rpt.astype(np.int64), c.astype(np.int32),
+               np.ascontiguousarray(vals, dtype=np.float32))
+
+
+def _unit_open_low(rng: np.random.Generator, size) -> np.ndarray:
+    """FP32 values in (0, 1]."""
+    return (1.0 - rng.random(size)).astype(np.float32)
+
+
+def er(n: int, nnz: int, seed: int, ncols: int | None = None,
+       lo: float = -1.0, hi: float = 1.0) -> Csr:
+    """G(n, M): exactly ``nnz`` distinct positions uniform over n x ncols."""
+    ncols = n if ncols is None else ncols
+    rng = np.random.default_rng(seed)
+    total = n * ncols
+    if nnz > total:
+        raise ValueError("more nonzeros than positions")
+    if total <= 50_000_000:
+        pos = rng.choice(total, size=nnz, replace=False)
+    else:
+        got = np.empty(0, dtype=np.int64)
+        while got.shape[0] < nnz:
+            extra = rng.integers(0, total, size=int((nnz - got.shape[0]) * 1.1) + 16)
+            got = np.unique(np.concatenate([got, extra]))
+        pos = rng.permutation(got)[:nnz]
+    pos = np.sort(pos)
+    rows = pos // ncols
+    cols = pos - rows * ncols
+    vals = rng.uniform(lo, hi, size=nnz).astype(np.float32)
+    return from_coo(n, ncols, rows, cols, vals, merge=False)
+
+
+def rmat_edges(scale: int, edge_factor: int, abcd=(0.57, 0.19, 0.19, 0.05),
+               seed: int = 2) -> tuple[np.ndarray, np.ndarray]:
+    """Raw R-MAT samples (duplicates not merged), highest bit first."""
+    a, b, c, _ = abcd
+    n_edges = edge_factor * (1 << scale)
+    rng = np.random.default_rng(seed)
+    rows = np.zeros(n_edges, dtype=np.int64)
+    cols = np.zeros(n_edges, dtype=np.int64)
+    for _ in range(scale):
+        u = rng.random(n_edges)
+        rbit = u >= (a + b)
+        cbit = ((u >= a) & (u < a + b)) | (u >= (a + b + c))
+        rows = (rows << 1) | rbit
+        cols = (cols << 1) | cbit
+    return rows, cols
+
+
+def rmat(scale: int, edge_factor: int, abcd=(0.57, 0.19, 0.19, 0.05),
+         seed: int = 2) -> Csr:
+    """Directed R-MAT, duplicates merged, FP32 values in (0, 1]."""
+    n = 1 << scale
+    rows, cols = rmat_edges(scale, edge_factor, abcd, seed)
+    m = from_coo(n, n, rows, cols, None, merge=True)
+    rng = np.random.default_rng(seed + 1_000_003)
+    m.val = _unit_open_low(rng, m.nnz)
+    return m
+
+
+def planted_partition(n_comm: int = 1000, comm_size: int = 100,
+                      intra_deg: float = 25.0, inter_deg: float = 5.0,
+                      seed: int = 5) -> Csr:
+    """Undirected community graph + self loops, column-stochastic, returned
+    transposed (row i holds column i of the column-stochastic matrix)."""
+    rng = np.random.default_rng(seed)
+    n = n_comm * comm_size
+    p_in = intra_deg / (comm_size - 1)
+    p_out = inter_deg / (n - comm_size)
+    iu, ju = np.triu_indices(comm_size, k=1)
+    keep = rng.random((n_comm, iu.shape[0])) < p_in
+    cidx, pidx = np.nonzero(keep)
+    u_in = cidx * comm_size + iu[pidx]
+    v_in = cidx * comm_size + ju[pidx]
+    inter_pairs = n * (n - comm_size) // 2
+    m_out = rng.binomial(inter_pairs, p_out)
+    got_u = np.empty(0, dtype=np.int64)
+    got_v = np.empty(0, dtype=np.int64)
+    while got_u.shape[0] < m_out:
+        need = int((m_out - got_u.shape[0]) * 1.05) + 64
+        u = rng.integers(0, n, size=need)
+        v = rng.integers(0, n, size=need)
+        ok = (u // comm_size) != (v // comm_size)
+        u, v = np.minimum(u[ok], v[ok]), np.maximum(u[ok], v[ok])
+        key = np.concatenate([got_u * n + got_v, u * n + v])
+        _, first = np.unique(key, return_index=True)
+        first = np.sort(first)
+        key = key[first]
+        got_u, got_v = key // n, key % n
+    got_u, got_v = got_u[:m_out], got_v[:m_out]
+    diag = np.arange(n, dtype=np.int64)
+    rows = np.concatenate([u_in, v_in, got_u, got_v, diag])
+    cols = np.concatenate([v_in, u_in, got_v, got_u, diag])
+    g = from_coo(n, n, rows, cols, None, merge=True)
+    # The graph is symmetric, so column sums equal row lengths; the
+    # transposed column-stochastic matrix is the row-normalised adjacency.
+    deg = np.diff(g.rpt).astype(np.float64)
+    rid = np.repeat(np.arange(n), np.diff(g.rpt))
+    g.val = (1.0 / deg[rid]).astype(np.float32)
+    return g
+
+
+def contraction_labels(n: int, k: int, seed: int = 3) -> np.ndarray:
+    """One uniform cluster id in [0, k) per vertex (int32)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, k, size=n).astype(np.int32)
+
+
+def selector(labels: np.ndarray, k: int) -> Csr:
+    """n x k matrix with S[v, labels[v]] = 1.0."""
+    n = labels.shape[0]
+    rpt = np.arange(n + 1, dtype=np.int64)
+    return Csr(n, k, rpt, labels.astype(np.int32), np.ones(n, dtype=np.float32))
+
+
+@dataclasses.dataclass
+class GnnRequest:
+    """One served aggregation request C = A_hat X."""
+
+    a_hat: Csr
+    x: Csr
+    n: int
+    avg_degree: float
+    features: int
+    kept: np.ndarray  # int32 sorted kept columns
+
+
+def gnn_request_params(seed: int, n_lo: int = 1000, n_hi: int = 200_000):
+    rng = np.random.default_rng(seed)
+    n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+    d = float(rng.uniform(5.0, 50.0))
+    f = int(rng.integers(64, 513))
+    rho = float(rng.uniform(0.1, 0.5))
+    return n, d, f, rho
+
+
+def gnn_request(seed: int, n: int | None = None, d: float | None = None,
+                f: int | None = None, rho: float | None = None) -> GnnRequest:
+    pn, pd, pf, prho = gnn_request_params(seed)
+    n = pn if n is None else n
+    d = pd if d is None else d
+    f = pf if f is None else f
+    rho = prho if rho is None else rho
+    rng = np.random.default_rng(seed * 7919 + 17)
+    m_edges = int(round(n * d / 2.0))
+    m_edges = min(m_edges, n * (n - 1) // 2)
+    got = np.empty(0, dtype=np.int64)
+    while got.shape[0] < m_edges:
+        need = int((m_edges - got.shape[0]) * 1.05) + 16
+        u = rng.integers(0, n, size=need)
+        v = rng.integers(0, n, size=need)
+        ok = u != v
+        u, v = np.minimum(u[ok], v[ok]), np.maximum(u[ok], v[ok])
+        key = np.concatenate([got, u * n + v])
+        _, first = np.unique(key, return_index=True)
+        got = key[np.sort(first)]
+    got = got[:m_edges]
+    u, v = got // n, got % n
+    diag = np.arange(n, dtype=np.int64)
+    rows = np.concatenate([u, v, diag])
+    cols = np.concatenate([v, u, diag])
+    a = from_coo(n, n, rows, cols, None, merge=True)
+    deg = np.diff(a.rpt).astype(np.float64)
+    rid = np.repeat(np.arange(n), np.diff(a.rpt))
+    dinv = 1.0 / np.sqrt(deg)
+    a.val = (dinv[rid] * dinv[a.col.astype(np.int64)]).astype(np.float32)
+    nk = max(1, int(round(rho * f)))
+    kept = np.sort(rng.choice(f, size=nk, replace=False)).astype(np.int32)
+    xrpt = np.arange(n + 1, dtype=np.int64) * nk
+    xcol = np.tile(kept, n)
+    xval = _unit_open_low(rng, n * nk)
+    x = Csr(n, f, xrpt, xcol, xval)
+    return GnnRequest(a, x, n, d, f, kept)
+
+
+def int_valued(m: Csr, seed: int, lo: int = -3, hi: int = 3) -> Csr:
+    """Same structure, nonzero integer values in [lo, hi] (exact in FP32)."""
+    rng = np.random.default_rng(seed)
+    choices = np.array([v for v in range(lo, hi + 1) if v != 0], dtype=np.float32)
+    return m.with_values(rng.choice(choices, size=m.nnz))
+
+
+def ones_valued(m: Csr) -> Csr:
+    return m.with_values(np.ones(m.nnz, dtype=np.float32))
+
+
+def shuffle_rows(m: Csr, seed: int) -> Csr:
+    """Same matrix with the entries of every row stored in random order."""
+    rng = np.random.default_rng(seed)
+    rid = np.repeat(np.arange(m.nrows), np.diff(m.rpt))
+    order = np.lexsort((rng.random(m.nnz), rid))
+    return Csr(m.nrows, m.ncols, m.rpt.copy(), m.col[order].copy(), m.val[order].copy())
+
+
+def random_csr(nrows: int, ncols: int, density: float, seed: int,
+               lo: float = -1.0, hi: float = 1.0) -> Csr:
+    """Small Bernoulli(density) matrix for brute-force checks."""
+    rng = np.random.default_rng(seed)
+    mask = rng.random((nrows, ncols)) < density
+    r, c = np.nonzero(mask)
+    v = rng.uniform(lo, hi, size=r.shape[0]).astype(np.float32)
+    return from_coo(nrows, ncols, r, c, v, merge=False)
+
+
+def skewed_csr(nrows: int, ncols: int, seed: int, max_len: int,
+               heavy_rows: int = 4, heavy_len: int | None = None) -> Csr:
+    """Rows with geometric lengths plus a few very long rows; used to reach
+    every bin of the multi-phase path at small size."""
+    rng = np.random.default_rng(seed)
+    lens = np.minimum(rng.geometric(0.15, size=nrows) - 1, max_len)
+    if heavy_rows:
+        idx = rng.choice(nrows, size=min(heavy_rows, nrows), replace=False)
+        lens[idx] = min(ncols, heavy_len or ncols // 2)
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        if ln:
+            cols.append(rng.choice(ncols, size=int(ln), replace=False))
+            rows.append(np.full(int(ln), i, dtype=np.int64))
+    if rows:
+        rows = np.concatenate(rows)
+        cols = np.concatenate(cols)
+    else:
+        rows = np.zeros(0, dtype=np.int64)
+        cols = np.zeros(0, dtype=np.int64)
+    vals = rng.uniform(-1.0, 1.0, size=rows.shape[0]).astype(np.float32)
+    return from_coo(nrows, ncols, rows, cols, vals, merge=False)
