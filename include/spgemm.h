@@ -1,0 +1,223 @@
+/*
+ * spgemm.h -- C ABI of the MI355X (gfx950) hash-based multi-phase SpGEMM.
+ *
+ * Computes C = A * B for sparse A (m x k) and B (k x n) in compressed-row
+ * storage (paper Section I states the problem; Section III the method).  The
+ * work is split into the phases of paper Section III:
+ *
+ *   spgemm_plan_create   row-size estimation: intermediate products per row
+ *                        (paper Algorithm 1) and row grouping by that count
+ *                        (paper Section III-B, Table I).
+ *   spgemm_symbolic      allocation phase: distinct output columns per row
+ *                        with hash tables (paper Algorithms 2-4, keys only),
+ *                        then the exclusive scan that yields C's row
+ *                        pointers (paper Algorithms 2-3, last step).
+ *   spgemm_numeric       accumulation phase: hash accumulation of the
+ *                        products (paper Algorithms 4-5), gathering of the
+ *                        occupied slots and ascending column sort of every
+ *                        row (paper Section III-D).
+ *   spgemm_free          releases a plan.
+ *
+ * Conventions for every entry point:
+ *  - Pointers inside spgemm_csr and the output arrays are DEVICE pointers
+ *    unless a parameter says "host".
+ *  - Index types: row pointers int64, column indices int32, values FP32.
+ *  - All work is enqueued on the HIP stream given at plan creation.  Only the
+ *    calls documented as synchronising wait for the stream.
+ *  - Errors are returned as spgemm_status; nothing aborts and no C++
+ *    exception crosses the ABI.  After any failure the plan can still be
+ *    freed.  A plan is not thread safe; distinct plans are independent.
+ *  - Output contract: every row of C has strictly ascending columns, no
+ *    duplicates, and keeps explicit zeros produced by cancellation (the
+ *    structure of C is the boolean product of the stored patterns).
+ *  - Values: each product a*b is rounded to FP32 and added in FP32 (paper
+ *    Algorithm 4 adds valA x valB atomically); the order of the additions is
+ *    not fixed, so values may differ in the last bits between runs while the
+ *    structure is always identical.
+ */
+#ifndef SPGEMM_H
+#define SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPGEMM_OK = 0,
+    SPGEMM_EINVAL = 1,     /* NULL pointer, negative size, bad option value   */
+    SPGEMM_EDIM = 2,       /* A.ncols != B.nrows, or a dimension out of range  */
+    SPGEMM_EINDEX = 3,     /* device validation found a malformed CSR          */
+    SPGEMM_EOVERFLOW = 4,  /* a count exceeds what the library's types hold    */
+    SPGEMM_ENOMEM = 5,     /* the allocator returned NULL                      */
+    SPGEMM_EHIP = 6,       /* a HIP runtime call failed                        */
+    SPGEMM_ESTATE = 7,     /* calls made out of order                          */
+    SPGEMM_EINTERNAL = 8   /* a kernel raised its error flag (probe limit,
+                              symbolic / numeric count mismatch)               */
+} spgemm_status;
+
+/* spgemm_csr.flags: every row stores strictly ascending columns. */
+#define SPGEMM_ROWS_SORTED 1u
+
+/* A sparse matrix in compressed-row storage.  All arrays are device memory
+ * owned by the caller and borrowed by the library until the stream has
+ * passed the last call that reads them. */
+typedef struct {
+    int64_t nrows;           /* >= 0, < 2^31                                   */
+    int64_t ncols;           /* >= 0, < 2^31                                   */
+    int64_t nnz;             /* == row_ptr[nrows]                              */
+    const int64_t *row_ptr;  /* nrows + 1 entries, non-decreasing, [0] = 0     */
+    const int32_t *col_idx;  /* nnz entries, 0 <= c < ncols; duplicates in a
+                                row are summed                                 */
+    const float *values;     /* nnz entries; may be NULL until spgemm_numeric  */
+    uint32_t flags;          /* SPGEMM_ROWS_SORTED or 0 (then detected)        */
+} spgemm_csr;
+
+/* Device allocator used for all workspace (for example PyTorch's caching
+ * allocator).  alloc returns NULL on failure.  Both may be NULL in
+ * spgemm_plan_create, in which case hipMalloc / hipFree are used. */
+typedef void *(*spgemm_alloc_fn)(void *ctx, size_t bytes, void *stream);
+typedef void (*spgemm_free_fn)(void *ctx, void *ptr, void *stream);
+
+/* Number of row groups.  Group 0 holds rows with nothing to do (no
+ * intermediate products, or no output), groups 1-4 rows handled by 8, 16,
+ * 32 or 64 lanes with a per-row LDS hash table of 8 slots per lane, groups
+ * 5-6 rows handled by a 256- or 512-thread workgroup with an LDS hash table,
+ * group 7 rows handled as column chunks with an LDS bitmap (symbolic) or an
+ * LDS dense accumulator (numeric).  Paper Table I gives the four groups used
+ * on the paper's GPU; these are the gfx950 equivalents. */
+#define SPGEMM_NGROUPS 8
+
+typedef struct {
+    /* Inclusive upper bounds of groups 1..6 (index 0 unused, must be 0).
+     * Symbolic groups are keyed by the intermediate-product count of the row,
+     * numeric groups by its output length (paper Section III-C: the table
+     * size is first set from the intermediate products, then from the
+     * distinct count).  Non-decreasing.  Capacities (maximum legal bound):
+     *   symbolic: 63, 127, 255, 511, 8191, 32767
+     *   numeric : 63, 127, 255, 511, 2047, 8191
+     * and sym_upper[6] <= num_upper[6] (a row handled as chunks in the
+     * numeric phase must have been handled as chunks in the symbolic one). */
+    int64_t sym_upper[SPGEMM_NGROUPS - 1];
+    int64_t num_upper[SPGEMM_NGROUPS - 1];
+    /* Maximum columns per chunk of group 7 (multiple of 64, 64 .. 32768).  The
+     * number of chunks per row is a multiple of 8 so that chunk c of every
+     * row runs on the same accelerator die (XCD c mod 8). */
+    int32_t chunk_cols;
+    /* 0: host-side checks only; 1: also check row_ptr / col_idx of A and B
+     * on the device (one pass each) and fail with SPGEMM_EINDEX. */
+    int32_t validate;
+    /* 1: record a HIP event pair around every kernel launch group on the
+     * plan's stream (read back with spgemm_timing). */
+    int32_t profile;
+    int32_t reserved[5];
+} spgemm_options;
+
+typedef struct spgemm_plan spgemm_plan;
+
+/* Per-plan figures, filled after each phase. */
+typedef struct {
+    int64_t flops;                         /* 2 * sum of intermediate products */
+    int64_t ip_total;                      /* sum of intermediate products     */
+    int64_t ip_max;                        /* largest row                      */
+    int64_t nnz_c;                         /* after spgemm_symbolic, else -1   */
+    int64_t sym_group_rows[SPGEMM_NGROUPS];
+    int64_t num_group_rows[SPGEMM_NGROUPS];/* after spgemm_symbolic            */
+    int64_t chunk_cols;                    /* chunk width used (product 0)     */
+    int64_t chunks_per_row;                /* chunks per group-7 row (prod. 0) */
+    size_t workspace_bytes;                /* device workspace held            */
+} spgemm_info;
+
+/* Fills *opt with the tuned defaults for gfx950. */
+void spgemm_default_options(spgemm_options *opt);
+
+/* Creates a plan for C = A * B and runs the row-size estimation (paper
+ * Algorithm 1) and the row grouping (paper Section III-B) on `stream`
+ * (a hipStream_t; NULL = default stream).  Synchronises the stream once to
+ * read the group sizes.  A and B describe structure only (values may be
+ * NULL); the descriptors are copied, the arrays they point to are borrowed.
+ * opt NULL = spgemm_default_options.  Errors: EINVAL, EDIM (A->ncols !=
+ * B->nrows or a size >= 2^31), EINDEX (validate = 1 and a malformed input),
+ * ENOMEM, EHIP.  On error *out is NULL. */
+spgemm_status spgemm_plan_create(spgemm_plan **out, const spgemm_csr *A,
+                                 const spgemm_csr *B, const spgemm_options *opt,
+                                 void *stream, spgemm_alloc_fn alloc_fn,
+                                 spgemm_free_fn free_fn, void *alloc_ctx);
+
+/* Same for `nprod` independent products C_p = A_p * B_p that share every
+ * launch: each phase runs one launch per row group over the rows of all
+ * products (a global group queue).  A and B are host arrays of nprod
+ * descriptors. */
+spgemm_status spgemm_plan_create_batch(spgemm_plan **out, int32_t nprod,
+                                       const spgemm_csr *A, const spgemm_csr *B,
+                                       const spgemm_options *opt, void *stream,
+                                       spgemm_alloc_fn alloc_fn,
+                                       spgemm_free_fn free_fn, void *alloc_ctx);
+
+/* Allocation phase (paper Algorithms 2-4, keys only) and row-pointer scan.
+ * Writes the m + 1 row pointers of C to c_row_ptr (device, caller owned).
+ * Synchronises the stream and returns nnz(C) in *nnz_c (host) and, when
+ * flops is not NULL, 2 * sum(IP) in *flops (host).  Must follow
+ * spgemm_plan_create exactly once (else ESTATE).  Single-product plans only
+ * (ESTATE on a batch plan). */
+spgemm_status spgemm_symbolic(spgemm_plan *p, int64_t *c_row_ptr,
+                              int64_t *nnz_c, int64_t *flops);
+
+/* Batch form: c_row_ptr is a host array of nprod device pointers (product p
+ * gets A_p.nrows + 1 entries); nnz_c a host array of nprod counts. */
+spgemm_status spgemm_symbolic_batch(spgemm_plan *p, int64_t *const *c_row_ptr,
+                                    int64_t *nnz_c);
+
+/* Accumulation phase (paper Algorithms 4-5, Section III-D): writes nnz(C)
+ * sorted column indices and FP32 values (device, caller owned) for the
+ * structure computed by spgemm_symbolic.  Asynchronous on the plan's stream.
+ * May be called again with new values for the same structures (value-only
+ * re-run).  a_values / b_values must hold A.nnz / B.nnz FP32 values.
+ * ESTATE before spgemm_symbolic. */
+spgemm_status spgemm_numeric(spgemm_plan *p, const float *a_values,
+                             const float *b_values, int32_t *c_col_idx,
+                             float *c_values);
+
+/* Batch form: host arrays of nprod device pointers each. */
+spgemm_status spgemm_numeric_batch(spgemm_plan *p, const float *const *a_values,
+                                   const float *const *b_values,
+                                   int32_t *const *c_col_idx,
+                                   float *const *c_values);
+
+/* Waits for the plan's stream and reports a kernel-raised error flag
+ * (EINTERNAL) or a failed launch (EHIP). */
+spgemm_status spgemm_sync(spgemm_plan *p);
+
+/* Fills *info (host).  Never synchronises. */
+spgemm_status spgemm_get_info(const spgemm_plan *p, spgemm_info *info);
+
+/* Copies internal per-row arrays into caller device buffers (for tests):
+ *   what 0: intermediate products, int64 [total rows]
+ *   what 1: symbolic row map, int64 [total rows], entries (product << 32) | row,
+ *           listed group by group, ascending row order inside a group
+ *   what 2: numeric row map, same layout (after spgemm_symbolic)
+ * group_start (host, SPGEMM_NGROUPS + 1 entries) receives the group offsets
+ * into the map (what 1 / 2) and may be NULL.  Enqueued on the plan's stream. */
+spgemm_status spgemm_export(const spgemm_plan *p, int32_t what, void *dst,
+                            int64_t *group_start);
+
+/* With options.profile = 1: number of timed launch groups recorded so far,
+ * and the name and duration (milliseconds, from HIP events on the plan's
+ * stream) of entry idx.  spgemm_timing synchronises the stream.  Names are
+ * static strings ("plan.ipcount", "sym.g5", "num.g7", ...). */
+int32_t spgemm_timing_count(const spgemm_plan *p);
+spgemm_status spgemm_timing(spgemm_plan *p, int32_t idx, const char **name, float *ms);
+
+/* Releases a plan and its workspace.  NULL-safe.  Waits for the stream. */
+void spgemm_free(spgemm_plan *p);
+
+/* Static description of a status code. */
+const char *spgemm_status_string(spgemm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_H */

@@ -1,0 +1,709 @@
+// Host side of the C ABI declared in include/spgemm.h: plan state, workspace
+// management and the launch sequence of the three phases of paper Section III
+// (row grouping, allocation, accumulation).  All kernels are enqueued on the
+// plan's stream; the only host synchronisations are the two documented ones
+// (group sizes after planning, nnz(C) after the symbolic phase).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "spgemm.h"
+
+using namespace spg;
+
+namespace {
+
+constexpr int kDescSlots = 4;  // pinned descriptor staging buffers (ring)
+
+struct HostStats {
+    int64_t ip_sum = 0, ip_max = 0, nnz_sum = 0, nnz_max = 0;
+};
+
+}  // namespace
+
+struct spgemm_plan {
+    hipStream_t stream = nullptr;
+    spgemm_alloc_fn afn = nullptr;
+    spgemm_free_fn ffn = nullptr;
+    void *actx = nullptr;
+    spgemm_options opt{};
+    bool batch = false;
+    int nprod = 0;
+    std::vector<spgemm_csr> A, B;
+    std::vector<ProdDev> hprods;
+    ProdDev *dprods = nullptr;
+    ProdDev *pinned = nullptr;  // kDescSlots * nprod descriptors
+    hipEvent_t desc_ev[kDescSlots] = {};
+    bool desc_ev_used[kDescSlots] = {};
+    int desc_next = 0;
+    std::vector<RowBlk> hblks;
+    RowBlk *dblks = nullptr;
+    int nblk = 0;
+    int64_t Mtot = 0;
+
+    int64_t *ip = nullptr, *row_nnz = nullptr, *rptv = nullptr;
+    uint64_t *map_sym = nullptr, *map_num = nullptr;
+    int32_t *hslot = nullptr;
+    int64_t *blkcnt = nullptr, *blkoff = nullptr, *starts = nullptr;
+    ProdStats *stats = nullptr;
+    int *flags = nullptr;  // [0] kernel error bits, [1..2] validation, [3..] unsorted per product
+    void *scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
+
+    // chunk group (symbolic group 7)
+    int64_t nh = 0, h_alen = 0, h_split = 0, h_items = 0;
+    int64_t *alen = nullptr, *aoff = nullptr, *splitlen = nullptr, *soff = nullptr;
+    int64_t *nchv = nullptr, *ibase = nullptr, *chunk_cnt = nullptr, *chunk_pos = nullptr;
+    int32_t *split = nullptr;
+    // numeric group 7
+    int64_t nd = 0, d_items = 0;
+    int64_t *dnchv = nullptr, *dbase = nullptr;
+
+    // pinned host readback
+    int64_t *hread = nullptr;
+    size_t hread_bytes = 0;
+
+    int64_t sym_start[kGroups + 1] = {};
+    int64_t num_start[kGroups + 1] = {};
+    std::vector<HostStats> hstats;
+    int64_t ip_total = 0, ip_max = 0, nnz_total = -1;
+    std::vector<int64_t> nnz_c;
+
+    struct Timed { const char *name; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+
+    int state = 0;  // 1 planned, 2 symbolic done
+    std::vector<void *> allocs;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                     \
+    do {                                                  \
+        hipError_t e__ = (expr);                          \
+        if (e__ != hipSuccess) return SPGEMM_EHIP;        \
+    } while (0)
+
+#define ST_TRY(expr)                                      \
+    do {                                                  \
+        spgemm_status s__ = (expr);                       \
+        if (s__ != SPGEMM_OK) return s__;                 \
+    } while (0)
+
+spgemm_status launch_check() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPGEMM_OK : SPGEMM_EHIP;
+}
+
+// Event pair around a launch group when profiling is on.
+struct TimeScope {
+    spgemm_plan *p;
+    size_t idx = SIZE_MAX;
+    TimeScope(spgemm_plan *plan, const char *name) : p(plan) {
+        if (!p->opt.profile) return;
+        spgemm_plan::Timed t{name, nullptr, nullptr};
+        if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return;
+        (void)hipEventRecord(t.a, p->stream);
+        idx = p->timed.size();
+        p->timed.push_back(t);
+    }
+    ~TimeScope() {
+        if (idx != SIZE_MAX) (void)hipEventRecord(p->timed[idx].b, p->stream);
+    }
+};
+
+template <typename T>
+spgemm_status dalloc(spgemm_plan *p, T **out, size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    bytes = (bytes + 255) & ~size_t(255);
+    void *ptr = nullptr;
+    if (p->afn) {
+        ptr = p->afn(p->actx, bytes, (void *)p->stream);
+        if (!ptr) return SPGEMM_ENOMEM;
+    } else {
+        if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return SPGEMM_ENOMEM;
+        }
+    }
+    p->allocs.push_back(ptr);
+    p->ws_bytes += bytes;
+    *out = (T *)ptr;
+    return SPGEMM_OK;
+}
+
+spgemm_status ensure_scan_tmp(spgemm_plan *p, int64_t n) {
+    size_t need = scan_temp_bytes(n);
+    if (need <= p->scan_tmp_bytes) return SPGEMM_OK;
+    char *t = nullptr;
+    ST_TRY(dalloc(p, &t, need));
+    p->scan_tmp = t;
+    p->scan_tmp_bytes = need;
+    return SPGEMM_OK;
+}
+
+spgemm_status scan(spgemm_plan *p, const int64_t *in, int64_t *out, int64_t n) {
+    ST_TRY(ensure_scan_tmp(p, n));
+    launch_scan_i64(in, out, n, p->scan_tmp, p->stream);
+    return launch_check();
+}
+
+spgemm_status ensure_hread(spgemm_plan *p, size_t bytes) {
+    if (bytes <= p->hread_bytes) return SPGEMM_OK;
+    if (p->hread) (void)hipHostFree(p->hread);
+    p->hread = nullptr;
+    p->hread_bytes = 0;
+    void *h = nullptr;
+    HIP_TRY(hipHostMalloc(&h, bytes, hipHostMallocDefault));
+    p->hread = (int64_t *)h;
+    p->hread_bytes = bytes;
+    return SPGEMM_OK;
+}
+
+// Copies the host descriptors to the device through a pinned ring slot.
+spgemm_status upload_descriptors(spgemm_plan *p) {
+    const int slot = p->desc_next;
+    p->desc_next = (p->desc_next + 1) % kDescSlots;
+    if (p->desc_ev_used[slot]) HIP_TRY(hipEventSynchronize(p->desc_ev[slot]));
+    ProdDev *src = p->pinned + (size_t)slot * p->nprod;
+    std::memcpy(src, p->hprods.data(), sizeof(ProdDev) * p->nprod);
+    HIP_TRY(hipMemcpyAsync(p->dprods, src, sizeof(ProdDev) * p->nprod, hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipEventRecord(p->desc_ev[slot], p->stream));
+    p->desc_ev_used[slot] = true;
+    return SPGEMM_OK;
+}
+
+spgemm_status check_options(const spgemm_options &o) {
+    if (o.sym_upper[0] != 0 || o.num_upper[0] != 0) return SPGEMM_EINVAL;
+    for (int g = 1; g < kGroups - 1; ++g) {
+        if (o.sym_upper[g] < o.sym_upper[g - 1] || o.num_upper[g] < o.num_upper[g - 1])
+            return SPGEMM_EINVAL;
+        if (o.sym_upper[g] > kSymCap[g] || o.num_upper[g] > kNumCap[g]) return SPGEMM_EINVAL;
+    }
+    if (o.sym_upper[kGroups - 2] > o.num_upper[kGroups - 2]) return SPGEMM_EINVAL;
+    if (o.chunk_cols < 64 || o.chunk_cols > kMaxChunkCols || (o.chunk_cols % 64) != 0)
+        return SPGEMM_EINVAL;
+    if (o.validate < 0 || o.validate > 1) return SPGEMM_EINVAL;
+    if (o.profile < 0 || o.profile > 1) return SPGEMM_EINVAL;
+    return SPGEMM_OK;
+}
+
+spgemm_status check_csr(const spgemm_csr &m, bool need_values) {
+    if (m.nrows < 0 || m.ncols < 0 || m.nnz < 0) return SPGEMM_EINVAL;
+    if (m.nrows >= (int64_t(1) << 31) || m.ncols >= (int64_t(1) << 31)) return SPGEMM_EDIM;
+    if (!m.row_ptr) return SPGEMM_EINVAL;
+    if (m.nnz > 0 && !m.col_idx) return SPGEMM_EINVAL;
+    if (need_values && m.nnz > 0 && !m.values) return SPGEMM_EINVAL;
+    return SPGEMM_OK;
+}
+
+GroupBounds bounds_of(const int64_t *up) {
+    GroupBounds gb{};
+    for (int g = 0; g < kGroups - 1; ++g) gb.up[g] = up[g];
+    gb.up[kGroups - 1] = INT64_MAX;
+    return gb;
+}
+
+spgemm_status read_flags(spgemm_plan *p, int *out, int n) {
+    ST_TRY(ensure_hread(p, sizeof(int) * n + 64));
+    HIP_TRY(hipMemcpyAsync(p->hread, p->flags, sizeof(int) * n, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    std::memcpy(out, p->hread, sizeof(int) * n);
+    return SPGEMM_OK;
+}
+
+spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
+                               const spgemm_csr *B) {
+    p->nprod = nprod;
+    p->A.assign(A, A + nprod);
+    p->B.assign(B, B + nprod);
+    p->hprods.resize(nprod);
+    p->hstats.resize(nprod);
+    p->nnz_c.assign(nprod, -1);
+    int64_t row_base = 0;
+    for (int q = 0; q < nprod; ++q) {
+        const spgemm_csr &a = A[q], &b = B[q];
+        ST_TRY(check_csr(a, false));
+        ST_TRY(check_csr(b, false));
+        if (a.ncols != b.nrows) return SPGEMM_EDIM;
+        ProdDev &P = p->hprods[q];
+        std::memset(&P, 0, sizeof(P));
+        P.rptA = a.row_ptr;
+        P.colA = a.col_idx;
+        P.valA = a.values;
+        P.rptB = b.row_ptr;
+        P.colB = b.col_idx;
+        P.valB = b.values;
+        P.m = a.nrows;
+        P.k = a.ncols;
+        P.n = b.ncols;
+        P.row_base = row_base;
+        const int64_t wmax = p->opt.chunk_cols;
+        int64_t qn = (P.n + 8 * wmax - 1) / (8 * wmax);
+        if (qn < 1) qn = 1;
+        P.nch = (int32_t)(8 * qn);
+        int64_t w = (P.n + P.nch - 1) / P.nch;
+        w = (w + 63) / 64 * 64;
+        if (w < 64) w = 64;
+        P.W = (int32_t)w;
+        P.b_sorted = (b.flags & SPGEMM_ROWS_SORTED) ? 1 : 2;
+        for (int64_t i0 = 0; i0 < a.nrows; i0 += kRowBlock) {
+            RowBlk rb;
+            rb.p = q;
+            rb.nrows = (int32_t)std::min<int64_t>(kRowBlock, a.nrows - i0);
+            rb.i0 = i0;
+            p->hblks.push_back(rb);
+        }
+        row_base += a.nrows;
+    }
+    p->Mtot = row_base;
+    p->nblk = (int)p->hblks.size();
+    if ((int64_t)p->hblks.size() >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
+
+    const int64_t M = p->Mtot;
+    ST_TRY(dalloc(p, &p->dprods, nprod));
+    ST_TRY(dalloc(p, &p->dblks, p->hblks.size()));
+    ST_TRY(dalloc(p, &p->ip, M));
+    ST_TRY(dalloc(p, &p->row_nnz, M));
+    ST_TRY(dalloc(p, &p->rptv, M + 1));
+    ST_TRY(dalloc(p, &p->map_sym, M));
+    ST_TRY(dalloc(p, &p->map_num, M));
+    ST_TRY(dalloc(p, &p->hslot, M));
+    ST_TRY(dalloc(p, &p->blkcnt, (size_t)kGroups * p->nblk));
+    ST_TRY(dalloc(p, &p->blkoff, (size_t)kGroups * p->nblk + 1));
+    ST_TRY(dalloc(p, &p->starts, 2 * (kGroups + 1)));
+    ST_TRY(dalloc(p, &p->stats, nprod));
+    ST_TRY(dalloc(p, &p->flags, 3 + nprod));
+    ST_TRY(ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk)));
+    {
+        void *h = nullptr;
+        HIP_TRY(hipHostMalloc(&h, sizeof(ProdDev) * nprod * kDescSlots, hipHostMallocDefault));
+        p->pinned = (ProdDev *)h;
+        for (int s = 0; s < kDescSlots; ++s)
+            HIP_TRY(hipEventCreateWithFlags(&p->desc_ev[s], hipEventDisableTiming));
+    }
+    HIP_TRY(hipMemsetAsync(p->stats, 0, sizeof(ProdStats) * nprod, p->stream));
+    HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int) * (3 + nprod), p->stream));
+    ST_TRY(upload_descriptors(p));
+    if (!p->hblks.empty())
+        HIP_TRY(hipMemcpyAsync(p->dblks, p->hblks.data(), sizeof(RowBlk) * p->hblks.size(),
+                               hipMemcpyHostToDevice, p->stream));
+
+    if (p->opt.validate) {
+        int f[3];
+        for (int q = 0; q < nprod; ++q) {
+            CsrCheck ca{A[q].row_ptr, A[q].col_idx, A[q].nrows, A[q].nnz, A[q].ncols};
+            CsrCheck cb{B[q].row_ptr, B[q].col_idx, B[q].nrows, B[q].nnz, B[q].ncols};
+            launch_validate_rows(ca, p->flags + 1, p->stream);
+            launch_validate_rows(cb, p->flags + 2, p->stream);
+        }
+        ST_TRY(launch_check());
+        ST_TRY(read_flags(p, f, 3));
+        if (f[1] || f[2]) return SPGEMM_EINDEX;
+        for (int q = 0; q < nprod; ++q) {
+            CsrCheck ca{A[q].row_ptr, A[q].col_idx, A[q].nrows, A[q].nnz, A[q].ncols};
+            CsrCheck cb{B[q].row_ptr, B[q].col_idx, B[q].nrows, B[q].nnz, B[q].ncols};
+            launch_validate_cols(ca, p->flags + 1, p->stream);
+            launch_validate_cols(cb, p->flags + 2, p->stream);
+        }
+        ST_TRY(launch_check());
+        ST_TRY(read_flags(p, f, 3));
+        if (f[1] || f[2]) return SPGEMM_EINDEX;
+    }
+
+    launch_detect_sorted(p->dprods, nprod, p->hprods.data(), p->flags + 3, p->stream);
+    const GroupBounds gb = bounds_of(p->opt.sym_upper);
+    {
+        TimeScope ts(p, "plan.ipcount");
+        launch_ipcount(p->dprods, p->dblks, p->nblk, gb, p->ip, p->blkcnt, p->stats, p->stream);
+    }
+    ST_TRY(launch_check());
+    {
+        TimeScope ts(p, "plan.group");
+        ST_TRY(scan(p, p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk));
+        launch_scatter(p->dprods, p->dblks, p->nblk, gb, p->ip, p->blkoff, p->map_sym, p->hslot,
+                       p->stream);
+        launch_group_starts(p->blkoff, p->nblk, p->starts, p->stream);
+    }
+    ST_TRY(launch_check());
+
+    // one synchronisation: group sizes and per-product figures
+    const size_t sbytes = sizeof(int64_t) * (kGroups + 1);
+    const size_t pbytes = sizeof(ProdStats) * nprod;
+    ST_TRY(ensure_hread(p, sbytes + pbytes + sizeof(int) * (3 + nprod)));
+    char *hb = (char *)p->hread;
+    HIP_TRY(hipMemcpyAsync(hb, p->starts, sbytes, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(hb + sbytes, p->stats, pbytes, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(hb + sbytes + pbytes, p->flags + 3, sizeof(int) * nprod,
+                           hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    std::memcpy(p->sym_start, hb, sbytes);
+    const ProdStats *ps = (const ProdStats *)(hb + sbytes);
+    const int *unsorted = (const int *)(hb + sbytes + pbytes);
+    p->ip_total = 0;
+    p->ip_max = 0;
+    for (int q = 0; q < nprod; ++q) {
+        p->hstats[q].ip_sum = (int64_t)ps[q].ip_sum;
+        p->hstats[q].ip_max = (int64_t)ps[q].ip_max;
+        p->ip_total += (int64_t)ps[q].ip_sum;
+        p->ip_max = std::max<int64_t>(p->ip_max, (int64_t)ps[q].ip_max);
+        p->nh += (int64_t)ps[q].h_rows;
+        p->h_alen += (int64_t)ps[q].h_alen;
+        p->h_split += (int64_t)ps[q].h_split;
+        p->h_items += (int64_t)ps[q].h_items;
+        if (p->hprods[q].b_sorted == 2) p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
+    }
+    if (p->nh != p->sym_start[kGroups] - p->sym_start[kGroups - 1]) return SPGEMM_EINTERNAL;
+    if (p->h_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
+
+    // chunk-group preparation: per-row A lengths, split tables, chunk bases
+    if (p->nh > 0) {
+        const int64_t nh = p->nh;
+        const uint64_t *hitems = p->map_sym + p->sym_start[kGroups - 1];
+        ST_TRY(dalloc(p, &p->alen, nh));
+        ST_TRY(dalloc(p, &p->splitlen, nh));
+        ST_TRY(dalloc(p, &p->nchv, nh));
+        ST_TRY(dalloc(p, &p->aoff, nh + 1));
+        ST_TRY(dalloc(p, &p->soff, nh + 1));
+        ST_TRY(dalloc(p, &p->ibase, nh + 1));
+        ST_TRY(dalloc(p, &p->split, p->h_split));
+        ST_TRY(dalloc(p, &p->chunk_cnt, p->h_items));
+        ST_TRY(dalloc(p, &p->chunk_pos, p->h_items + 1));
+        TimeScope ts(p, "plan.split");
+        launch_heavy_prep(p->dprods, hitems, nh, p->alen, p->splitlen, p->nchv, p->stream);
+        ST_TRY(launch_check());
+        ST_TRY(scan(p, p->alen, p->aoff, nh));
+        ST_TRY(scan(p, p->splitlen, p->soff, nh));
+        ST_TRY(scan(p, p->nchv, p->ibase, nh));
+        launch_split(p->dprods, hitems, nh, p->aoff, p->soff, p->h_alen, p->split, p->stream);
+        ST_TRY(launch_check());
+    }
+    p->state = 1;
+    return SPGEMM_OK;
+}
+
+spgemm_status create_common(spgemm_plan **out, int32_t nprod, const spgemm_csr *A,
+                            const spgemm_csr *B, const spgemm_options *opt, void *stream,
+                            spgemm_alloc_fn afn, spgemm_free_fn ffn, void *actx, bool batch) {
+    if (!out) return SPGEMM_EINVAL;
+    *out = nullptr;
+    if (nprod <= 0 || !A || !B) return SPGEMM_EINVAL;
+    if ((afn == nullptr) != (ffn == nullptr)) return SPGEMM_EINVAL;
+    spgemm_options o;
+    if (opt) o = *opt; else spgemm_default_options(&o);
+    ST_TRY(check_options(o));
+    spgemm_plan *p = new (std::nothrow) spgemm_plan();
+    if (!p) return SPGEMM_ENOMEM;
+    p->stream = (hipStream_t)stream;
+    p->afn = afn;
+    p->ffn = ffn;
+    p->actx = actx;
+    p->opt = o;
+    p->batch = batch;
+    spgemm_status s;
+    try {
+        s = plan_create_impl(p, nprod, A, B);
+    } catch (...) {
+        s = SPGEMM_ENOMEM;
+    }
+    if (s != SPGEMM_OK) {
+        spgemm_free(p);
+        return s;
+    }
+    *out = p;
+    return SPGEMM_OK;
+}
+
+spgemm_status symbolic_impl(spgemm_plan *p) {
+    if (p->state != 1) return SPGEMM_ESTATE;
+    const int64_t M = p->Mtot;
+    hipStream_t st = p->stream;
+    static const char *const sym_names[kGroups] = {"sym.g0", "sym.g1", "sym.g2", "sym.g3",
+                                                   "sym.g4", "sym.g5", "sym.g6", "sym.g7"};
+    launch_fill_i64(p->row_nnz, M, 0, st);
+    for (int g = 1; g <= 4; ++g) {
+        if (p->sym_start[g + 1] == p->sym_start[g]) continue;
+        TimeScope ts(p, sym_names[g]);
+        launch_sym_group(g, p->dprods, p->map_sym + p->sym_start[g],
+                         p->sym_start[g + 1] - p->sym_start[g], p->row_nnz, p->flags, st);
+    }
+    for (int g = 5; g <= 6; ++g) {
+        if (p->sym_start[g + 1] == p->sym_start[g]) continue;
+        TimeScope ts(p, sym_names[g]);
+        launch_sym_block(g, p->dprods, p->map_sym + p->sym_start[g], p->ip,
+                         p->sym_start[g + 1] - p->sym_start[g], p->row_nnz, p->flags, st);
+    }
+    if (p->nh > 0) {
+        TimeScope ts(p, sym_names[7]);
+        launch_sym_chunk(p->dprods, p->map_sym + p->sym_start[kGroups - 1], p->nh, p->ibase,
+                         p->h_items, p->aoff, p->soff, p->split, p->chunk_cnt, p->row_nnz,
+                         p->flags, st);
+    }
+    ST_TRY(launch_check());
+    {
+        TimeScope ts(p, "sym.scan");
+        ST_TRY(scan(p, p->row_nnz, p->rptv, M));
+        if (p->nh > 0) ST_TRY(scan(p, p->chunk_cnt, p->chunk_pos, p->h_items));
+    }
+
+    // numeric grouping by output length (paper Section III-C)
+    const GroupBounds gb = bounds_of(p->opt.num_upper);
+    {
+        TimeScope ts(p, "sym.regroup");
+        launch_count_groups(p->dprods, p->dblks, p->nblk, gb, p->row_nnz, p->blkcnt, p->stats,
+                            st);
+        ST_TRY(launch_check());
+        ST_TRY(scan(p, p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk));
+        launch_scatter(p->dprods, p->dblks, p->nblk, gb, p->row_nnz, p->blkoff, p->map_num,
+                       nullptr, st);
+        launch_group_starts(p->blkoff, p->nblk, p->starts + (kGroups + 1), st);
+    }
+    ST_TRY(launch_check());
+
+    const size_t sbytes = sizeof(int64_t) * (kGroups + 1);
+    const size_t pbytes = sizeof(ProdStats) * p->nprod;
+    ST_TRY(ensure_hread(p, sbytes + pbytes + 64));
+    char *hb = (char *)p->hread;
+    HIP_TRY(hipMemcpyAsync(hb, p->starts + (kGroups + 1), sbytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hb + sbytes, p->stats, pbytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hb + sbytes + pbytes, p->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(p->num_start, hb, sbytes);
+    const ProdStats *ps = (const ProdStats *)(hb + sbytes);
+    const int err = *(const int *)(hb + sbytes + pbytes);
+    if (err) return SPGEMM_EINTERNAL;
+    p->nnz_total = 0;
+    p->nd = 0;
+    p->d_items = 0;
+    for (int q = 0; q < p->nprod; ++q) {
+        p->hstats[q].nnz_sum = (int64_t)ps[q].nnz_sum;
+        p->hstats[q].nnz_max = (int64_t)ps[q].nnz_max;
+        p->nnz_c[q] = (int64_t)ps[q].nnz_sum;
+        p->nnz_total += (int64_t)ps[q].nnz_sum;
+        p->nd += (int64_t)ps[q].d_rows;
+        p->d_items += (int64_t)ps[q].d_items;
+    }
+    if (p->nd != p->num_start[kGroups] - p->num_start[kGroups - 1]) return SPGEMM_EINTERNAL;
+    if (p->d_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
+    if (p->nd > 0) {
+        ST_TRY(dalloc(p, &p->dnchv, p->nd));
+        ST_TRY(dalloc(p, &p->dbase, p->nd + 1));
+        launch_dense_prep(p->dprods, p->map_num + p->num_start[kGroups - 1], p->nd, p->dnchv, st);
+        ST_TRY(launch_check());
+        ST_TRY(scan(p, p->dnchv, p->dbase, p->nd));
+    }
+    p->state = 2;
+    return SPGEMM_OK;
+}
+
+spgemm_status numeric_impl(spgemm_plan *p) {
+    if (p->state != 2) return SPGEMM_ESTATE;
+    ST_TRY(upload_descriptors(p));
+    hipStream_t st = p->stream;
+    static const char *const num_names[kGroups] = {"num.g0", "num.g1", "num.g2", "num.g3",
+                                                   "num.g4", "num.g5", "num.g6", "num.g7"};
+    for (int g = 1; g <= 4; ++g) {
+        if (p->num_start[g + 1] == p->num_start[g]) continue;
+        TimeScope ts(p, num_names[g]);
+        launch_num_group(g, p->dprods, p->map_num + p->num_start[g],
+                         p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st);
+    }
+    for (int g = 5; g <= 6; ++g) {
+        if (p->num_start[g + 1] == p->num_start[g]) continue;
+        TimeScope ts(p, num_names[g]);
+        launch_num_block(g, p->dprods, p->map_num + p->num_start[g],
+                         p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st);
+    }
+    if (p->nd > 0) {
+        TimeScope ts(p, num_names[7]);
+        launch_num_chunk(p->dprods, p->map_num + p->num_start[kGroups - 1], p->nd, p->dbase,
+                         p->d_items, p->hslot, p->ibase, p->aoff, p->soff, p->split,
+                         p->chunk_cnt, p->chunk_pos, p->rptv, p->flags, st);
+    }
+    return launch_check();
+}
+
+}  // namespace
+
+extern "C" {
+
+void spgemm_default_options(spgemm_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 4096, 8192};
+    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 8192};
+    for (int g = 0; g < kGroups - 1; ++g) {
+        opt->sym_upper[g] = sym[g];
+        opt->num_upper[g] = num[g];
+    }
+    opt->chunk_cols = kMaxChunkCols;
+    opt->validate = 0;
+}
+
+spgemm_status spgemm_plan_create(spgemm_plan **out, const spgemm_csr *A, const spgemm_csr *B,
+                                 const spgemm_options *opt, void *stream,
+                                 spgemm_alloc_fn alloc_fn, spgemm_free_fn free_fn,
+                                 void *alloc_ctx) {
+    return create_common(out, 1, A, B, opt, stream, alloc_fn, free_fn, alloc_ctx, false);
+}
+
+spgemm_status spgemm_plan_create_batch(spgemm_plan **out, int32_t nprod, const spgemm_csr *A,
+                                       const spgemm_csr *B, const spgemm_options *opt,
+                                       void *stream, spgemm_alloc_fn alloc_fn,
+                                       spgemm_free_fn free_fn, void *alloc_ctx) {
+    return create_common(out, nprod, A, B, opt, stream, alloc_fn, free_fn, alloc_ctx, true);
+}
+
+spgemm_status spgemm_symbolic(spgemm_plan *p, int64_t *c_row_ptr, int64_t *nnz_c,
+                              int64_t *flops) {
+    if (!p || !c_row_ptr || !nnz_c) return SPGEMM_EINVAL;
+    if (p->batch) return SPGEMM_ESTATE;
+    spgemm_status s;
+    try { s = symbolic_impl(p); } catch (...) { s = SPGEMM_ENOMEM; }
+    if (s != SPGEMM_OK) return s;
+    HIP_TRY(hipMemcpyAsync(c_row_ptr, p->rptv, sizeof(int64_t) * (p->Mtot + 1),
+                           hipMemcpyDeviceToDevice, p->stream));
+    *nnz_c = p->nnz_total;
+    if (flops) *flops = 2 * p->ip_total;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_symbolic_batch(spgemm_plan *p, int64_t *const *c_row_ptr, int64_t *nnz_c) {
+    if (!p || !c_row_ptr || !nnz_c) return SPGEMM_EINVAL;
+    for (int q = 0; q < p->nprod; ++q)
+        if (!c_row_ptr[q]) return SPGEMM_EINVAL;
+    spgemm_status s;
+    try { s = symbolic_impl(p); } catch (...) { s = SPGEMM_ENOMEM; }
+    if (s != SPGEMM_OK) return s;
+    for (int q = 0; q < p->nprod; ++q) {
+        launch_rows_local(p->rptv, p->hprods[q].row_base, p->hprods[q].m, c_row_ptr[q], p->stream);
+        nnz_c[q] = p->nnz_c[q];
+    }
+    return launch_check();
+}
+
+spgemm_status spgemm_numeric(spgemm_plan *p, const float *a_values, const float *b_values,
+                             int32_t *c_col_idx, float *c_values) {
+    if (!p) return SPGEMM_EINVAL;
+    if (p->batch) return SPGEMM_ESTATE;
+    if (p->state != 2) return SPGEMM_ESTATE;
+    if ((p->A[0].nnz > 0 && !a_values) || (p->B[0].nnz > 0 && !b_values)) return SPGEMM_EINVAL;
+    if (p->nnz_total > 0 && (!c_col_idx || !c_values)) return SPGEMM_EINVAL;
+    p->hprods[0].valA = a_values;
+    p->hprods[0].valB = b_values;
+    p->hprods[0].colC = c_col_idx;
+    p->hprods[0].valC = c_values;
+    return numeric_impl(p);
+}
+
+spgemm_status spgemm_numeric_batch(spgemm_plan *p, const float *const *a_values,
+                                   const float *const *b_values, int32_t *const *c_col_idx,
+                                   float *const *c_values) {
+    if (!p || !a_values || !b_values || !c_col_idx || !c_values) return SPGEMM_EINVAL;
+    if (p->state != 2) return SPGEMM_ESTATE;
+    for (int q = 0; q < p->nprod; ++q) {
+        if ((p->A[q].nnz > 0 && !a_values[q]) || (p->B[q].nnz > 0 && !b_values[q]))
+            return SPGEMM_EINVAL;
+        if (p->nnz_c[q] > 0 && (!c_col_idx[q] || !c_values[q])) return SPGEMM_EINVAL;
+        p->hprods[q].valA = a_values[q];
+        p->hprods[q].valB = b_values[q];
+        p->hprods[q].colC = c_col_idx[q];
+        p->hprods[q].valC = c_values[q];
+    }
+    return numeric_impl(p);
+}
+
+spgemm_status spgemm_sync(spgemm_plan *p) {
+    if (!p) return SPGEMM_EINVAL;
+    HIP_TRY(hipGetLastError());
+    int f[1];
+    ST_TRY(read_flags(p, f, 1));
+    return f[0] ? SPGEMM_EINTERNAL : SPGEMM_OK;
+}
+
+spgemm_status spgemm_get_info(const spgemm_plan *p, spgemm_info *info) {
+    if (!p || !info) return SPGEMM_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->flops = 2 * p->ip_total;
+    info->ip_total = p->ip_total;
+    info->ip_max = p->ip_max;
+    info->nnz_c = p->state >= 2 ? p->nnz_total : -1;
+    for (int g = 0; g < kGroups; ++g) {
+        info->sym_group_rows[g] = p->sym_start[g + 1] - p->sym_start[g];
+        info->num_group_rows[g] = p->state >= 2 ? p->num_start[g + 1] - p->num_start[g] : 0;
+    }
+    info->chunk_cols = p->hprods.empty() ? 0 : p->hprods[0].W;
+    info->chunks_per_row = p->hprods.empty() ? 0 : p->hprods[0].nch;
+    info->workspace_bytes = p->ws_bytes;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_export(const spgemm_plan *p, int32_t what, void *dst, int64_t *group_start) {
+    if (!p || !dst) return SPGEMM_EINVAL;
+    const void *src = nullptr;
+    const int64_t *gs = nullptr;
+    if (what == 0) src = p->ip;
+    else if (what == 1) { src = p->map_sym; gs = p->sym_start; }
+    else if (what == 2) {
+        if (p->state < 2) return SPGEMM_ESTATE;
+        src = p->map_num;
+        gs = p->num_start;
+    } else return SPGEMM_EINVAL;
+    if (p->Mtot > 0)
+        HIP_TRY(hipMemcpyAsync(dst, src, sizeof(int64_t) * p->Mtot, hipMemcpyDeviceToDevice,
+                               p->stream));
+    if (group_start && gs) std::memcpy(group_start, gs, sizeof(int64_t) * (kGroups + 1));
+    return SPGEMM_OK;
+}
+
+void spgemm_free(spgemm_plan *p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    for (void *ptr : p->allocs) {
+        if (p->ffn) p->ffn(p->actx, ptr, (void *)p->stream);
+        else (void)hipFree(ptr);
+    }
+    p->allocs.clear();
+    for (auto &t : p->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    if (p->hread) (void)hipHostFree(p->hread);
+    for (int s = 0; s < kDescSlots; ++s)
+        if (p->desc_ev[s]) (void)hipEventDestroy(p->desc_ev[s]);
+    delete p;
+}
+
+int32_t spgemm_timing_count(const spgemm_plan *p) { return p ? (int32_t)p->timed.size() : 0; }
+
+spgemm_status spgemm_timing(spgemm_plan *p, int32_t idx, const char **name, float *ms) {
+    if (!p || !name || !ms || idx < 0 || idx >= (int32_t)p->timed.size()) return SPGEMM_EINVAL;
+    HIP_TRY(hipEventSynchronize(p->timed[idx].b));
+    HIP_TRY(hipEventElapsedTime(ms, p->timed[idx].a, p->timed[idx].b));
+    *name = p->timed[idx].name;
+    return SPGEMM_OK;
+}
+
+const char *spgemm_status_string(spgemm_status s) {
+    switch (s) {
+        case SPGEMM_OK: return "ok";
+        case SPGEMM_EINVAL: return "invalid argument";
+        case SPGEMM_EDIM: return "dimension mismatch or out of range";
+        case SPGEMM_EINDEX: return "malformed CSR input";
+        case SPGEMM_EOVERFLOW: return "count overflow";
+        case SPGEMM_ENOMEM: return "out of device memory";
+        case SPGEMM_EHIP: return "HIP runtime error";
+        case SPGEMM_ESTATE: return "call out of order";
+        case SPGEMM_EINTERNAL: return "kernel error flag raised";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP kernels and the host side of the
+// library.  Wavefronts are 64 lanes wide (CDNA4); every kernel is written for
+// that width.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spg {
+
+constexpr int kGroups = 8;           // row groups, see spgemm.h
+constexpr int kChunkGroup = 7;       // column-chunked group
+constexpr int kMaxChunkCols = 32768; // LDS dense accumulator: 128 KiB FP32
+constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
+// Largest key each group can take (tables at most half full).
+constexpr int64_t kSymCap[kGroups] = {0, 32, 64, 128, 256, 4096, 16384, 0};
+constexpr int64_t kNumCap[kGroups] = {0, 32, 64, 128, 256, 2048, 8192, 0};
+constexpr int kEmptyKey = -1;
+
+// Error bits raised by kernels (OR-ed into the plan's device flag word).
+constexpr int kErrProbe = 1;         // hash probe sequence exceeded the table
+constexpr int kErrCount = 2;         // numeric count != symbolic count
+constexpr int kErrChunk = 4;         // chunk count != symbolic chunk count
+constexpr int kErrRow = 8;           // group-kernel row exceeds group capacity
+
+// One product C = A * B as seen by the kernels.
+struct ProdDev {
+    const int64_t *rptA;
+    const int32_t *colA;
+    const float *valA;
+    const int64_t *rptB;
+    const int32_t *colB;
+    const float *valB;
+    int32_t *colC;
+    float *valC;
+    int64_t m, k, n;
+    int64_t row_base;   // first row of this product in the batch row space
+    int32_t W;          // columns per chunk
+    int32_t nch;        // chunks per row (multiple of 8)
+    int32_t b_sorted;   // rows of B strictly ascending: 1 yes, 0 no, 2 detect
+    int32_t pad;
+};
+
+// A block of up to kRowBlock consecutive rows of one product.
+struct RowBlk {
+    int32_t p;
+    int32_t nrows;
+    int64_t i0;
+};
+
+// Per-product figures accumulated on the device (one atomic per block).
+struct ProdStats {
+    unsigned long long ip_sum;
+    unsigned long long ip_max;
+    unsigned long long nnz_sum;
+    unsigned long long nnz_max;
+    unsigned long long h_rows;    // symbolic group-7 rows
+    unsigned long long h_alen;    // their A nonzeros
+    unsigned long long h_split;   // sum of alen * (nch + 1)
+    unsigned long long h_items;   // sum of nch
+    unsigned long long d_rows;    // numeric group-7 rows
+    unsigned long long d_items;   // sum of nch over them
+    unsigned long long pad[6];
+};
+
+__device__ __forceinline__ uint64_t pack_item(int p, int64_t i) {
+    return ((uint64_t)(uint32_t)p << 32) | (uint64_t)(uint32_t)i;
+}
+__device__ __forceinline__ int item_prod(uint64_t e) { return (int)(e >> 32); }
+__device__ __forceinline__ int64_t item_row(uint64_t e) { return (int64_t)(uint32_t)e; }
+
+// Multiplicative (Fibonacci) hashing: the top log2T bits of c * 2^32/phi.
+__device__ __forceinline__ uint32_t hash_slot(int c, int log2T) {
+    return ((uint32_t)c * 0x9E3779B1u) >> (32 - log2T);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+struct GroupBounds { int64_t up[kGroups]; };  // up[0] = 0, up[7] unused
+
+size_t scan_temp_bytes(int64_t n);
+// out[0..n] = exclusive prefix of in[0..n) (out[n] = total).  out != in.
+void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, void *temp,
+                     hipStream_t s);
+
+struct CsrCheck {
+    const int64_t *rpt;
+    const int32_t *col;
+    int64_t m, nnz, ncols;
+};
+void launch_detect_sorted(ProdDev *prods, int nprod, const ProdDev *host_prods,
+                          int *flags_out, hipStream_t s);
+void launch_validate_rows(const CsrCheck &c, int *bad, hipStream_t s);
+void launch_validate_cols(const CsrCheck &c, int *bad, hipStream_t s);
+
+void launch_ipcount(const ProdDev *prods, const RowBlk *blks, int nblk,
+                    GroupBounds gb, int64_t *ip, int64_t *blkcnt, ProdStats *stats,
+                    hipStream_t s);
+void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk,
+                         GroupBounds gb, const int64_t *key, int64_t *blkcnt,
+                         ProdStats *stats, hipStream_t s);
+void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk,
+                    GroupBounds gb, const int64_t *key, const int64_t *off,
+                    uint64_t *map, int32_t *hslot, hipStream_t s);
+void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStream_t s);
+
+// Chunk preparation: per chunk-group row h (map positions [0, nh)):
+// alen[h], splitlen[h] = alen * (nch + 1), nchv[h] = nch.
+void launch_heavy_prep(const ProdDev *prods, const uint64_t *items, int64_t nh,
+                       int64_t *alen, int64_t *splitlen, int64_t *nchv, hipStream_t s);
+void launch_dense_prep(const ProdDev *prods, const uint64_t *items, int64_t nd,
+                       int64_t *nchv, hipStream_t s);
+void launch_split(const ProdDev *prods, const uint64_t *items, int64_t nh,
+                  const int64_t *aoff, const int64_t *soff, int64_t total_alen,
+                  int32_t *split, hipStream_t s);
+
+void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items,
+                      int64_t count, int64_t *row_nnz, int *err, hipStream_t s);
+void launch_sym_block(int g, const ProdDev *prods, const uint64_t *items,
+                      const int64_t *ipv, int64_t count, int64_t *row_nnz, int *err,
+                      hipStream_t s);
+void launch_sym_chunk(const ProdDev *prods, const uint64_t *items, int64_t nh,
+                      const int64_t *ibase, int64_t nitems, const int64_t *aoff,
+                      const int64_t *soff, const int32_t *split, int64_t *chunk_cnt,
+                      int64_t *row_nnz, int *err, hipStream_t s);
+
+void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
+                      int64_t count, const int64_t *rptv, int *err, hipStream_t s);
+void launch_num_block(int g, const ProdDev *prods, const uint64_t *items,
+                      int64_t count, const int64_t *rptv, int *err, hipStream_t s);
+void launch_num_chunk(const ProdDev *prods, const uint64_t *ditems, int64_t nd,
+                      const int64_t *dbase, int64_t nitems, const int32_t *hslot,
+                      const int64_t *ibase, const int64_t *aoff, const int64_t *soff,
+                      const int32_t *split, const int64_t *chunk_cnt,
+                      const int64_t *chunk_pos, const int64_t *rptv, int *err,
+                      hipStream_t s);
+
+void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
+void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,
+                       int64_t *dst, hipStream_t s);
+
+}  // namespace spg

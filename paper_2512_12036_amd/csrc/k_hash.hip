@@ -1,0 +1,486 @@
+// Hash-table kernels of the allocation (symbolic) and accumulation (numeric)
+// phases, paper Sections III-C / III-D, Algorithms 2-5.
+//
+// Open addressing with linear probing in LDS (paper Algorithm 4): a slot holds
+// -1 when empty, a key is claimed with a compare-and-swap, the claiming lane
+// counts one distinct column, and the numeric variant adds the FP32 product
+// into the value slot with an LDS float atomic.  Tables are sized so that
+// they are never more than half full; a probe-count guard turns an
+// impossible overflow into an error flag instead of a hang.
+//
+// Work mapping for 64-lane wavefronts (the paper's mappings, Algorithms 2-3,
+// are written for 32-lane warps and are not kept):
+//  * group kernels: G = 8/16/32/64 lanes per row, 256/G rows per workgroup,
+//    a table of 8G slots per row.  The G lanes load G nonzeros of the A row,
+//    scan their B-row lengths with lane shuffles and then walk the
+//    concatenated products G at a time, each lane finding its product's
+//    owner by a binary search over the shuffled prefix.  All lanes stay busy
+//    whatever the B-row lengths are.
+//  * block kernels: one row per 256- or 512-thread workgroup, tables up to
+//    32 K keys (symbolic) or 16 K key/value pairs (numeric).  Batches of A
+//    nonzeros are staged in LDS with the start of their B row and a block
+//    prefix of the lengths; the products are then enumerated flat, so the
+//    whole workgroup is busy even for rows of few, long B rows.
+//  * numeric epilogue (paper Section III-D): occupied slots are gathered,
+//    sorted by column (rank sort in the group kernels, as the paper's
+//    comparison-based ranking; bitonic sort in LDS in the block kernels, as
+//    paper Algorithm 5) and written to the row's segment of C.
+#include "common.hpp"
+
+namespace spg {
+
+__device__ __forceinline__ int lds_insert(int *tab, uint32_t mask, int log2T, int c, int *err) {
+    uint32_t h = hash_slot(c, log2T);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        int cur = tab[h];
+        if (cur == c) return 0;
+        if (cur == kEmptyKey) {
+            int old = atomicCAS(&tab[h], kEmptyKey, c);
+            if (old == kEmptyKey) return 1;
+            if (old == c) return 0;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicOr(err, kErrProbe);
+    return 0;
+}
+
+__device__ __forceinline__ void lds_add(int *tab, float *vals, uint32_t mask, int log2T, int c,
+                                        float v, int *err) {
+    uint32_t h = hash_slot(c, log2T);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        int cur = tab[h];
+        if (cur == c) { atomicAdd(&vals[h], v); return; }
+        if (cur == kEmptyKey) {
+            int old = atomicCAS(&tab[h], kEmptyKey, c);
+            if (old == kEmptyKey || old == c) { atomicAdd(&vals[h], v); return; }
+        }
+        h = (h + 1) & mask;
+    }
+    atomicOr(err, kErrProbe);
+}
+
+template <int N>
+struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <>
+struct Log2<1> { static constexpr int v = 0; };
+
+__device__ __forceinline__ int ceil_log2(int64_t x) {
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+// Largest o in [0, n) with e[o] <= q, e non-decreasing, e[0] = 0 <= q.
+template <typename T>
+__device__ __forceinline__ int lds_owner(const T *e, int n, T q) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (e[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int NT>
+__device__ __forceinline__ int block_excl_scan_i32(int v, int *wsum, int &total) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        int x = wsum[i];
+        if (i < w) before += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return before + incl - v;
+}
+
+template <int NT>
+__device__ __forceinline__ int block_sum_i32(int v, int *wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tot += wsum[i];
+    __syncthreads();
+    return tot;
+}
+
+// ---------------------------------------------------------------------------
+// Group kernels: G lanes per row.
+// ---------------------------------------------------------------------------
+// Walks every intermediate product of row i of P with the G lanes of a group
+// and calls f(col_b, a_value, b_index) for each.  Group-uniform control flow.
+template <int G, bool VALUES, typename F>
+__device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int lane, F &&f) {
+    const int64_t a0 = P.rptA[i], a1 = P.rptA[i + 1];
+    for (int64_t jb = a0; jb < a1; jb += G) {
+        const int64_t j = jb + lane;
+        int64_t s = 0;
+        int len = 0;
+        float a = 0.f;
+        if (j < a1) {
+            const int k = P.colA[j];
+            s = P.rptB[k];
+            len = (int)(P.rptB[k + 1] - s);
+            if (VALUES) a = P.valA[j];
+        }
+        int incl = len;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            int o = __shfl_up(incl, off, G);
+            if (lane >= off) incl += o;
+        }
+        const int total = __shfl(incl, G - 1, G);
+        const int excl = incl - len;
+        for (int qb = 0; qb < total; qb += G) {
+            const int q = qb + lane;
+            int o = 0;
+#pragma unroll
+            for (int step = G / 2; step > 0; step >>= 1) {
+                int v = __shfl(excl, o + step, G);
+                if (v <= q) o += step;
+            }
+            const int64_t so = __shfl(s, o, G);
+            const int eo = __shfl(excl, o, G);
+            float ao = 0.f;
+            if (VALUES) ao = __shfl(a, o, G);
+            if (q < total) f(P.colB[so + (q - eo)], ao, so + (q - eo));
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ prods,
+                                                    const uint64_t *__restrict__ items,
+                                                    int64_t count, int64_t *__restrict__ row_nnz,
+                                                    int *__restrict__ err) {
+    constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v;
+    __shared__ int keys[R * T];
+    for (int s = threadIdx.x; s < R * T; s += 256) keys[s] = kEmptyKey;
+    __syncthreads();
+    const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+    const int64_t it = (int64_t)blockIdx.x * R + gi;
+    if (it >= count) return;  // group-uniform; no block barrier follows
+    const uint64_t e = items[it];
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t i = item_row(e);
+    int *tab = keys + gi * T;
+    int cnt = 0;
+    group_products<G, false>(P, i, lane, [&](int c, float, int64_t) {
+        cnt += lds_insert(tab, T - 1, LOG2T, c, err);
+    });
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, G);
+    if (lane == 0) row_nnz[P.row_base + i] = cnt;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ prods,
+                                                    const uint64_t *__restrict__ items,
+                                                    int64_t count, const int64_t *__restrict__ rptv,
+                                                    int *__restrict__ err) {
+    constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v, PER = T / G;
+    __shared__ int keys[R * T];
+    __shared__ float vals[R * T];
+    for (int s = threadIdx.x; s < R * T; s += 256) { keys[s] = kEmptyKey; vals[s] = 0.f; }
+    __syncthreads();
+    const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+    const int64_t it = (int64_t)blockIdx.x * R + gi;
+    const bool active = it < count;
+    int *tab = keys + gi * T;
+    float *tv = vals + gi * T;
+    uint64_t e = 0;
+    if (active) {
+        e = items[it];
+        const ProdDev &P = prods[item_prod(e)];
+        group_products<G, true>(P, item_row(e), lane, [&](int c, float a, int64_t t) {
+            lds_add(tab, tv, T - 1, LOG2T, c, a * P.valB[t], err);
+        });
+    }
+    __syncthreads();
+    // gather: each lane owns slots lane + G*r
+    int kk[PER];
+    float vv[PER];
+    int mine = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        kk[r] = tab[lane + G * r];
+        vv[r] = tv[lane + G * r];
+        mine += kk[r] != kEmptyKey;
+    }
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        int o = __shfl_up(incl, off, G);
+        if (lane >= off) incl += o;
+    }
+    const int n = __shfl(incl, G - 1, G);
+    int pos = incl - mine;
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r)
+            if (kk[r] != kEmptyKey) { tab[pos] = kk[r]; ++pos; }
+    }
+    __syncthreads();
+    if (!active) return;  // no block barrier follows
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t g = P.row_base + item_row(e);
+    const int64_t expect = rptv[g + 1] - rptv[g];
+    if (lane == 0 && n != expect) atomicOr(err, kErrCount);
+    // rank of each held key among the n gathered keys (keys are distinct)
+    int rank[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) rank[r] = 0;
+    for (int f = 0; f < n; ++f) {
+        const int kf = tab[f];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) rank[r] += kf < kk[r];
+    }
+    const int64_t base = rptv[g] - rptv[P.row_base];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        if (kk[r] != kEmptyKey && rank[r] < expect) {
+            P.colC[base + rank[r]] = kk[r];
+            P.valC[base + rank[r]] = vv[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block kernels: one row per workgroup.
+// ---------------------------------------------------------------------------
+template <int WG, bool VALUES, typename F>
+__device__ __forceinline__ void block_products(const ProdDev &P, int64_t i, int64_t *st_s,
+                                               int *st_e, float *st_a, int *wsum, F &&f) {
+    const int64_t a0 = P.rptA[i], a1 = P.rptA[i + 1];
+    for (int64_t jb = a0; jb < a1; jb += WG) {
+        const int64_t j = jb + threadIdx.x;
+        int64_t s = 0;
+        int len = 0;
+        float a = 0.f;
+        if (j < a1) {
+            const int k = P.colA[j];
+            s = P.rptB[k];
+            len = (int)(P.rptB[k + 1] - s);
+            if (VALUES) a = P.valA[j];
+        }
+        int total;
+        const int excl = block_excl_scan_i32<WG>(len, wsum, total);
+        st_s[threadIdx.x] = s;
+        st_e[threadIdx.x] = excl;
+        if (VALUES) st_a[threadIdx.x] = a;
+        __syncthreads();
+        const int nv = (int)((a1 - jb) < WG ? (a1 - jb) : WG);
+        for (int q = threadIdx.x; q < total; q += WG) {
+            const int o = lds_owner<int>(st_e, nv, q);
+            const int64_t t = st_s[o] + (q - st_e[o]);
+            f(P.colB[t], VALUES ? st_a[o] : 0.f, t);
+        }
+        __syncthreads();
+    }
+}
+
+template <int WG, int TMAX>
+__global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ prods,
+                                                   const uint64_t *__restrict__ items,
+                                                   const int64_t *__restrict__ ipv,
+                                                   int64_t *__restrict__ row_nnz,
+                                                   int *__restrict__ err) {
+    __shared__ int keys[TMAX];
+    __shared__ int64_t st_s[WG];
+    __shared__ int st_e[WG];
+    __shared__ int wsum[WG / 64];
+    const uint64_t e = items[blockIdx.x];
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t i = item_row(e);
+    const int64_t g = P.row_base + i;
+    int64_t bound = ipv[g] < P.n ? ipv[g] : P.n;
+    int log2T = ceil_log2(2 * bound);
+    if (log2T < 8) log2T = 8;
+    if (log2T > Log2<TMAX>::v) log2T = Log2<TMAX>::v;
+    const int T = 1 << log2T;
+    if (bound >= T) {  // cannot happen with validated bounds
+        if (threadIdx.x == 0) atomicOr(err, kErrRow);
+        return;
+    }
+    for (int s = threadIdx.x; s < T; s += WG) keys[s] = kEmptyKey;
+    __syncthreads();
+    int cnt = 0;
+    block_products<WG, false>(P, i, st_s, st_e, (float *)nullptr, wsum,
+                              [&](int c, float, int64_t) {
+                                  cnt += lds_insert(keys, T - 1, log2T, c, err);
+                              });
+    const int tot = block_sum_i32<WG>(cnt, wsum);
+    if (threadIdx.x == 0) row_nnz[g] = tot;
+}
+
+template <int WG, int TMAX>
+__global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ prods,
+                                                   const uint64_t *__restrict__ items,
+                                                   const int64_t *__restrict__ rptv,
+                                                   int *__restrict__ err) {
+    __shared__ int keys[TMAX];
+    __shared__ float vals[TMAX];
+    __shared__ int64_t st_s[WG];
+    __shared__ int st_e[WG];
+    __shared__ float st_a[WG];
+    __shared__ int wsum[WG / 64];
+    __shared__ int fill;
+    const uint64_t e = items[blockIdx.x];
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t i = item_row(e);
+    const int64_t g = P.row_base + i;
+    const int64_t expect = rptv[g + 1] - rptv[g];
+    int log2T = ceil_log2(2 * expect);
+    if (log2T < 8) log2T = 8;
+    if (log2T > Log2<TMAX>::v) log2T = Log2<TMAX>::v;
+    const int T = 1 << log2T;
+    if (expect >= T) {
+        if (threadIdx.x == 0) atomicOr(err, kErrRow);
+        return;
+    }
+    for (int s = threadIdx.x; s < T; s += WG) { keys[s] = kEmptyKey; vals[s] = 0.f; }
+    if (threadIdx.x == 0) fill = 0;
+    __syncthreads();
+    block_products<WG, true>(P, i, st_s, st_e, st_a, wsum, [&](int c, float a, int64_t t) {
+        lds_add(keys, vals, T - 1, log2T, c, a * P.valB[t], err);
+    });
+    // gather occupied slots to the front, in place, one WG-wide round at a time
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int r0 = 0; r0 < T; r0 += WG) {
+        const int q = r0 + threadIdx.x;
+        int kk = kEmptyKey;
+        float vv = 0.f;
+        if (q < T) { kk = keys[q]; vv = vals[q]; }
+        const bool occ = kk != kEmptyKey;
+        __syncthreads();
+        const unsigned long long m = __ballot(occ);
+        int base = 0;
+        if (lane == 0 && m) base = atomicAdd(&fill, __popcll(m));
+        base = __shfl(base, 0, 64);
+        if (occ) {
+            const int pos = base + __popcll(m & lt);
+            keys[pos] = kk;
+            vals[pos] = vv;
+        }
+        __syncthreads();
+    }
+    const int n = fill;
+    if (threadIdx.x == 0 && n != expect) atomicOr(err, kErrCount);
+    int N = 1;
+    while (N < n) N <<= 1;
+    for (int q = n + threadIdx.x; q < N; q += WG) keys[q] = 0x7fffffff;
+    __syncthreads();
+    // bitonic sort of the N (key, value) pairs
+    for (int k = 2; k <= N; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int q = threadIdx.x; q < (N >> 1); q += WG) {
+                const int lo = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                const int hi = lo + j;
+                const bool asc = (lo & k) == 0;
+                const int ka = keys[lo], kb = keys[hi];
+                if ((ka > kb) == asc) {
+                    keys[lo] = kb;
+                    keys[hi] = ka;
+                    const float va = vals[lo];
+                    vals[lo] = vals[hi];
+                    vals[hi] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t base = rptv[g] - rptv[P.row_base];
+    const int nout = (int)(n < expect ? n : expect);
+    for (int q = threadIdx.x; q < nout; q += WG) {
+        P.colC[base + q] = keys[q];
+        P.valC[base + q] = vals[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.  Group g: 1..4 -> G = 8, 16, 32, 64; 5 -> 256-thread block,
+// 6 -> 512-thread block.
+// ---------------------------------------------------------------------------
+template <int G>
+static void sym_group_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
+                             int64_t *row_nnz, int *err, hipStream_t s) {
+    constexpr int R = 256 / G;
+    const int64_t nb = (count + R - 1) / R;
+    hipLaunchKernelGGL(k_sym_group<G>, dim3((unsigned)nb), dim3(256), 0, s, prods, items, count,
+                       row_nnz, err);
+}
+
+void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
+                      int64_t *row_nnz, int *err, hipStream_t s) {
+    if (count <= 0) return;
+    switch (g) {
+        case 1: sym_group_launch<8>(prods, items, count, row_nnz, err, s); break;
+        case 2: sym_group_launch<16>(prods, items, count, row_nnz, err, s); break;
+        case 3: sym_group_launch<32>(prods, items, count, row_nnz, err, s); break;
+        case 4: sym_group_launch<64>(prods, items, count, row_nnz, err, s); break;
+        default: break;
+    }
+}
+
+template <int G>
+static void num_group_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
+                             const int64_t *rptv, int *err, hipStream_t s) {
+    constexpr int R = 256 / G;
+    const int64_t nb = (count + R - 1) / R;
+    hipLaunchKernelGGL(k_num_group<G>, dim3((unsigned)nb), dim3(256), 0, s, prods, items, count,
+                       rptv, err);
+}
+
+void launch_num_group(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
+                      const int64_t *rptv, int *err, hipStream_t s) {
+    if (count <= 0) return;
+    switch (g) {
+        case 1: num_group_launch<8>(prods, items, count, rptv, err, s); break;
+        case 2: num_group_launch<16>(prods, items, count, rptv, err, s); break;
+        case 3: num_group_launch<32>(prods, items, count, rptv, err, s); break;
+        case 4: num_group_launch<64>(prods, items, count, rptv, err, s); break;
+        default: break;
+    }
+}
+
+void launch_sym_block(int g, const ProdDev *prods, const uint64_t *items, const int64_t *ipv,
+                      int64_t count, int64_t *row_nnz, int *err, hipStream_t s) {
+    if (count <= 0) return;
+    if (g == 5)
+        hipLaunchKernelGGL((k_sym_block<256, 8192>), dim3((unsigned)count), dim3(256), 0, s,
+                           prods, items, ipv, row_nnz, err);
+    else
+        hipLaunchKernelGGL((k_sym_block<512, 32768>), dim3((unsigned)count), dim3(512), 0, s,
+                           prods, items, ipv, row_nnz, err);
+}
+
+void launch_num_block(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
+                      const int64_t *rptv, int *err, hipStream_t s) {
+    if (count <= 0) return;
+    if (g == 5)
+        hipLaunchKernelGGL((k_num_block<256, 4096>), dim3((unsigned)count), dim3(256), 0, s,
+                           prods, items, rptv, err);
+    else
+        hipLaunchKernelGGL((k_num_block<512, 16384>), dim3((unsigned)count), dim3(512), 0, s,
+                           prods, items, rptv, err);
+}
+
+}  // namespace spg

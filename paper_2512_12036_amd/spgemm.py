@@ -1,0 +1,365 @@
+"""Thin Python binding of libspgemm.so (include/spgemm.h).
+
+Argument marshalling only: every step of the product runs in the library's
+HIP kernels.  PyTorch provides device memory (its caching allocator backs
+the library's workspace through the allocator callbacks) and the stream
+(``torch.cuda.current_stream()``).  There is no CPU fallback: if the
+library is not built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspgemm.so")
+NGROUPS = 8
+ROWS_SORTED = 1
+
+_I64 = ctypes.c_int64
+_VP = ctypes.c_void_p
+
+
+class CsrDesc(ctypes.Structure):
+    _fields_ = [("nrows", _I64), ("ncols", _I64), ("nnz", _I64), ("row_ptr", _VP),
+                ("col_idx", _VP), ("values", _VP), ("flags", ctypes.c_uint32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("sym_upper", _I64 * (NGROUPS - 1)), ("num_upper", _I64 * (NGROUPS - 1)),
+                ("chunk_cols", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("flops", _I64), ("ip_total", _I64), ("ip_max", _I64), ("nnz_c", _I64),
+                ("sym_group_rows", _I64 * NGROUPS), ("num_group_rows", _I64 * NGROUPS),
+                ("chunk_cols", _I64), ("chunks_per_row", _I64),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(_VP, _VP, ctypes.c_size_t, _VP)
+FREE_FN = ctypes.CFUNCTYPE(None, _VP, _VP, _VP)
+
+STATUS = {0: "SPGEMM_OK", 1: "SPGEMM_EINVAL", 2: "SPGEMM_EDIM", 3: "SPGEMM_EINDEX",
+          4: "SPGEMM_EOVERFLOW", 5: "SPGEMM_ENOMEM", 6: "SPGEMM_EHIP", 7: "SPGEMM_ESTATE",
+          8: "SPGEMM_EINTERNAL"}
+
+EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_batch",
+            "spgemm_symbolic", "spgemm_symbolic_batch", "spgemm_numeric",
+            "spgemm_numeric_batch", "spgemm_sync", "spgemm_get_info", "spgemm_export",
+            "spgemm_timing_count", "spgemm_timing", "spgemm_free", "spgemm_status_string"]
+
+
+class SpgemmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads the HIP library (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    pp = ctypes.POINTER(_VP)
+    lib.spgemm_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.spgemm_default_options.restype = None
+    lib.spgemm_plan_create.argtypes = [pp, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc),
+                                       ctypes.POINTER(Options), _VP, ALLOC_FN, FREE_FN, _VP]
+    lib.spgemm_plan_create_batch.argtypes = [pp, ctypes.c_int32, ctypes.POINTER(CsrDesc),
+                                             ctypes.POINTER(CsrDesc), ctypes.POINTER(Options),
+                                             _VP, ALLOC_FN, FREE_FN, _VP]
+    lib.spgemm_symbolic.argtypes = [_VP, _VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
+    lib.spgemm_symbolic_batch.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_I64)]
+    lib.spgemm_numeric.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    lib.spgemm_numeric_batch.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                         ctypes.POINTER(_VP), ctypes.POINTER(_VP)]
+    lib.spgemm_sync.argtypes = [_VP]
+    lib.spgemm_get_info.argtypes = [_VP, ctypes.POINTER(Info)]
+    lib.spgemm_export.argtypes = [_VP, ctypes.c_int32, _VP, ctypes.POINTER(_I64)]
+    lib.spgemm_timing_count.argtypes = [_VP]
+    lib.spgemm_timing_count.restype = ctypes.c_int32
+    lib.spgemm_timing.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p),
+                                  ctypes.POINTER(ctypes.c_float)]
+    lib.spgemm_timing.restype = ctypes.c_int
+    lib.spgemm_free.argtypes = [_VP]
+    lib.spgemm_free.restype = None
+    lib.spgemm_status_string.argtypes = [ctypes.c_int]
+    lib.spgemm_status_string.restype = ctypes.c_char_p
+    for name in ("spgemm_plan_create", "spgemm_plan_create_batch", "spgemm_symbolic",
+                 "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
+                 "spgemm_sync", "spgemm_get_info", "spgemm_export"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise SpgemmError(code, where)
+
+
+def default_options() -> Options:
+    o = Options()
+    load().spgemm_default_options(ctypes.byref(o))
+    return o
+
+
+def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
+                 profile=None) -> Options:
+    o = default_options()
+    if sym_upper is not None:
+        for g, v in enumerate(sym_upper):
+            o.sym_upper[g] = int(v)
+    if num_upper is not None:
+        for g, v in enumerate(num_upper):
+            o.num_upper[g] = int(v)
+    if chunk_cols is not None:
+        o.chunk_cols = int(chunk_cols)
+    if validate is not None:
+        o.validate = int(validate)
+    if profile is not None:
+        o.profile = int(profile)
+    return o
+
+
+# ---------------------------------------------------------------------------
+# torch glue
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+class _TorchAllocator:
+    """Routes the library's workspace through PyTorch's caching allocator."""
+
+    def __init__(self, device):
+        torch = _torch()
+        self.device = torch.device(device)
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device.index,
+                                                          stream or None)
+            except Exception:
+                return None
+
+        def _free(ctx, ptr, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+@dataclasses.dataclass
+class DeviceCsr:
+    """CSR matrix resident on the GPU (torch tensors)."""
+
+    nrows: int
+    ncols: int
+    rpt: "object"   # torch.int64 [nrows + 1]
+    col: "object"   # torch.int32 [nnz]
+    val: "object"   # torch.float32 [nnz]
+    sorted_rows: bool = True
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def desc(self, with_values: bool = True) -> CsrDesc:
+        return CsrDesc(self.nrows, self.ncols, self.nnz, self.rpt.data_ptr(),
+                       self.col.data_ptr() if self.nnz else None,
+                       self.val.data_ptr() if (with_values and self.nnz) else None,
+                       ROWS_SORTED if self.sorted_rows else 0)
+
+    def to_host(self):
+        from . import gen
+        return gen.Csr(self.nrows, self.ncols, self.rpt.cpu().numpy(), self.col.cpu().numpy(),
+                       self.val.cpu().numpy())
+
+
+def to_device(m, device="cuda", sorted_rows: bool | None = None) -> DeviceCsr:
+    """Host gen.Csr -> DeviceCsr.  Row sortedness is checked on the host
+    unless given."""
+    torch = _torch()
+    if sorted_rows is None:
+        sorted_rows = _rows_sorted(m)
+    return DeviceCsr(m.nrows, m.ncols,
+                     torch.from_numpy(np.ascontiguousarray(m.rpt, dtype=np.int64)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(m.col, dtype=np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(m.val, dtype=np.float32)).to(device),
+                     bool(sorted_rows))
+
+
+def _rows_sorted(m) -> bool:
+    if m.nnz < 2:
+        return True
+    d = np.diff(m.col.astype(np.int64))
+    inner = np.ones(m.nnz - 1, dtype=bool)
+    ends = m.rpt[1:-1]
+    ends = ends[(ends > 0) & (ends < m.nnz)]
+    inner[ends - 1] = False
+    return bool(np.all(d[inner] > 0))
+
+
+class Plan:
+    """One plan (single product or batch) on the current torch stream."""
+
+    def __init__(self, As, Bs, options: Options | None = None, stream=None,
+                 use_torch_allocator: bool = True):
+        torch = _torch()
+        lib = load()
+        self._lib = lib
+        self.batch = isinstance(As, (list, tuple))
+        self.As = list(As) if self.batch else [As]
+        self.Bs = list(Bs) if self.batch else [Bs]
+        if len(self.As) != len(self.Bs) or not self.As:
+            raise ValueError("need equally many A and B")
+        dev = self.As[0].rpt.device
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._alloc = _TorchAllocator(dev) if use_torch_allocator else None
+        self._handle = _VP()
+        n = len(self.As)
+        da = (CsrDesc * n)(*[a.desc(False) for a in self.As])
+        db = (CsrDesc * n)(*[b.desc(False) for b in self.Bs])
+        opt = options if options is not None else default_options()
+        afn = self._alloc.alloc if self._alloc else ALLOC_FN()
+        ffn = self._alloc.free if self._alloc else FREE_FN()
+        sh = _VP(self.stream.cuda_stream)
+        if self.batch:
+            code = lib.spgemm_plan_create_batch(ctypes.byref(self._handle), n, da, db,
+                                                ctypes.byref(opt), sh, afn, ffn, None)
+        else:
+            code = lib.spgemm_plan_create(ctypes.byref(self._handle), da, db, ctypes.byref(opt),
+                                          sh, afn, ffn, None)
+        _check(code, "spgemm_plan_create")
+        self.nnz = None
+        self.rpts = None
+
+    # -- phases ------------------------------------------------------------
+    def symbolic(self):
+        torch = _torch()
+        lib = self._lib
+        if not self.batch:
+            rpt = torch.empty(self.As[0].nrows + 1, dtype=torch.int64, device=self.device)
+            nnz = _I64()
+            flops = _I64()
+            _check(lib.spgemm_symbolic(self._handle, _VP(rpt.data_ptr()), ctypes.byref(nnz),
+                                       ctypes.byref(flops)), "spgemm_symbolic")
+            self.rpts = [rpt]
+            self.nnz = [int(nnz.value)]
+        else:
+            n = len(self.As)
+            self.rpts = [torch.empty(a.nrows + 1, dtype=torch.int64, device=self.device)
+                         for a in self.As]
+            ptrs = (_VP * n)(*[r.data_ptr() for r in self.rpts])
+            nnz = (_I64 * n)()
+            _check(lib.spgemm_symbolic_batch(self._handle, ptrs, nnz), "spgemm_symbolic_batch")
+            self.nnz = [int(x) for x in nnz]
+        return self.nnz
+
+    def allocate_outputs(self):
+        torch = _torch()
+        cols = [torch.empty(max(k, 1), dtype=torch.int32, device=self.device) for k in self.nnz]
+        vals = [torch.empty(max(k, 1), dtype=torch.float32, device=self.device) for k in self.nnz]
+        return cols, vals
+
+    def numeric(self, cols, vals, a_vals=None, b_vals=None):
+        lib = self._lib
+        a_vals = a_vals if a_vals is not None else [a.val for a in self.As]
+        b_vals = b_vals if b_vals is not None else [b.val for b in self.Bs]
+        if not self.batch:
+            _check(lib.spgemm_numeric(self._handle, _VP(a_vals[0].data_ptr()),
+                                      _VP(b_vals[0].data_ptr()), _VP(cols[0].data_ptr()),
+                                      _VP(vals[0].data_ptr())), "spgemm_numeric")
+        else:
+            n = len(self.As)
+            _check(lib.spgemm_numeric_batch(
+                self._handle, (_VP * n)(*[t.data_ptr() for t in a_vals]),
+                (_VP * n)(*[t.data_ptr() for t in b_vals]),
+                (_VP * n)(*[t.data_ptr() for t in cols]),
+                (_VP * n)(*[t.data_ptr() for t in vals])), "spgemm_numeric_batch")
+
+    def sync(self):
+        _check(self._lib.spgemm_sync(self._handle), "spgemm_sync")
+
+    def info(self) -> Info:
+        inf = Info()
+        _check(self._lib.spgemm_get_info(self._handle, ctypes.byref(inf)), "spgemm_get_info")
+        return inf
+
+    def export(self, what: int):
+        torch = _torch()
+        total = sum(a.nrows for a in self.As)
+        dst = torch.empty(max(total, 1), dtype=torch.int64, device=self.device)
+        gs = (_I64 * (NGROUPS + 1))()
+        _check(self._lib.spgemm_export(self._handle, what, _VP(dst.data_ptr()), gs),
+               "spgemm_export")
+        return dst[:total], [int(x) for x in gs]
+
+    def timings(self) -> list[tuple[str, float]]:
+        """(name, ms) of every profiled launch group (options.profile = 1)."""
+        lib = self._lib
+        out = []
+        for k in range(lib.spgemm_timing_count(self._handle)):
+            name = ctypes.c_char_p()
+            ms = ctypes.c_float()
+            _check(lib.spgemm_timing(self._handle, k, ctypes.byref(name), ctypes.byref(ms)),
+                   "spgemm_timing")
+            out.append((name.value.decode(), float(ms.value)))
+        return out
+
+    def free(self):
+        if self._handle:
+            self._lib.spgemm_free(self._handle)
+            self._handle = _VP()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def results(self, cols, vals):
+        out = []
+        for q in range(len(self.As)):
+            k = self.nnz[q]
+            out.append(DeviceCsr(self.As[q].nrows, self.Bs[q].ncols, self.rpts[q],
+                                 cols[q][:k], vals[q][:k], True))
+        return out
+
+
+def matmul(A: DeviceCsr, B: DeviceCsr, options: Options | None = None, stream=None) -> DeviceCsr:
+    """C = A * B on the GPU (plan, symbolic, allocate, numeric, free)."""
+    plan = Plan(A, B, options, stream)
+    try:
+        plan.symbolic()
+        cols, vals = plan.allocate_outputs()
+        plan.numeric(cols, vals)
+        return plan.results(cols, vals)[0]
+    finally:
+        plan.free()
+
+
+def matmul_batch(As, Bs, options: Options | None = None, stream=None):
+    """C_p = A_p * B_p for every p in one batched plan."""
+    plan = Plan(list(As), list(Bs), options, stream)
+    try:
+        plan.symbolic()
+        cols, vals = plan.allocate_outputs()
+        plan.numeric(cols, vals)
+        return plan.results(cols, vals)
+    finally:
+        plan.free()

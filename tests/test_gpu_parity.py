@@ -1,0 +1,181 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Structure (row_ptr, col_idx, explicit zeros included) must match the oracle
+bit for bit; FP32 values must satisfy |c - c*| <= 1e-5 * sum|a||b| per entry;
+integer-valued inputs must match exactly.  Every row group (kernel) is forced
+in turn on inputs that span several workgroups and a ragged tail.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_12036_amd import gen, spgemm
+
+from gpu_util import forced_options, log, run_and_compare, structure_invariants
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    spgemm.load()
+
+
+def test_er_config_small():
+    a = gen.er(2000, 16000, seed=1)
+    c = run_and_compare(a, a, label="er2k")
+    structure_invariants(c)
+
+
+@pytest.mark.parametrize("group", [1, 2, 3, 4, 5, 6, 7])
+def test_forced_group_ragged(group):
+    # rows of every length up to a few hundred, plus empty rows
+    a = gen.skewed_csr(3001, 2500, seed=10 + group, max_len=12, heavy_rows=0)
+    b = gen.skewed_csr(2500, 2700, seed=20 + group, max_len=9, heavy_rows=0)
+    run_and_compare(a, b, options=forced_options(group), label=f"group{group}")
+
+
+@pytest.mark.parametrize("group", [1, 4, 5, 6, 7])
+def test_forced_group_integer_exact(group):
+    a = gen.int_valued(gen.skewed_csr(1500, 1200, seed=31, max_len=10, heavy_rows=0), 1)
+    b = gen.int_valued(gen.skewed_csr(1200, 1300, seed=32, max_len=10, heavy_rows=0), 2)
+    run_and_compare(a, b, options=forced_options(group), exact=True, label=f"int{group}")
+
+
+def test_rmat_default_groups():
+    a = gen.rmat(13, 16, seed=7)
+    c = run_and_compare(a, a, label="rmat13")
+    structure_invariants(c)
+
+
+@pytest.mark.parametrize("chunk_cols", [64, 256, 4096])
+def test_chunk_widths(chunk_cols):
+    a = gen.rmat(12, 16, seed=9)
+    run_and_compare(a, a, options=forced_options(7, chunk_cols), label=f"chunk{chunk_cols}")
+
+
+def test_chunk_unsorted_b():
+    a = gen.rmat(11, 16, seed=12)
+    b = gen.shuffle_rows(a, 3)
+    run_and_compare(a, b, options=forced_options(7, 128), b_sorted=False, label="unsortedB")
+    run_and_compare(a, b, options=None, b_sorted=False, label="unsortedB-default")
+
+
+def test_unsorted_b_detected_on_device():
+    a = gen.rmat(11, 16, seed=13)
+    b = gen.shuffle_rows(a, 4)
+    # flag absent: the library detects the order itself
+    run_and_compare(a, b, options=forced_options(7, 256), b_sorted=False, label="detect")
+
+
+def test_heavy_rows_mixed():
+    a = gen.skewed_csr(2000, 3000, seed=40, max_len=30, heavy_rows=6, heavy_len=1500)
+    b = gen.skewed_csr(3000, 5000, seed=41, max_len=40, heavy_rows=3, heavy_len=2500)
+    run_and_compare(a, b, label="heavy-mixed")
+    run_and_compare(a, b, options=forced_options(7, 512), label="heavy-chunks")
+
+
+def test_cancellation_explicit_zeros():
+    a = gen.from_coo(3, 2, [0, 0, 1, 2], [0, 1, 1, 0], np.array([1, 1, 2, 3], np.float32))
+    b = gen.from_coo(2, 3, [0, 1, 0, 1], [0, 0, 2, 2], np.array([1, -1, 4, -4], np.float32))
+    for g in range(1, 8):
+        c = run_and_compare(a, b, options=forced_options(g), exact=True, label=f"cancel{g}")
+        assert c.nnz == 6
+
+
+def test_empty_inputs():
+    for (m, k, n) in [(0, 5, 7), (5, 0, 7), (5, 7, 0), (1, 1, 1)]:
+        a = gen.random_csr(m, k, 0.5, 1)
+        b = gen.random_csr(k, n, 0.5, 2)
+        run_and_compare(a, b, label=f"empty{(m, k, n)}")
+    z = gen.random_csr(100, 80, 0.0, 1)
+    run_and_compare(z, gen.random_csr(80, 90, 0.3, 2), label="zero-A")
+
+
+def test_identity_exact():
+    a = gen.rmat(12, 8, seed=5)
+    n = a.ncols
+    eye = gen.from_coo(n, n, np.arange(n), np.arange(n), np.ones(n, np.float32))
+    c = run_and_compare(a, eye, exact=True, label="identity")
+    assert np.array_equal(c.val.cpu().numpy(), a.val)
+
+
+def test_ip_and_maps_bit_exact():
+    import torch
+    a = gen.rmat(12, 16, seed=21)
+    da, db = spgemm.to_device(a), spgemm.to_device(a)
+    opt = spgemm.default_options()
+    plan = spgemm.Plan(da, db, opt)
+    try:
+        ip, _ = plan.export(0)
+        assert np.array_equal(ip.cpu().numpy(), oracle.ip(a, a))
+        m, gs = plan.export(1)
+        _, order, offs = oracle.bins_reference(oracle.ip(a, a), list(opt.sym_upper))
+        mm = m.cpu().numpy()
+        assert np.all((mm >> 32) == 0)
+        assert np.array_equal(mm & 0xffffffff, order)
+        assert gs == offs.tolist()
+        plan.symbolic()
+        m2, gs2 = plan.export(2)
+        counts = oracle.row_counts(a, a)
+        _, order2, offs2 = oracle.bins_reference(counts, list(opt.num_upper))
+        assert np.array_equal(m2.cpu().numpy() & 0xffffffff, order2)
+        assert gs2 == offs2.tolist()
+        assert np.array_equal(np.diff(plan.rpts[0].cpu().numpy()), counts)
+        info = plan.info()
+        assert info.ip_total == int(oracle.ip(a, a).sum())
+        assert info.nnz_c == int(counts.sum())
+    finally:
+        plan.free()
+    torch.cuda.synchronize()
+
+
+def test_value_only_rerun():
+    import torch
+    a = gen.rmat(11, 16, seed=33)
+    da, db = spgemm.to_device(a), spgemm.to_device(a)
+    plan = spgemm.Plan(da, db)
+    try:
+        plan.symbolic()
+        cols, vals = plan.allocate_outputs()
+        plan.numeric(cols, vals)
+        a2 = gen.int_valued(a, 5)
+        v2 = torch.from_numpy(a2.val).cuda()
+        plan.numeric(cols, vals, a_vals=[v2], b_vals=[v2])
+        plan.sync()
+        ref = oracle.product(a2, a2)
+        k = plan.nnz[0]
+        msg = oracle.compare(ref, plan.rpts[0].cpu().numpy(), cols[0][:k].cpu().numpy(),
+                             vals[0][:k].cpu().numpy(), exact_values=True)
+        assert msg is None, msg
+    finally:
+        plan.free()
+
+
+def test_validation_rejects_malformed():
+    import torch
+    a = gen.rmat(8, 8, seed=1)
+    da = spgemm.to_device(a)
+    bad = spgemm.DeviceCsr(da.nrows, da.ncols, da.rpt.clone(), da.col.clone(), da.val, True)
+    bad.col[3] = da.ncols + 5          # column out of range
+    opt = spgemm.make_options(validate=1)
+    with pytest.raises(spgemm.SpgemmError) as e:
+        spgemm.Plan(da, bad, opt)
+    assert e.value.code == 3
+    bad2 = spgemm.DeviceCsr(da.nrows, da.ncols, da.rpt.clone(), da.col, da.val, True)
+    bad2.rpt[5] = bad2.rpt[6] + 1      # non-monotone row pointers
+    with pytest.raises(spgemm.SpgemmError) as e:
+        spgemm.Plan(bad2, da, opt)
+    assert e.value.code == 3
+    torch.cuda.synchronize()
+
+
+def test_dimension_mismatch():
+    a = spgemm.to_device(gen.random_csr(10, 12, 0.3, 1))
+    b = spgemm.to_device(gen.random_csr(13, 9, 0.3, 2))
+    with pytest.raises(spgemm.SpgemmError) as e:
+        spgemm.Plan(a, b)
+    assert e.value.code == 2
