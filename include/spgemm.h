@@ -102,7 +102,7 @@ typedef struct {
      * numeric phase must have been handled as chunks in the symbolic one). */
     int64_t sym_upper[SPGEMM_NGROUPS - 1];
     int64_t num_upper[SPGEMM_NGROUPS - 1];
-    /* Maximum columns per chunk of group 7 (multiple of 64, 64 .. 32768).  The
+    /* Maximum columns per chunk of group 7 (multiple of 64, 64 .. 16384).  The
      * number of chunks per row is a multiple of 8 so that chunk c of every
      * row runs on the same accelerator die (XCD c mod 8). */
     int32_t chunk_cols;
@@ -112,7 +112,10 @@ typedef struct {
     /* 1: record a HIP event pair around every kernel launch group on the
      * plan's stream (read back with spgemm_timing). */
     int32_t profile;
-    int32_t reserved[5];
+    /* Chunks of one group-7 row handled by one workgroup (1, 2, 4 or 8):
+     * more amortises the row's staging, fewer gives more parallelism. */
+    int32_t chunks_per_item;
+    int32_t reserved[4];
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;

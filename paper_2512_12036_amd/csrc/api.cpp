@@ -55,13 +55,18 @@ struct spgemm_plan {
     size_t scan_tmp_bytes = 0;
 
     // chunk group (symbolic group 7)
-    int64_t nh = 0, h_alen = 0, h_split = 0, h_items = 0;
-    int64_t *alen = nullptr, *aoff = nullptr, *splitlen = nullptr, *soff = nullptr;
-    int64_t *nchv = nullptr, *ibase = nullptr, *chunk_cnt = nullptr, *chunk_pos = nullptr;
-    int32_t *split = nullptr;
+    int64_t nh = 0, h_items = 0;
+    int64_t *nchv = nullptr, *ibase = nullptr, *cbase = nullptr, *chunk_cnt = nullptr;
+    int64_t *chunk_pos = nullptr;
+    int32_t *hitem_row = nullptr;
+    ChunkDesc *sdesc = nullptr;
     // numeric group 7
     int64_t nd = 0, d_items = 0;
     int64_t *dnchv = nullptr, *dbase = nullptr;
+    int32_t *ditem_row = nullptr;
+    ChunkDesc *ndesc = nullptr;
+    int wmax = 0;       // widest chunk over the products
+    bool fast = true;   // every B sorted with < 2^30 entries (32-bit chunk indexing)
 
     // pinned host readback
     int64_t *hread = nullptr;
@@ -191,6 +196,9 @@ spgemm_status check_options(const spgemm_options &o) {
         return SPGEMM_EINVAL;
     if (o.validate < 0 || o.validate > 1) return SPGEMM_EINVAL;
     if (o.profile < 0 || o.profile > 1) return SPGEMM_EINVAL;
+    if (o.chunks_per_item != 1 && o.chunks_per_item != 2 && o.chunks_per_item != 4 &&
+        o.chunks_per_item != 8)
+        return SPGEMM_EINVAL;
     return SPGEMM_OK;
 }
 
@@ -252,6 +260,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         w = (w + 63) / 64 * 64;
         if (w < 64) w = 64;
         P.W = (int32_t)w;
+        p->wmax = std::max<int>(p->wmax, P.W);
         P.b_sorted = (b.flags & SPGEMM_ROWS_SORTED) ? 1 : 2;
         for (int64_t i0 = 0; i0 < a.nrows; i0 += kRowBlock) {
             RowBlk rb;
@@ -354,34 +363,47 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         p->ip_total += (int64_t)ps[q].ip_sum;
         p->ip_max = std::max<int64_t>(p->ip_max, (int64_t)ps[q].ip_max);
         p->nh += (int64_t)ps[q].h_rows;
-        p->h_alen += (int64_t)ps[q].h_alen;
-        p->h_split += (int64_t)ps[q].h_split;
         p->h_items += (int64_t)ps[q].h_items;
         if (p->hprods[q].b_sorted == 2) p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
+        if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
     }
     if (p->nh != p->sym_start[kGroups] - p->sym_start[kGroups - 1]) return SPGEMM_EINTERNAL;
     if (p->h_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
 
-    // chunk-group preparation: per-row A lengths, split tables, chunk bases
+    // chunk-group preparation: chunk bases, item -> row map, chunk bounds of
+    // every B row, item descriptors
     if (p->nh > 0) {
         const int64_t nh = p->nh;
         const uint64_t *hitems = p->map_sym + p->sym_start[kGroups - 1];
-        ST_TRY(dalloc(p, &p->alen, nh));
-        ST_TRY(dalloc(p, &p->splitlen, nh));
+        const int64_t nitems = p->h_items / p->opt.chunks_per_item;
         ST_TRY(dalloc(p, &p->nchv, nh));
-        ST_TRY(dalloc(p, &p->aoff, nh + 1));
-        ST_TRY(dalloc(p, &p->soff, nh + 1));
         ST_TRY(dalloc(p, &p->ibase, nh + 1));
-        ST_TRY(dalloc(p, &p->split, p->h_split));
+        ST_TRY(dalloc(p, &p->cbase, nh + 1));
         ST_TRY(dalloc(p, &p->chunk_cnt, p->h_items));
         ST_TRY(dalloc(p, &p->chunk_pos, p->h_items + 1));
+        ST_TRY(dalloc(p, &p->hitem_row, nitems));
+        ST_TRY(dalloc(p, &p->sdesc, nitems));
         TimeScope ts(p, "plan.split");
-        launch_heavy_prep(p->dprods, hitems, nh, p->alen, p->splitlen, p->nchv, p->stream);
+        bool reupload = false;
+        for (int q = 0; q < nprod; ++q) {
+            ProdDev &P = p->hprods[q];
+            if (ps[q].h_rows == 0 || P.b_sorted != 1) continue;
+            int32_t *bs = nullptr;
+            ST_TRY(dalloc(p, &bs, (size_t)P.k * (P.nch + 1)));
+            launch_bsplit(P.rptB, P.colB, P.k, P.W, P.nch, bs, p->stream);
+            P.bsplit = bs;
+            reupload = true;
+        }
+        if (reupload) ST_TRY(upload_descriptors(p));
+        launch_nch_of(p->dprods, hitems, nh, 1, p->nchv, p->stream);
         ST_TRY(launch_check());
-        ST_TRY(scan(p, p->alen, p->aoff, nh));
-        ST_TRY(scan(p, p->splitlen, p->soff, nh));
+        ST_TRY(scan(p, p->nchv, p->cbase, nh));
+        launch_nch_of(p->dprods, hitems, nh, p->opt.chunks_per_item, p->nchv, p->stream);
+        ST_TRY(launch_check());
         ST_TRY(scan(p, p->nchv, p->ibase, nh));
-        launch_split(p->dprods, hitems, nh, p->aoff, p->soff, p->h_alen, p->split, p->stream);
+        launch_expand(p->ibase, nh, p->hitem_row, p->stream);
+        launch_sym_desc(p->dprods, hitems, p->hitem_row, p->ibase, p->cbase, nitems,
+                        p->opt.chunks_per_item, p->sdesc, p->stream);
         ST_TRY(launch_check());
     }
     p->state = 1;
@@ -436,14 +458,13 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     for (int g = 5; g <= 6; ++g) {
         if (p->sym_start[g + 1] == p->sym_start[g]) continue;
         TimeScope ts(p, sym_names[g]);
-        launch_sym_block(g, p->dprods, p->map_sym + p->sym_start[g], p->ip,
+        launch_sym_block(g, p->opt.sym_upper[g], p->dprods, p->map_sym + p->sym_start[g], p->ip,
                          p->sym_start[g + 1] - p->sym_start[g], p->row_nnz, p->flags, st);
     }
     if (p->nh > 0) {
         TimeScope ts(p, sym_names[7]);
-        launch_sym_chunk(p->dprods, p->map_sym + p->sym_start[kGroups - 1], p->nh, p->ibase,
-                         p->h_items, p->aoff, p->soff, p->split, p->chunk_cnt, p->row_nnz,
-                         p->flags, st);
+        launch_sym_chunk(p->wmax, p->fast, p->dprods, p->sdesc, p->h_items / p->opt.chunks_per_item, p->opt.chunks_per_item,
+                         p->chunk_cnt, p->row_nnz, st);
     }
     ST_TRY(launch_check());
     {
@@ -492,11 +513,19 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     if (p->nd != p->num_start[kGroups] - p->num_start[kGroups - 1]) return SPGEMM_EINTERNAL;
     if (p->d_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
     if (p->nd > 0) {
+        const uint64_t *ditems = p->map_num + p->num_start[kGroups - 1];
+        const int64_t nitems = p->d_items / p->opt.chunks_per_item;
         ST_TRY(dalloc(p, &p->dnchv, p->nd));
         ST_TRY(dalloc(p, &p->dbase, p->nd + 1));
-        launch_dense_prep(p->dprods, p->map_num + p->num_start[kGroups - 1], p->nd, p->dnchv, st);
+        ST_TRY(dalloc(p, &p->ditem_row, nitems));
+        ST_TRY(dalloc(p, &p->ndesc, nitems));
+        launch_nch_of(p->dprods, ditems, p->nd, p->opt.chunks_per_item, p->dnchv, st);
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->dnchv, p->dbase, p->nd));
+        launch_expand(p->dbase, p->nd, p->ditem_row, st);
+        launch_num_desc(p->dprods, ditems, p->ditem_row, p->dbase, nitems,
+                        p->opt.chunks_per_item, p->hslot, p->cbase, p->rptv, p->ndesc, st);
+        ST_TRY(launch_check());
     }
     p->state = 2;
     return SPGEMM_OK;
@@ -517,14 +546,13 @@ spgemm_status numeric_impl(spgemm_plan *p) {
     for (int g = 5; g <= 6; ++g) {
         if (p->num_start[g + 1] == p->num_start[g]) continue;
         TimeScope ts(p, num_names[g]);
-        launch_num_block(g, p->dprods, p->map_num + p->num_start[g],
+        launch_num_block(g, p->opt.num_upper[g], p->dprods, p->map_num + p->num_start[g],
                          p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st);
     }
     if (p->nd > 0) {
         TimeScope ts(p, num_names[7]);
-        launch_num_chunk(p->dprods, p->map_num + p->num_start[kGroups - 1], p->nd, p->dbase,
-                         p->d_items, p->hslot, p->ibase, p->aoff, p->soff, p->split,
-                         p->chunk_cnt, p->chunk_pos, p->rptv, p->flags, st);
+        launch_num_chunk(p->wmax, p->fast, p->dprods, p->ndesc, p->d_items / p->opt.chunks_per_item,
+                         p->opt.chunks_per_item, p->chunk_cnt, p->chunk_pos, p->flags, st);
     }
     return launch_check();
 }
@@ -536,14 +564,16 @@ extern "C" {
 void spgemm_default_options(spgemm_options *opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
-    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 4096, 8192};
-    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 8192};
+    // tuned on gfx950 (R-MAT scale 18 self-product; see the autotuner)
+    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 4096, 4096};
+    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 4096};
     for (int g = 0; g < kGroups - 1; ++g) {
         opt->sym_upper[g] = sym[g];
         opt->num_upper[g] = num[g];
     }
-    opt->chunk_cols = kMaxChunkCols;
+    opt->chunk_cols = 8192;
     opt->validate = 0;
+    opt->chunks_per_item = 1;
 }
 
 spgemm_status spgemm_plan_create(spgemm_plan **out, const spgemm_csr *A, const spgemm_csr *B,

@@ -10,7 +10,7 @@ namespace spg {
 
 constexpr int kGroups = 8;           // row groups, see spgemm.h
 constexpr int kChunkGroup = 7;       // column-chunked group
-constexpr int kMaxChunkCols = 32768; // LDS dense accumulator: 128 KiB FP32
+constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 accumulator + 32 KiB flags
 constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
 // Largest key each group can take (tables at most half full).
 constexpr int64_t kSymCap[kGroups] = {0, 32, 64, 128, 256, 4096, 16384, 0};
@@ -33,11 +33,23 @@ struct ProdDev {
     const float *valB;
     int32_t *colC;
     float *valC;
+    const int32_t *bsplit;  // chunk bounds per B row (group-7 rows, sorted B)
     int64_t m, k, n;
     int64_t row_base;   // first row of this product in the batch row space
     int32_t W;          // columns per chunk
     int32_t nch;        // chunks per row (multiple of 8)
     int32_t b_sorted;   // rows of B strictly ascending: 1 yes, 0 no, 2 detect
+    int32_t pad;
+};
+
+// One work item of group 7: the chunks q, q + Q, ... (K of them) of one row.
+struct ChunkDesc {
+    int64_t a0;      // first A nonzero of the row
+    int64_t out0;    // symbolic: batch row index; numeric: output offset of the row in C_p
+    int64_t slot0;   // chunk-count slot of the row's chunk 0
+    int32_t alen;    // A nonzeros of the row
+    int32_t q;       // first chunk of the item
+    int32_t prod;    // product index
     int32_t pad;
 };
 
@@ -105,36 +117,34 @@ void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk,
                     uint64_t *map, int32_t *hslot, hipStream_t s);
 void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStream_t s);
 
-// Chunk preparation: per chunk-group row h (map positions [0, nh)):
-// alen[h], splitlen[h] = alen * (nch + 1), nchv[h] = nch.
-void launch_heavy_prep(const ProdDev *prods, const uint64_t *items, int64_t nh,
-                       int64_t *alen, int64_t *splitlen, int64_t *nchv, hipStream_t s);
-void launch_dense_prep(const ProdDev *prods, const uint64_t *items, int64_t nd,
-                       int64_t *nchv, hipStream_t s);
-void launch_split(const ProdDev *prods, const uint64_t *items, int64_t nh,
-                  const int64_t *aoff, const int64_t *soff, int64_t total_alen,
-                  int32_t *split, hipStream_t s);
+// Chunk preparation (group 7).
+void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
+                   int32_t *bsplit, hipStream_t s);
+void launch_nch_of(const ProdDev *prods, const uint64_t *items, int64_t n, int div,
+                   int64_t *nchv, hipStream_t s);
+void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s);
+void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
+                     const int64_t *ibase, const int64_t *cbase, int64_t nitems, int kper,
+                     ChunkDesc *desc, hipStream_t s);
+void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t *item_of,
+                     const int64_t *dbase, int64_t nitems, int kper, const int32_t *hslot,
+                     const int64_t *cbase, const int64_t *rptv, ChunkDesc *desc, hipStream_t s);
 
 void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, int64_t *row_nnz, int *err, hipStream_t s);
-void launch_sym_block(int g, const ProdDev *prods, const uint64_t *items,
+void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       const int64_t *ipv, int64_t count, int64_t *row_nnz, int *err,
                       hipStream_t s);
-void launch_sym_chunk(const ProdDev *prods, const uint64_t *items, int64_t nh,
-                      const int64_t *ibase, int64_t nitems, const int64_t *aoff,
-                      const int64_t *soff, const int32_t *split, int64_t *chunk_cnt,
-                      int64_t *row_nnz, int *err, hipStream_t s);
-
+void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
+                      int64_t nitems, int kper, int64_t *chunk_cnt, int64_t *row_nnz,
+                      hipStream_t s);
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
-void launch_num_block(int g, const ProdDev *prods, const uint64_t *items,
+void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
-void launch_num_chunk(const ProdDev *prods, const uint64_t *ditems, int64_t nd,
-                      const int64_t *dbase, int64_t nitems, const int32_t *hslot,
-                      const int64_t *ibase, const int64_t *aoff, const int64_t *soff,
-                      const int32_t *split, const int64_t *chunk_cnt,
-                      const int64_t *chunk_pos, const int64_t *rptv, int *err,
-                      hipStream_t s);
+void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
+                      int64_t nitems, int kper, const int64_t *chunk_cnt,
+                      const int64_t *chunk_pos, int *err, hipStream_t s);
 
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,

@@ -1,0 +1,144 @@
+// Device-side helpers shared by the hash and chunk kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace spg {
+
+// Loads through the global address space: the pointers the kernels read come
+// from descriptors in device memory, so the compiler cannot infer the address
+// space and would otherwise emit flat loads (which also wait on LDS traffic).
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
+// A pointer that every lane of the wave holds, moved to scalar registers so
+// that loads can use the scalar-base + 32-bit-offset addressing form.
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const T *)(((uint64_t)hi << 32) | lo);
+}
+
+// Element idx of a uniform base, addressed with a 32-bit byte offset
+// (requires idx * sizeof(T) < 2^32).
+template <typename T>
+__device__ __forceinline__ T gld_off(const T *base, uint32_t idx) {
+    const uint32_t byte = idx * (uint32_t)sizeof(T);
+    return *(const __attribute__((address_space(1))) T *)((const char *)base + byte);
+}
+
+// Largest o in [lo, hi) with e[o] <= q (e non-decreasing, e[lo] <= q).
+template <typename T>
+__device__ __forceinline__ int lds_owner(const T *e, int lo, int hi, T q) {
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (e[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *wsum, T &total) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        T x = wsum[i];
+        if (i < w) before += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return before + incl - v;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    T tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tot += wsum[i];
+    __syncthreads();
+    return tot;
+}
+
+// Enumerates the products of one staged batch of A nonzeros, flat over the
+// workgroup: product q belongs to the staged entry o with st_e[o] <= q <
+// st_e[o+1] (st_e[nv] = total) and reads B entry st_s[o] + q - st_e[o].
+// Each thread takes runs of VT consecutive products (merge-path style): one
+// binary search per run, then a sequential walk that crosses B-row
+// boundaries with one LDS read each (sub-ranges are often only a few entries
+// long), and all VT gathers of a run are issued before any is consumed.
+// S is the type of the staged B-row starts: uint32_t when every B of the
+// plan has fewer than 2^30 entries (gathers then use 32-bit offsets from a
+// scalar base, one address register per load), int64_t otherwise.
+// f(col, a_value, b_value).
+template <int WG, int VT, bool VALUES, typename E, typename S, typename F>
+__device__ __forceinline__ void staged_products(const S *st_s, const E *st_e, const float *st_a,
+                                                int nv, E total, const int32_t *colB,
+                                                const float *valB, F &&f) {
+    constexpr bool kOff32 = sizeof(S) == 4;
+    const int32_t *ucol = uniform_ptr(colB);
+    const float *uval = VALUES ? uniform_ptr(valB) : valB;
+    for (E r0 = (E)threadIdx.x * VT; r0 < total; r0 += (E)WG * VT) {
+        int o = lds_owner<E>(st_e, 0, nv, r0);
+        E enext = st_e[o + 1];
+        S t = st_s[o] + (S)(r0 - st_e[o]);
+        float a = VALUES ? st_a[o] : 0.f;
+        int cc[VT];
+        float aa[VT], vv[VT];
+        bool ok[VT];
+#pragma unroll
+        for (int v = 0; v < VT; ++v) {
+            const E q = r0 + v;
+            ok[v] = q < total;
+            cc[v] = 0;
+            aa[v] = 0.f;
+            vv[v] = 0.f;
+            if (ok[v]) {
+                while (q >= enext) {
+                    ++o;
+                    t = st_s[o];
+                    enext = st_e[o + 1];
+                    if (VALUES) a = st_a[o];
+                }
+                if (kOff32) {
+                    cc[v] = gld_off(ucol, (uint32_t)t);
+                    if (VALUES) vv[v] = gld_off(uval, (uint32_t)t);
+                } else {
+                    cc[v] = gld(colB + t);
+                    if (VALUES) vv[v] = gld(valB + t);
+                }
+                aa[v] = a;
+                ++t;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VT; ++v)
+            if (ok[v]) f(cc[v], aa[v], vv[v]);
+    }
+}
+
+}  // namespace spg

@@ -9,315 +9,445 @@
 //   * numeric : a W-float dense accumulator plus the W-bit occupancy bitmap
 //     (so explicit zeros from cancellation are kept); the chunk is emitted in
 //     column order straight from the bitmap, so these rows need no sort.
-// Chunk c of every row lands on the workgroup index c (mod 8), i.e. on
-// accelerator die c mod 8, so each die's L2 only ever holds the slab of B
-// columns of its chunks.
 //
-// With B's rows sorted, the sub-range of B row k that falls into chunk c is
-// precomputed once per (A nonzero, chunk) by k_split (binary searches) and
-// reused by both phases; with unsorted B rows every chunk scans whole rows and
-// filters, which is correct but nch times the gather traffic.
-#include "common.hpp"
+// Latency: a workgroup handles K chunks of one row (an item) and keeps the
+// row's A nonzeros in registers across them, so per chunk only the chunk
+// bounds are gathered (one chunk ahead) before the B gathers; every item has
+// a 32-byte descriptor built once per phase (k_sym_desc / k_num_desc), so a
+// workgroup starts with one uniform load.  With B's rows sorted, the
+// position of every chunk bound inside every B row is tabulated once per
+// product (k_bsplit, one binary search per (B row, bound)); a workgroup then
+// finds its sub-range of each B row with one gather.  With unsorted B rows
+// every chunk scans whole rows and filters, which is correct but nch times
+// the gather traffic.
+#include <type_traits>
+
+#include "dev.hpp"
 
 namespace spg {
 
-__device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ base, int64_t n,
-                                               int64_t x) {
-    // largest h in [0, n) with base[h] <= x (base non-decreasing, base[0] <= x)
-    int64_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (base[mid] <= x) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-template <int NT>
-__device__ __forceinline__ int64_t block_excl_scan_i64(int64_t v, int64_t *wsum, int64_t &total) {
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int64_t o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    int64_t before = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        int64_t x = wsum[i];
-        if (i < w) before += x;
-        tot += x;
-    }
-    __syncthreads();
-    total = tot;
-    return before + incl - v;
-}
-
-__global__ void k_heavy_prep(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
-                             int64_t nh, int64_t *__restrict__ alen, int64_t *__restrict__ splitlen,
-                             int64_t *__restrict__ nchv) {
-    int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= nh) return;
-    const uint64_t e = items[h];
-    const ProdDev &P = prods[item_prod(e)];
-    const int64_t i = item_row(e);
-    const int64_t a = P.rptA[i + 1] - P.rptA[i];
-    alen[h] = a;
-    splitlen[h] = a * (P.nch + 1);
-    nchv[h] = P.nch;
-}
-
-__global__ void k_dense_prep(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
-                             int64_t nd, int64_t *__restrict__ nchv) {
-    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= nd) return;
-    nchv[d] = prods[item_prod(items[d])].nch;
-}
-
-// One thread per nonzero of a group-7 row: positions of the chunk bounds
-// c * W (c = 0..nch) inside the nonzero's B row, relative to the row start.
-__global__ __launch_bounds__(256) void k_split(const ProdDev *__restrict__ prods,
-                                                const uint64_t *__restrict__ items, int64_t nh,
-                                                const int64_t *__restrict__ aoff,
-                                                const int64_t *__restrict__ soff,
-                                                int64_t total_alen, int32_t *__restrict__ split) {
-    const int64_t jj = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (jj >= total_alen) return;
-    const int64_t h = upper_index(aoff, nh, jj);
-    const int64_t jl = jj - aoff[h];
-    const int64_t alen = aoff[h + 1] - aoff[h];
-    const uint64_t e = items[h];
-    const ProdDev &P = prods[item_prod(e)];
-    const int64_t i = item_row(e);
-    const int k = P.colA[P.rptA[i] + jl];
-    const int64_t b0 = P.rptB[k], b1 = P.rptB[k + 1];
-    int32_t *sp = split + soff[h] + jl;
-    const int nch = P.nch;
-    sp[0] = 0;
-    sp[(int64_t)nch * alen] = (int32_t)(b1 - b0);
-    if (!P.b_sorted) return;  // filtered scans: bounds unused
-    int64_t lo = b0;
-    for (int c = 1; c < nch; ++c) {
-        const int bound = c * P.W;
-        int64_t l = lo, r = b1;  // first index in [lo, b1) with col >= bound
+// bsplit[k * (nch + 1) + c] = first position in B row k (relative to its
+// start) whose column is >= c * W, for c = 0..nch.
+__global__ __launch_bounds__(256) void k_bsplit(const int64_t *__restrict__ rptB,
+                                                 const int32_t *__restrict__ colB, int64_t k_rows,
+                                                 int W, int nch, int32_t *__restrict__ bsplit) {
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t per = nch + 1;
+    if (x >= k_rows * per) return;
+    const int64_t k = x / per;
+    const int c = (int)(x - k * per);
+    const int64_t b0 = rptB[k], b1 = rptB[k + 1];
+    int64_t pos;
+    if (c == 0) {
+        pos = b0;
+    } else if (c == nch) {
+        pos = b1;
+    } else {
+        const int bound = c * W;
+        int64_t l = b0, r = b1;
         while (l < r) {
-            int64_t mid = (l + r) >> 1;
-            if (P.colB[mid] < bound) l = mid + 1; else r = mid;
+            const int64_t mid = (l + r) >> 1;
+            if (colB[mid] < bound) l = mid + 1; else r = mid;
         }
-        sp[(int64_t)c * alen] = (int32_t)(l - b0);
-        lo = l;
+        pos = l;
     }
+    bsplit[x] = (int32_t)(pos - b0);
 }
 
-// Stages the chunk sub-ranges of a batch of A nonzeros and enumerates their
-// products flat over the workgroup.  f(col, a_value, b_index).
-template <int WG, bool VALUES, typename F>
-__device__ __forceinline__ void chunk_products(const ProdDev &P, int64_t a0, int64_t a1,
-                                               const int32_t *sp, int64_t alen, int c, int lo,
-                                               int hi, int64_t *st_s, int64_t *st_e, float *st_a,
-                                               int64_t *wsum, F &&f) {
-    const bool sorted = P.b_sorted != 0;
+// out[base[r] .. base[r+1]) = r for r < n: the row of every chunk item.
+__global__ void k_expand(const int64_t *__restrict__ base, int64_t n, int32_t *__restrict__ out) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    for (int64_t x = base[r]; x < base[r + 1]; ++x) out[x] = (int32_t)r;
+}
+
+// nchv[r] = chunks of row r divided by div (div = 1: chunks, div = K: items).
+__global__ void k_nch_of(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
+                         int64_t n, int div, int64_t *__restrict__ nchv) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) nchv[r] = prods[item_prod(items[r])].nch / div;
+}
+
+// Item `it` of row r covers the chunks q, q + Q, q + 2Q, ... (Q = nch / K
+// items per row, K chunks per item): strided, so that every item mixes dense
+// and sparse column ranges (column densities are skewed) and items carry
+// similar work.  One workgroup per item amortises the row's A staging over
+// K chunks.
+// The item order inside a row is rotated by the row index: workgroup index
+// modulo 8 selects the accelerator die, and with skewed column densities a
+// fixed item-to-die mapping would pile the dense column ranges on one die.
+__device__ __forceinline__ int item_q(int64_t it, int64_t base, int64_t row, int nitems_row) {
+    return (int)((it - base + row) % nitems_row);
+}
+
+// Symbolic items: desc.out0 = batch row, desc.slot0 = first chunk-count slot
+// of the row.
+__global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
+                           const int32_t *__restrict__ item_of, const int64_t *__restrict__ ibase,
+                           const int64_t *__restrict__ cbase, int64_t nitems, int kper,
+                           ChunkDesc *__restrict__ desc) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    const int64_t h = item_of[it];
+    const uint64_t e = items[h];
+    const int p = item_prod(e);
+    const ProdDev &P = prods[p];
+    const int64_t i = item_row(e);
+    ChunkDesc d;
+    d.a0 = P.rptA[i];
+    d.alen = (int32_t)(P.rptA[i + 1] - d.a0);
+    d.out0 = P.row_base + i;
+    d.q = item_q(it, ibase[h], h, P.nch / kper);
+    d.prod = p;
+    d.slot0 = cbase[h];
+    desc[it] = d;
+}
+
+// Numeric items: desc.out0 = output offset of the row inside C_p.
+__global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ ditems,
+                           const int32_t *__restrict__ item_of, const int64_t *__restrict__ dbase,
+                           int64_t nitems, int kper, const int32_t *__restrict__ hslot,
+                           const int64_t *__restrict__ cbase, const int64_t *__restrict__ rptv,
+                           ChunkDesc *__restrict__ desc) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    const int64_t dr = item_of[it];
+    const uint64_t e = ditems[dr];
+    const int p = item_prod(e);
+    const ProdDev &P = prods[p];
+    const int64_t i = item_row(e);
+    const int64_t g = P.row_base + i;
+    ChunkDesc d;
+    d.a0 = P.rptA[i];
+    d.alen = (int32_t)(P.rptA[i + 1] - d.a0);
+    d.out0 = rptv[g] - rptv[P.row_base];
+    d.q = item_q(it, dbase[dr], dr, P.nch / kper);
+    d.prod = p;
+    d.slot0 = cbase[hslot[g]];
+    desc[it] = d;
+}
+
+// One chunk of one row: stages the chunk's sub-range of every B row named
+// by the row's A nonzeros and enumerates the products flat over the
+// workgroup.  When the row has at most WG nonzeros (`resident`), the caller
+// has already loaded them: thread t holds nonzero t as (b0, a) and the
+// chunk bounds x0/x1 of its B row; otherwise the nonzeros are loaded here in
+// batches of WG.  f(col, a_value, b_value).
+// One chunk of one row: stages the chunk's sub-range of every B row named
+// by the row's A nonzeros and enumerates the products flat over the
+// workgroup.  When the row has at most WG nonzeros (`resident`), the caller
+// has already loaded them: thread t holds nonzero t as (b0, a) and the
+// chunk bounds x0/x1 of its B row; otherwise the nonzeros are loaded here in
+// batches of WG.
+// FAST: B rows sorted and fewer than 2^30 entries in B -- a batch then has at
+// most WG * W products (32-bit indices) and B positions fit 32 bits.
+// Otherwise 64-bit indices, and unsorted B rows are scanned whole and
+// filtered to the chunk.  f(col, a_value, b_value).
+template <int WG, int VT, bool VALUES, bool FAST, typename F>
+__device__ __forceinline__ void chunk_pass(const ProdDev &P, int64_t a0, int64_t alen, int c,
+                                           int lo, int hi, bool resident, int64_t rb0, float ra,
+                                           int32_t rx0, int32_t rx1, void *st_s_raw,
+                                           void *st_e_raw, float *st_a, void *wsum_raw, F &&f) {
+    using E = typename std::conditional<FAST, int, int64_t>::type;
+    using S = typename std::conditional<FAST, uint32_t, int64_t>::type;
+    S *st_s = (S *)st_s_raw;
+    E *st_e = (E *)st_e_raw;
+    E *wsum = (E *)wsum_raw;
+    // st_e holds WG + 1 entries; st_e[WG] = batch total
+    const bool sorted = FAST || P.b_sorted == 1;
+    const int64_t per = P.nch + 1;
+    const int64_t a1 = a0 + alen;
     for (int64_t jb = a0; jb < a1; jb += WG) {
         const int64_t j = jb + threadIdx.x;
-        int64_t s = 0, len = 0;
+        int64_t s = 0;
+        E len = 0;
         float a = 0.f;
         if (j < a1) {
-            const int k = P.colA[j];
-            const int64_t b0 = P.rptB[k];
-            if (sorted) {
-                const int32_t *q = sp + (j - a0);
-                const int32_t x0 = q[(int64_t)c * alen], x1 = q[(int64_t)(c + 1) * alen];
-                s = b0 + x0;
-                len = x1 - x0;
+            if (resident) {
+                s = rb0 + rx0;
+                len = (E)(rx1 - rx0);
+                a = ra;
             } else {
-                s = b0;
-                len = P.rptB[k + 1] - b0;
+                const int k = gld(P.colA + j);
+                if (VALUES) a = gld(P.valA + j);
+                const int64_t b0 = gld(P.rptB + k);
+                if (sorted) {
+                    const int32_t *q = P.bsplit + (int64_t)k * per + c;
+                    const int32_t x0 = gld(q), x1 = gld(q + 1);
+                    s = b0 + x0;
+                    len = (E)(x1 - x0);
+                } else {
+                    s = b0;
+                    len = (E)(gld(P.rptB + k + 1) - b0);
+                }
             }
-            if (VALUES) a = P.valA[j];
         }
-        int64_t total;
-        const int64_t excl = block_excl_scan_i64<WG>(len, wsum, total);
-        st_s[threadIdx.x] = s;
+        E total;
+        const E excl = block_excl_scan<WG, E>(len, wsum, total);
+        st_s[threadIdx.x] = (S)s;
         st_e[threadIdx.x] = excl;
+        if (threadIdx.x == 0) st_e[WG] = total;
         if (VALUES) st_a[threadIdx.x] = a;
         __syncthreads();
         const int nv = (int)((a1 - jb) < WG ? (a1 - jb) : WG);
-        for (int64_t q = threadIdx.x; q < total; q += WG) {
-            int l = 0, r = nv;
-            while (r - l > 1) {
-                int mid = (l + r) >> 1;
-                if (st_e[mid] <= q) l = mid; else r = mid;
-            }
-            const int64_t t = st_s[l] + (q - st_e[l]);
-            const int col = P.colB[t];
-            if (sorted || (col >= lo && col < hi)) f(col, VALUES ? st_a[l] : 0.f, t);
+        if (sorted) {
+            staged_products<WG, VT, VALUES, E, S>(st_s, st_e, st_a, nv, total, P.colB, P.valB,
+                                                  f);
+        } else {
+            staged_products<WG, VT, VALUES, E, S>(
+                st_s, st_e, st_a, nv, total, P.colB, P.valB, [&](int col, float av, float bv) {
+                    if (col >= lo && col < hi) f(col, av, bv);
+                });
         }
         __syncthreads();
     }
 }
 
-template <int WG>
-__global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ prods,
-                                                   const uint64_t *__restrict__ items, int64_t nh,
-                                                   const int64_t *__restrict__ ibase,
-                                                   const int64_t *__restrict__ aoff,
-                                                   const int64_t *__restrict__ soff,
-                                                   const int32_t *__restrict__ split,
-                                                   int64_t *__restrict__ chunk_cnt,
-                                                   int64_t *__restrict__ row_nnz) {
-    __shared__ uint32_t bm[kMaxChunkCols / 32];
-    __shared__ int64_t st_s[WG];
-    __shared__ int64_t st_e[WG];
-    __shared__ int64_t wsum[WG / 64];
-    const int64_t it = blockIdx.x;
-    const int64_t h = upper_index(ibase, nh, it);
-    const int c = (int)(it - ibase[h]);
-    const uint64_t e = items[h];
-    const ProdDev &P = prods[item_prod(e)];
-    const int64_t i = item_row(e);
-    const int lo = c * P.W;
-    const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
-    if (hi <= lo) {  // chunk past the last column
-        if (threadIdx.x == 0) chunk_cnt[it] = 0;
-        return;
-    }
-    const int nwords = (hi - lo + 31) >> 5;
-    for (int w = threadIdx.x; w < nwords; w += WG) bm[w] = 0u;
-    __syncthreads();
-    const int64_t a0 = P.rptA[i], a1 = P.rptA[i + 1];
-    chunk_products<WG, false>(P, a0, a1, split + soff[h], a1 - a0, c, lo, hi, st_s, st_e,
-                              (float *)nullptr, wsum, [&](int col, float, int64_t) {
-                                  const int rel = col - lo;
-                                  atomicOr(&bm[rel >> 5], 1u << (rel & 31));
-                              });
-    int64_t cnt = 0;
-    for (int w = threadIdx.x; w < nwords; w += WG) cnt += __popc(bm[w]);
-    int64_t tot;
-    block_excl_scan_i64<WG>(cnt, wsum, tot);
-    if (threadIdx.x == 0) {
-        chunk_cnt[it] = tot;
-        if (tot) atomicAdd((unsigned long long *)&row_nnz[P.row_base + i], (unsigned long long)tot);
+// Loads the row's nonzero owned by this thread (resident rows) and the chunk
+// bounds of its B row for chunk c.
+__device__ __forceinline__ void resident_load(const ProdDev &P, int64_t a0, int64_t alen,
+                                              bool values, int &k, int64_t &b0, float &a) {
+    k = 0;
+    b0 = 0;
+    a = 0.f;
+    if ((int64_t)threadIdx.x < alen) {
+        k = gld(P.colA + a0 + threadIdx.x);
+        if (values) a = gld(P.valA + a0 + threadIdx.x);
+        b0 = gld(P.rptB + k);
     }
 }
 
-template <int WG, int WMAX>
-__global__ __launch_bounds__(WG) void k_num_chunk(
-    const ProdDev *__restrict__ prods, const uint64_t *__restrict__ ditems, int64_t nd,
-    const int64_t *__restrict__ dbase, const int32_t *__restrict__ hslot,
-    const int64_t *__restrict__ ibase, const int64_t *__restrict__ soff,
-    const int32_t *__restrict__ split, const int64_t *__restrict__ chunk_cnt,
-    const int64_t *__restrict__ chunk_pos, const int64_t *__restrict__ rptv,
-    int *__restrict__ err) {
+__device__ __forceinline__ void resident_bounds(const ProdDev &P, int64_t alen, int k, int c,
+                                                int32_t &x0, int32_t &x1) {
+    x0 = 0;
+    x1 = 0;
+    if ((int64_t)threadIdx.x < alen) {
+        if (P.b_sorted == 1) {
+            const int32_t *q = P.bsplit + (int64_t)k * (P.nch + 1) + c;
+            x0 = gld(q);
+            x1 = gld(q + 1);
+        } else {
+            const int64_t b0 = gld(P.rptB + k);
+            x1 = (int32_t)(gld(P.rptB + k + 1) - b0);
+        }
+    }
+}
+
+template <int WG, int WMAX, bool FAST>
+__global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ prods,
+                                                   const ChunkDesc *__restrict__ desc, int kper,
+                                                   int64_t *__restrict__ chunk_cnt,
+                                                   int64_t *__restrict__ row_nnz) {
+    __shared__ uint32_t bm[WMAX / 32];
+    __shared__ int64_t st_s[WG];
+    __shared__ int64_t st_e[WG + 1];
+    __shared__ int64_t wsum[WG / 64];
+    const ChunkDesc d = desc[blockIdx.x];
+    const ProdDev &P = prods[d.prod];
+    const int Q = P.nch / kper;
+    const bool resident = d.alen <= WG;
+    int k;
+    int64_t b0;
+    float a;
+    if (resident) resident_load(P, d.a0, d.alen, false, k, b0, a);
+    int32_t nx0 = 0, nx1 = 0;
+    if (resident) resident_bounds(P, d.alen, k, d.q, nx0, nx1);
+    for (int x = threadIdx.x; x < WMAX / 32; x += WG) bm[x] = 0u;
+    int64_t row_total = 0;
+    for (int t = 0; t < kper; ++t) {
+        const int c = d.q + Q * t;
+        const int32_t x0 = nx0, x1 = nx1;
+        if (resident && t + 1 < kper) resident_bounds(P, d.alen, k, c + Q, nx0, nx1);  // prefetch
+        const int lo = c * P.W;
+        const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+        if (hi <= lo) {  // chunk past the last column
+            if (threadIdx.x == 0) chunk_cnt[d.slot0 + c] = 0;
+            continue;
+        }
+        const int nwords = (hi - lo + 31) >> 5;
+        __syncthreads();  // bitmap clear (first chunk) / previous count done
+        chunk_pass<WG, 8, false, FAST>(P, d.a0, d.alen, c, lo, hi, resident, b0, 0.f, x0, x1,
+                                       st_s, st_e, (float *)nullptr, wsum,
+                                       [&](int col, float, float) {
+                                           const int rel = col - lo;
+                                           atomicOr(&bm[rel >> 5], 1u << (rel & 31));
+                                       });
+        int64_t cnt = 0;
+        for (int x = threadIdx.x; x < nwords; x += WG) {
+            cnt += __popc(bm[x]);
+            bm[x] = 0u;  // clear for the next chunk
+        }
+        const int64_t tot = block_sum<WG, int64_t>(cnt, wsum);
+        if (threadIdx.x == 0) chunk_cnt[d.slot0 + c] = tot;
+        row_total += tot;
+    }
+    if (threadIdx.x == 0 && row_total)
+        atomicAdd((unsigned long long *)&row_nnz[d.out0], (unsigned long long)row_total);
+}
+
+constexpr int NVT = 8;  // products per lane per round in the numeric chunk kernel
+
+template <int WG, int WMAX, bool FAST>
+__global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
+                                                   const ChunkDesc *__restrict__ desc, int kper,
+                                                   const int64_t *__restrict__ chunk_cnt,
+                                                   const int64_t *__restrict__ chunk_pos,
+                                                   int *__restrict__ err) {
     __shared__ float acc[WMAX];
     __shared__ uint32_t bm[WMAX / 32];
     __shared__ int64_t st_s[WG];
-    __shared__ int64_t st_e[WG];
+    __shared__ int64_t st_e[WG + 1];
     __shared__ float st_a[WG];
     __shared__ int64_t wsum[WG / 64];
-    constexpr int NW = WG / 64;
-    const int64_t it = blockIdx.x;
-    const int64_t d = upper_index(dbase, nd, it);
-    const int c = (int)(it - dbase[d]);
-    const uint64_t e = ditems[d];
-    const ProdDev &P = prods[item_prod(e)];
-    const int64_t i = item_row(e);
-    const int64_t g = P.row_base + i;
-    const int64_t h = hslot[g];
-    const int64_t sit = ibase[h] + c;
-    const int64_t expect = chunk_cnt[sit];
-    if (expect == 0) return;
-    const int lo = c * P.W;
-    const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
-    const int width = hi - lo;
-    const int nwords = (width + 31) >> 5;
-    for (int q = threadIdx.x; q < width; q += WG) acc[q] = 0.f;
-    for (int w = threadIdx.x; w < nwords; w += WG) bm[w] = 0u;
-    __syncthreads();
-    const int64_t a0 = P.rptA[i], a1 = P.rptA[i + 1];
-    chunk_products<WG, true>(P, a0, a1, split + soff[h], a1 - a0, c, lo, hi, st_s, st_e, st_a,
-                             wsum, [&](int col, float a, int64_t t) {
-                                 const int rel = col - lo;
-                                 atomicAdd(&acc[rel], a * P.valB[t]);
-                                 atomicOr(&bm[rel >> 5], 1u << (rel & 31));
-                             });
-    // Emission in column order: wave w owns columns [w*span, (w+1)*span).
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int units = (width + 63) >> 6;                  // 64-column units
-    const int per = (units + NW - 1) / NW;
-    const int cbeg = w * per * 64;
-    const int cend = min(width, (w + 1) * per * 64);
-    int64_t mine = 0;
-    for (int wd = (cbeg >> 5) + lane; wd < ((cend + 31) >> 5); wd += 64) mine += __popc(bm[wd]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mine += __shfl_down(mine, off, 64);
-    mine = __shfl(mine, 0, 64);
-    int64_t total;
-    int64_t before = block_excl_scan_i64<WG>(lane == 0 ? mine : 0, wsum, total);
-    before = __shfl(before, 0, 64);
-    if (threadIdx.x == 0 && total != expect) atomicOr(err, kErrChunk);
-    const int64_t out0 = rptv[g] - rptv[P.row_base] + (chunk_pos[sit] - chunk_pos[ibase[h]]);
-    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int64_t pos = before;
-    for (int col0 = cbeg; col0 < cend; col0 += 64) {
-        const int col = col0 + lane;
-        const bool bit = col < cend && ((bm[col >> 5] >> (col & 31)) & 1u);
-        const unsigned long long m = __ballot(bit);
-        if (bit) {
-            const int64_t r = pos + __popcll(m & lt);
-            if (r < expect) {
-                P.colC[out0 + r] = lo + col;
-                P.valC[out0 + r] = acc[col];
-            }
+    const ChunkDesc d = desc[blockIdx.x];
+    const ProdDev &P = prods[d.prod];
+    const int Q = P.nch / kper;
+    const bool resident = d.alen <= WG;
+    int k;
+    int64_t b0;
+    float a;
+    if (resident) resident_load(P, d.a0, d.alen, true, k, b0, a);
+    int32_t nx0 = 0, nx1 = 0;
+    if (resident) resident_bounds(P, d.alen, k, d.q, nx0, nx1);
+    // clear once; the emission clears every slot it reads
+    for (int q = threadIdx.x; q < WMAX; q += WG) acc[q] = 0.f;
+    for (int q = threadIdx.x; q < WMAX / 32; q += WG) bm[q] = 0u;
+    const int64_t pos0 = chunk_pos[d.slot0];
+    for (int t = 0; t < kper; ++t) {
+        const int c = d.q + Q * t;
+        const int32_t x0 = nx0, x1 = nx1;
+        if (resident && t + 1 < kper) resident_bounds(P, d.alen, k, c + Q, nx0, nx1);  // prefetch
+        const int64_t expect = chunk_cnt[d.slot0 + c];
+        if (expect == 0) continue;
+        const int64_t out0 = d.out0 + (chunk_pos[d.slot0 + c] - pos0);
+        const int lo = c * P.W;
+        const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+        const int width = hi - lo;
+        if (width > WMAX) {  // the plan picks WMAX >= W; never taken
+            if (threadIdx.x == 0) atomicOr(err, kErrRow);
+            return;
         }
-        pos += __popcll(m);
+        __syncthreads();  // clear (first chunk) / previous emission done
+        chunk_pass<WG, NVT, true, FAST>(P, d.a0, d.alen, c, lo, hi, resident, b0, a, x0, x1,
+                                        st_s, st_e, st_a, wsum, [&](int col, float av, float bv) {
+                                            const int rel = col - lo;
+                                            atomicAdd(&acc[rel], av * bv);
+                                            atomicOr(&bm[rel >> 5], 1u << (rel & 31));
+                                        });
+        // Emission in column order: one bitmap word (32 columns) per lane, the
+        // word's output position from a block scan of the popcounts; a lane
+        // walks only its set bits, and clears the slots it reads.
+        const int nwords = (width + 31) >> 5;
+        int64_t base = 0;
+        for (int w0 = 0; w0 < nwords; w0 += WG) {
+            const int x = w0 + threadIdx.x;
+            uint32_t word = x < nwords ? bm[x] : 0u;
+            int64_t total;
+            const int64_t pre = block_excl_scan<WG, int64_t>(__popc(word), wsum, total);
+            if (word) bm[x] = 0u;
+            int64_t r = base + pre;
+            int32_t *colC = P.colC + out0;
+            float *valC = P.valC + out0;
+            while (word) {
+                const int b = __builtin_ctz(word);
+                word &= word - 1u;
+                const int rel = (x << 5) + b;
+                const float v = acc[rel];
+                acc[rel] = 0.f;
+                if (r < expect) {
+                    gst(colC + r, lo + rel);
+                    gst(valC + r, v);
+                }
+                ++r;
+            }
+            base += total;
+        }
+        if (threadIdx.x == 0 && base != expect) atomicOr(err, kErrChunk);
     }
-    (void)NW;
 }
 
-void launch_heavy_prep(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *alen,
-                       int64_t *splitlen, int64_t *nchv, hipStream_t s) {
-    if (nh <= 0) return;
-    hipLaunchKernelGGL(k_heavy_prep, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, prods,
-                       items, nh, alen, splitlen, nchv);
+void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
+                   int32_t *bsplit, hipStream_t s) {
+    const int64_t n = k_rows * (nch + 1);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rptB, colB,
+                       k_rows, W, nch, bsplit);
 }
 
-void launch_dense_prep(const ProdDev *prods, const uint64_t *items, int64_t nd, int64_t *nchv,
-                       hipStream_t s) {
-    if (nd <= 0) return;
-    hipLaunchKernelGGL(k_dense_prep, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, s, prods,
-                       items, nd, nchv);
+void launch_nch_of(const ProdDev *prods, const uint64_t *items, int64_t n, int div,
+                   int64_t *nchv, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_nch_of, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prods,
+                       items, n, div, nchv);
 }
 
-void launch_split(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *aoff,
-                  const int64_t *soff, int64_t total_alen, int32_t *split, hipStream_t s) {
-    if (total_alen <= 0) return;
-    hipLaunchKernelGGL(k_split, dim3((unsigned)((total_alen + 255) / 256)), dim3(256), 0, s,
-                       prods, items, nh, aoff, soff, total_alen, split);
+void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n, out);
 }
 
-void launch_sym_chunk(const ProdDev *prods, const uint64_t *items, int64_t nh,
-                      const int64_t *ibase, int64_t nitems, const int64_t *aoff,
-                      const int64_t *soff, const int32_t *split, int64_t *chunk_cnt,
-                      int64_t *row_nnz, int *err, hipStream_t s) {
-    (void)err;
+void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
+                     const int64_t *ibase, const int64_t *cbase, int64_t nitems, int kper,
+                     ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_sym_chunk<256>, dim3((unsigned)nitems), dim3(256), 0, s, prods, items,
-                       nh, ibase, aoff, soff, split, chunk_cnt, row_nnz);
+    hipLaunchKernelGGL(k_sym_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
+                       items, item_of, ibase, cbase, nitems, kper, desc);
 }
 
-void launch_num_chunk(const ProdDev *prods, const uint64_t *ditems, int64_t nd,
-                      const int64_t *dbase, int64_t nitems, const int32_t *hslot,
-                      const int64_t *ibase, const int64_t *aoff, const int64_t *soff,
-                      const int32_t *split, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                      const int64_t *rptv, int *err, hipStream_t s) {
-    (void)aoff;
+void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t *item_of,
+                     const int64_t *dbase, int64_t nitems, int kper, const int32_t *hslot,
+                     const int64_t *cbase, const int64_t *rptv, ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL((k_num_chunk<512, kMaxChunkCols>), dim3((unsigned)nitems), dim3(512), 0,
-                       s, prods, ditems, nd, dbase, hslot, ibase, soff, split, chunk_cnt,
-                       chunk_pos, rptv, err);
+    hipLaunchKernelGGL(k_num_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
+                       ditems, item_of, dbase, nitems, kper, hslot, cbase, rptv, desc);
+}
+
+template <bool FAST>
+static void sym_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+                             int64_t nitems, int kper, int64_t *chunk_cnt, int64_t *row_nnz,
+                             hipStream_t s) {
+    const dim3 grid((unsigned)nitems);
+    if (wmax <= 4096)
+        hipLaunchKernelGGL((k_sym_chunk<256, 4096, FAST>), grid, dim3(256), 0, s, prods, desc,
+                           kper, chunk_cnt, row_nnz);
+    else if (wmax <= 8192)
+        hipLaunchKernelGGL((k_sym_chunk<256, 8192, FAST>), grid, dim3(256), 0, s, prods, desc,
+                           kper, chunk_cnt, row_nnz);
+    else
+        hipLaunchKernelGGL((k_sym_chunk<256, kMaxChunkCols, FAST>), grid, dim3(256), 0, s, prods,
+                           desc, kper, chunk_cnt, row_nnz);
+}
+
+void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
+                      int64_t nitems, int kper, int64_t *chunk_cnt, int64_t *row_nnz,
+                      hipStream_t s) {
+    if (nitems <= 0) return;
+    if (fast) sym_chunk_launch<true>(wmax, prods, desc, nitems, kper, chunk_cnt, row_nnz, s);
+    else sym_chunk_launch<false>(wmax, prods, desc, nitems, kper, chunk_cnt, row_nnz, s);
+}
+
+template <bool FAST>
+static void num_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+                             int64_t nitems, int kper, const int64_t *chunk_cnt,
+                             const int64_t *chunk_pos, int *err, hipStream_t s) {
+    const dim3 grid((unsigned)nitems);
+    if (wmax <= 4096)
+        hipLaunchKernelGGL((k_num_chunk<256, 4096, FAST>), grid, dim3(256), 0, s, prods, desc,
+                           kper, chunk_cnt, chunk_pos, err);
+    else if (wmax <= 8192)
+        hipLaunchKernelGGL((k_num_chunk<256, 8192, FAST>), grid, dim3(256), 0, s, prods, desc,
+                           kper, chunk_cnt, chunk_pos, err);
+    else
+        hipLaunchKernelGGL((k_num_chunk<512, kMaxChunkCols, FAST>), grid, dim3(512), 0, s,
+                           prods, desc, kper, chunk_cnt, chunk_pos, err);
+}
+
+void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
+                      int64_t nitems, int kper, const int64_t *chunk_cnt,
+                      const int64_t *chunk_pos, int *err, hipStream_t s) {
+    if (nitems <= 0) return;
+    if (fast) num_chunk_launch<true>(wmax, prods, desc, nitems, kper, chunk_cnt, chunk_pos, err, s);
+    else num_chunk_launch<false>(wmax, prods, desc, nitems, kper, chunk_cnt, chunk_pos, err, s);
 }
 
 }  // namespace spg

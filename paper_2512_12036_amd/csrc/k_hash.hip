@@ -25,7 +25,7 @@
 //    sorted by column (rank sort in the group kernels, as the paper's
 //    comparison-based ranking; bitonic sort in LDS in the block kernels, as
 //    paper Algorithm 5) and written to the row's segment of C.
-#include "common.hpp"
+#include "dev.hpp"
 
 namespace spg {
 
@@ -71,73 +71,27 @@ __device__ __forceinline__ int ceil_log2(int64_t x) {
     return l;
 }
 
-// Largest o in [0, n) with e[o] <= q, e non-decreasing, e[0] = 0 <= q.
-template <typename T>
-__device__ __forceinline__ int lds_owner(const T *e, int n, T q) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (e[mid] <= q) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-template <int NT>
-__device__ __forceinline__ int block_excl_scan_i32(int v, int *wsum, int &total) {
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    int before = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        int x = wsum[i];
-        if (i < w) before += x;
-        tot += x;
-    }
-    __syncthreads();
-    total = tot;
-    return before + incl - v;
-}
-
-template <int NT>
-__device__ __forceinline__ int block_sum_i32(int v, int *wsum) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) wsum[w] = v;
-    __syncthreads();
-    int tot = 0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) tot += wsum[i];
-    __syncthreads();
-    return tot;
-}
-
 // ---------------------------------------------------------------------------
 // Group kernels: G lanes per row.
 // ---------------------------------------------------------------------------
 // Walks every intermediate product of row i of P with the G lanes of a group
-// and calls f(col_b, a_value, b_index) for each.  Group-uniform control flow.
-template <int G, bool VALUES, typename F>
+// and calls f(col_b, a_value, b_value) for each.  Group-uniform control flow;
+// U windows of G products per round so that U gathers per lane are in flight.
+template <int G, int U, bool VALUES, typename F>
 __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int lane, F &&f) {
-    const int64_t a0 = P.rptA[i], a1 = P.rptA[i + 1];
+    const int64_t a0 = gld(P.rptA + i), a1 = gld(P.rptA + i + 1);
+    const int32_t *colB = P.colB;
+    const float *valB = P.valB;
     for (int64_t jb = a0; jb < a1; jb += G) {
         const int64_t j = jb + lane;
         int64_t s = 0;
         int len = 0;
         float a = 0.f;
         if (j < a1) {
-            const int k = P.colA[j];
-            s = P.rptB[k];
-            len = (int)(P.rptB[k + 1] - s);
-            if (VALUES) a = P.valA[j];
+            const int k = gld(P.colA + j);
+            s = gld(P.rptB + k);
+            len = (int)(gld(P.rptB + k + 1) - s);
+            if (VALUES) a = gld(P.valA + j);
         }
         int incl = len;
 #pragma unroll
@@ -147,19 +101,33 @@ __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int 
         }
         const int total = __shfl(incl, G - 1, G);
         const int excl = incl - len;
-        for (int qb = 0; qb < total; qb += G) {
-            const int q = qb + lane;
-            int o = 0;
+        for (int qb = 0; qb < total; qb += G * U) {
+            int cc[U];
+            float aa[U], vv[U];
+            bool ok[U];
 #pragma unroll
-            for (int step = G / 2; step > 0; step >>= 1) {
-                int v = __shfl(excl, o + step, G);
-                if (v <= q) o += step;
+            for (int u = 0; u < U; ++u) {
+                const int q = qb + u * G + lane;
+                int o = 0;
+#pragma unroll
+                for (int step = G / 2; step > 0; step >>= 1) {
+                    int v = __shfl(excl, o + step, G);
+                    if (v <= q) o += step;
+                }
+                const int64_t so = __shfl(s, o, G);
+                const int eo = __shfl(excl, o, G);
+                aa[u] = VALUES ? __shfl(a, o, G) : 0.f;
+                ok[u] = q < total;
+                cc[u] = 0;
+                vv[u] = 0.f;
+                if (ok[u]) {
+                    cc[u] = gld(colB + so + (q - eo));
+                    if (VALUES) vv[u] = gld(valB + so + (q - eo));
+                }
             }
-            const int64_t so = __shfl(s, o, G);
-            const int eo = __shfl(excl, o, G);
-            float ao = 0.f;
-            if (VALUES) ao = __shfl(a, o, G);
-            if (q < total) f(P.colB[so + (q - eo)], ao, so + (q - eo));
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) f(cc[u], aa[u], vv[u]);
         }
     }
 }
@@ -181,7 +149,7 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     const int64_t i = item_row(e);
     int *tab = keys + gi * T;
     int cnt = 0;
-    group_products<G, false>(P, i, lane, [&](int c, float, int64_t) {
+    group_products<G, 2, false>(P, i, lane, [&](int c, float, float) {
         cnt += lds_insert(tab, T - 1, LOG2T, c, err);
     });
 #pragma unroll
@@ -208,8 +176,8 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     if (active) {
         e = items[it];
         const ProdDev &P = prods[item_prod(e)];
-        group_products<G, true>(P, item_row(e), lane, [&](int c, float a, int64_t t) {
-            lds_add(tab, tv, T - 1, LOG2T, c, a * P.valB[t], err);
+        group_products<G, 2, true>(P, item_row(e), lane, [&](int c, float a, float b) {
+            lds_add(tab, tv, T - 1, LOG2T, c, a * b, err);
         });
     }
     __syncthreads();
@@ -256,8 +224,8 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         if (kk[r] != kEmptyKey && rank[r] < expect) {
-            P.colC[base + rank[r]] = kk[r];
-            P.valC[base + rank[r]] = vv[r];
+            gst(P.colC + base + rank[r], kk[r]);
+            gst(P.valC + base + rank[r], vv[r]);
         }
     }
 }
@@ -265,33 +233,31 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
 // ---------------------------------------------------------------------------
 // Block kernels: one row per workgroup.
 // ---------------------------------------------------------------------------
-template <int WG, bool VALUES, typename F>
+template <int WG, int U, bool VALUES, typename F>
 __device__ __forceinline__ void block_products(const ProdDev &P, int64_t i, int64_t *st_s,
                                                int *st_e, float *st_a, int *wsum, F &&f) {
-    const int64_t a0 = P.rptA[i], a1 = P.rptA[i + 1];
+    const int64_t a0 = gld(P.rptA + i), a1 = gld(P.rptA + i + 1);
     for (int64_t jb = a0; jb < a1; jb += WG) {
         const int64_t j = jb + threadIdx.x;
         int64_t s = 0;
         int len = 0;
         float a = 0.f;
         if (j < a1) {
-            const int k = P.colA[j];
-            s = P.rptB[k];
-            len = (int)(P.rptB[k + 1] - s);
-            if (VALUES) a = P.valA[j];
+            const int k = gld(P.colA + j);
+            s = gld(P.rptB + k);
+            len = (int)(gld(P.rptB + k + 1) - s);
+            if (VALUES) a = gld(P.valA + j);
         }
         int total;
-        const int excl = block_excl_scan_i32<WG>(len, wsum, total);
+        const int excl = block_excl_scan<WG, int>(len, wsum, total);
         st_s[threadIdx.x] = s;
         st_e[threadIdx.x] = excl;
+        if (threadIdx.x == 0) st_e[WG] = total;
         if (VALUES) st_a[threadIdx.x] = a;
         __syncthreads();
         const int nv = (int)((a1 - jb) < WG ? (a1 - jb) : WG);
-        for (int q = threadIdx.x; q < total; q += WG) {
-            const int o = lds_owner<int>(st_e, nv, q);
-            const int64_t t = st_s[o] + (q - st_e[o]);
-            f(P.colB[t], VALUES ? st_a[o] : 0.f, t);
-        }
+        staged_products<WG, U, VALUES, int, int64_t>(st_s, st_e, st_a, nv, total, P.colB, P.valB,
+                                                     f);
         __syncthreads();
     }
 }
@@ -304,7 +270,7 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
                                                    int *__restrict__ err) {
     __shared__ int keys[TMAX];
     __shared__ int64_t st_s[WG];
-    __shared__ int st_e[WG];
+    __shared__ int st_e[WG + 1];
     __shared__ int wsum[WG / 64];
     const uint64_t e = items[blockIdx.x];
     const ProdDev &P = prods[item_prod(e)];
@@ -322,11 +288,11 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
     for (int s = threadIdx.x; s < T; s += WG) keys[s] = kEmptyKey;
     __syncthreads();
     int cnt = 0;
-    block_products<WG, false>(P, i, st_s, st_e, (float *)nullptr, wsum,
-                              [&](int c, float, int64_t) {
-                                  cnt += lds_insert(keys, T - 1, log2T, c, err);
-                              });
-    const int tot = block_sum_i32<WG>(cnt, wsum);
+    block_products<WG, 8, false>(P, i, st_s, st_e, (float *)nullptr, wsum,
+                                 [&](int c, float, float) {
+                                     cnt += lds_insert(keys, T - 1, log2T, c, err);
+                                 });
+    const int tot = block_sum<WG, int>(cnt, wsum);
     if (threadIdx.x == 0) row_nnz[g] = tot;
 }
 
@@ -338,7 +304,7 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     __shared__ int keys[TMAX];
     __shared__ float vals[TMAX];
     __shared__ int64_t st_s[WG];
-    __shared__ int st_e[WG];
+    __shared__ int st_e[WG + 1];
     __shared__ float st_a[WG];
     __shared__ int wsum[WG / 64];
     __shared__ int fill;
@@ -358,8 +324,8 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     for (int s = threadIdx.x; s < T; s += WG) { keys[s] = kEmptyKey; vals[s] = 0.f; }
     if (threadIdx.x == 0) fill = 0;
     __syncthreads();
-    block_products<WG, true>(P, i, st_s, st_e, st_a, wsum, [&](int c, float a, int64_t t) {
-        lds_add(keys, vals, T - 1, log2T, c, a * P.valB[t], err);
+    block_products<WG, 8, true>(P, i, st_s, st_e, st_a, wsum, [&](int c, float a, float b) {
+        lds_add(keys, vals, T - 1, log2T, c, a * b, err);
     });
     // gather occupied slots to the front, in place, one WG-wide round at a time
     const int lane = threadIdx.x & 63;
@@ -410,8 +376,8 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     const int64_t base = rptv[g] - rptv[P.row_base];
     const int nout = (int)(n < expect ? n : expect);
     for (int q = threadIdx.x; q < nout; q += WG) {
-        P.colC[base + q] = keys[q];
-        P.valC[base + q] = vals[q];
+        gst(P.colC + base + q, keys[q]);
+        gst(P.valC + base + q, vals[q]);
     }
 }
 
@@ -461,26 +427,51 @@ void launch_num_group(int g, const ProdDev *prods, const uint64_t *items, int64_
     }
 }
 
-void launch_sym_block(int g, const ProdDev *prods, const uint64_t *items, const int64_t *ipv,
-                      int64_t count, int64_t *row_nnz, int *err, hipStream_t s) {
-    if (count <= 0) return;
-    if (g == 5)
-        hipLaunchKernelGGL((k_sym_block<256, 8192>), dim3((unsigned)count), dim3(256), 0, s,
-                           prods, items, ipv, row_nnz, err);
-    else
-        hipLaunchKernelGGL((k_sym_block<512, 32768>), dim3((unsigned)count), dim3(512), 0, s,
-                           prods, items, ipv, row_nnz, err);
+static int table_for(int64_t upper, int lo, int hi) {
+    int t = lo;
+    while (t < hi && (int64_t)t < 2 * upper) t <<= 1;
+    return t;
 }
 
-void launch_num_block(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
-                      const int64_t *rptv, int *err, hipStream_t s) {
+// LDS tables are sized to the group's upper bound (twice the largest key,
+// a power of two), so a group tuned to small rows keeps a high occupancy.
+void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
+                      const int64_t *ipv, int64_t count, int64_t *row_nnz, int *err,
+                      hipStream_t s) {
     if (count <= 0) return;
-    if (g == 5)
-        hipLaunchKernelGGL((k_num_block<256, 4096>), dim3((unsigned)count), dim3(256), 0, s,
-                           prods, items, rptv, err);
-    else
-        hipLaunchKernelGGL((k_num_block<512, 16384>), dim3((unsigned)count), dim3(512), 0, s,
-                           prods, items, rptv, err);
+    const dim3 grid((unsigned)count);
+    if (g == 5) {
+        switch (table_for(upper, 2048, 8192)) {
+            case 2048: hipLaunchKernelGGL((k_sym_block<256, 2048>), grid, dim3(256), 0, s, prods, items, ipv, row_nnz, err); break;
+            case 4096: hipLaunchKernelGGL((k_sym_block<256, 4096>), grid, dim3(256), 0, s, prods, items, ipv, row_nnz, err); break;
+            default: hipLaunchKernelGGL((k_sym_block<256, 8192>), grid, dim3(256), 0, s, prods, items, ipv, row_nnz, err); break;
+        }
+    } else {
+        switch (table_for(upper, 8192, 32768)) {
+            case 8192: hipLaunchKernelGGL((k_sym_block<512, 8192>), grid, dim3(512), 0, s, prods, items, ipv, row_nnz, err); break;
+            case 16384: hipLaunchKernelGGL((k_sym_block<512, 16384>), grid, dim3(512), 0, s, prods, items, ipv, row_nnz, err); break;
+            default: hipLaunchKernelGGL((k_sym_block<512, 32768>), grid, dim3(512), 0, s, prods, items, ipv, row_nnz, err); break;
+        }
+    }
+}
+
+void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
+                      int64_t count, const int64_t *rptv, int *err, hipStream_t s) {
+    if (count <= 0) return;
+    const dim3 grid((unsigned)count);
+    if (g == 5) {
+        switch (table_for(upper, 1024, 4096)) {
+            case 1024: hipLaunchKernelGGL((k_num_block<256, 1024>), grid, dim3(256), 0, s, prods, items, rptv, err); break;
+            case 2048: hipLaunchKernelGGL((k_num_block<256, 2048>), grid, dim3(256), 0, s, prods, items, rptv, err); break;
+            default: hipLaunchKernelGGL((k_num_block<256, 4096>), grid, dim3(256), 0, s, prods, items, rptv, err); break;
+        }
+    } else {
+        switch (table_for(upper, 4096, 16384)) {
+            case 4096: hipLaunchKernelGGL((k_num_block<512, 4096>), grid, dim3(512), 0, s, prods, items, rptv, err); break;
+            case 8192: hipLaunchKernelGGL((k_num_block<512, 8192>), grid, dim3(512), 0, s, prods, items, rptv, err); break;
+            default: hipLaunchKernelGGL((k_num_block<512, 16384>), grid, dim3(512), 0, s, prods, items, rptv, err); break;
+        }
+    }
 }
 
 }  // namespace spg

@@ -31,7 +31,8 @@ class CsrDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("sym_upper", _I64 * (NGROUPS - 1)), ("num_upper", _I64 * (NGROUPS - 1)),
                 ("chunk_cols", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("profile", ctypes.c_int32), ("chunks_per_item", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Info(ctypes.Structure):
@@ -116,7 +117,7 @@ def default_options() -> Options:
 
 
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
-                 profile=None) -> Options:
+                 profile=None, chunks_per_item=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -130,6 +131,8 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.validate = int(validate)
     if profile is not None:
         o.profile = int(profile)
+    if chunks_per_item is not None:
+        o.chunks_per_item = int(chunks_per_item)
     return o
 
 
@@ -348,6 +351,7 @@ def matmul(A: DeviceCsr, B: DeviceCsr, options: Options | None = None, stream=No
         plan.symbolic()
         cols, vals = plan.allocate_outputs()
         plan.numeric(cols, vals)
+        plan.sync()  # surfaces a kernel-raised error flag
         return plan.results(cols, vals)[0]
     finally:
         plan.free()
@@ -360,6 +364,7 @@ def matmul_batch(As, Bs, options: Options | None = None, stream=None):
         plan.symbolic()
         cols, vals = plan.allocate_outputs()
         plan.numeric(cols, vals)
+        plan.sync()
         return plan.results(cols, vals)
     finally:
         plan.free()

@@ -12,7 +12,7 @@ SYM_CAP = [0, 32, 64, 128, 256, 4096, 16384]
 NUM_CAP = [0, 32, 64, 128, 256, 2048, 8192]
 
 
-def forced_options(group: int, chunk_cols: int | None = None):
+def forced_options(group: int, chunk_cols: int | None = None, chunks_per_item: int | None = None):
     """Options that send every row whose key fits to `group` (1..7)."""
     sym = [0] * 7
     num = [0] * 7
@@ -25,7 +25,7 @@ def forced_options(group: int, chunk_cols: int | None = None):
     for g in range(1, 7):
         sym[g] = max(sym[g], sym[g - 1])
         num[g] = max(num[g], num[g - 1])
-    return spgemm.make_options(sym, num, chunk_cols=chunk_cols)
+    return spgemm.make_options(sym, num, chunk_cols=chunk_cols, chunks_per_item=chunks_per_item)
 
 
 def log(msg):

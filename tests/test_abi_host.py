@@ -59,7 +59,7 @@ def test_default_options_are_consistent():
     assert sym[0] == 0 and num[0] == 0
     assert sym == sorted(sym) and num == sorted(num)
     assert sym[6] <= num[6]
-    assert o.chunk_cols % 64 == 0 and 64 <= o.chunk_cols <= 32768
+    assert o.chunk_cols % 64 == 0 and 64 <= o.chunk_cols <= 16384
 
 
 def _create(a, b, o):
@@ -72,7 +72,7 @@ def _create(a, b, o):
 
 
 @pytest.mark.parametrize("field,value", [("chunk_cols", 100), ("chunk_cols", 0),
-                                         ("chunk_cols", 65536), ("validate", 7)])
+                                         ("chunk_cols", 32768), ("validate", 7)])
 def test_bad_options_rejected(field, value):
     o = spgemm.default_options()
     setattr(o, field, value)
@@ -121,3 +121,10 @@ def test_product_path_fails_loudly_without_library(tmp_path):
         mod.load(str(tmp_path / "missing.so"))
     import importlib
     importlib.reload(spgemm)
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    lib = os.path.join(ROOT, "paper_2512_12036_amd", "libspgemm.so")
+    out = subprocess.check_output(["nm", "-D", "--undefined-only", lib]).decode()
+    missing = [l for l in out.splitlines() if "spg" in l]
+    assert not missing, missing

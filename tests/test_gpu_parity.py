@@ -57,6 +57,15 @@ def test_chunk_widths(chunk_cols):
     run_and_compare(a, a, options=forced_options(7, chunk_cols), label=f"chunk{chunk_cols}")
 
 
+@pytest.mark.parametrize("kper", [1, 2, 4, 8])
+def test_chunks_per_item(kper):
+    a = gen.rmat(12, 16, seed=10)
+    run_and_compare(a, a, options=forced_options(7, 256, kper), label=f"kper{kper}")
+    b = gen.shuffle_rows(a, 7)
+    run_and_compare(a, b, options=forced_options(7, 512, kper), b_sorted=False,
+                    label=f"kper{kper}-unsorted")
+
+
 def test_chunk_unsorted_b():
     a = gen.rmat(11, 16, seed=12)
     b = gen.shuffle_rows(a, 3)
