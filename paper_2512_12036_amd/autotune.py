@@ -27,12 +27,12 @@ def candidates(quick: bool = False):
     """Candidate (chunk_cols, sym_upper, num_upper, chunks_per_item)."""
     small = [0, 32, 64, 128, 256]
     out = []
-    for cc, top, kper in itertools.product([4096, 8192, 16384], [4096, 8192], [1, 8]):
+    for cc, top, kper in itertools.product([1024, 2048, 4096, 8192, 16384], [4096, 8192], [1]):
         sym = small + [4096, top]
         num = small + [2048, top]
         out.append((cc, sym, num, kper))
     if quick:
-        out = [c for c in out if c[0] == 8192]
+        out = [c for c in out if c[0] in (2048, 8192)]
     return out
 
 

@@ -55,11 +55,15 @@ struct spgemm_plan {
     size_t scan_tmp_bytes = 0;
 
     // chunk group (symbolic group 7)
-    int64_t nh = 0, h_items = 0;
+    int64_t nh = 0, h_items = 0, h_split = 0;
     int64_t *nchv = nullptr, *ibase = nullptr, *cbase = nullptr, *chunk_cnt = nullptr;
     int64_t *chunk_pos = nullptr;
     int32_t *hitem_row = nullptr;
     ChunkDesc *sdesc = nullptr;
+    int64_t *slen = nullptr, *sbase = nullptr;  // sub-range tables (fast path)
+    uint32_t *sabs = nullptr;
+    uint32_t *sbits = nullptr;  // per-chunk structure bitmaps from the symbolic phase
+    int wpc = 0;                // bitmap words per chunk
     // numeric group 7
     int64_t nd = 0, d_items = 0;
     int64_t *dnchv = nullptr, *dbase = nullptr;
@@ -363,6 +367,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         p->ip_total += (int64_t)ps[q].ip_sum;
         p->ip_max = std::max<int64_t>(p->ip_max, (int64_t)ps[q].ip_max);
         p->nh += (int64_t)ps[q].h_rows;
+        p->h_split += (int64_t)ps[q].h_split;
         p->h_items += (int64_t)ps[q].h_items;
         if (p->hprods[q].b_sorted == 2) p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
         if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
@@ -383,6 +388,8 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         ST_TRY(dalloc(p, &p->chunk_pos, p->h_items + 1));
         ST_TRY(dalloc(p, &p->hitem_row, nitems));
         ST_TRY(dalloc(p, &p->sdesc, nitems));
+        p->wpc = (p->wmax + 31) / 32;
+        ST_TRY(dalloc(p, &p->sbits, (size_t)p->h_items * p->wpc));
         TimeScope ts(p, "plan.split");
         bool reupload = false;
         for (int q = 0; q < nprod; ++q) {
@@ -395,6 +402,16 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
             reupload = true;
         }
         if (reupload) ST_TRY(upload_descriptors(p));
+        if (p->fast) {
+            ST_TRY(dalloc(p, &p->slen, nh));
+            ST_TRY(dalloc(p, &p->sbase, nh + 1));
+            ST_TRY(dalloc(p, &p->sabs, p->h_split));
+            launch_row_splitlen(p->dprods, hitems, nh, p->slen, p->stream);
+            ST_TRY(launch_check());
+            ST_TRY(scan(p, p->slen, p->sbase, nh));
+            launch_sabs(p->dprods, hitems, nh, p->sbase, p->sabs, p->stream);
+            ST_TRY(launch_check());
+        }
         launch_nch_of(p->dprods, hitems, nh, 1, p->nchv, p->stream);
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->nchv, p->cbase, nh));
@@ -402,7 +419,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->nchv, p->ibase, nh));
         launch_expand(p->ibase, nh, p->hitem_row, p->stream);
-        launch_sym_desc(p->dprods, hitems, p->hitem_row, p->ibase, p->cbase, nitems,
+        launch_sym_desc(p->dprods, hitems, p->hitem_row, p->ibase, p->cbase, p->sbase, nitems,
                         p->opt.chunks_per_item, p->sdesc, p->stream);
         ST_TRY(launch_check());
     }
@@ -463,8 +480,8 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     }
     if (p->nh > 0) {
         TimeScope ts(p, sym_names[7]);
-        launch_sym_chunk(p->wmax, p->fast, p->dprods, p->sdesc, p->h_items / p->opt.chunks_per_item, p->opt.chunks_per_item,
-                         p->chunk_cnt, p->row_nnz, st);
+        launch_sym_chunk(p->wmax, p->fast, p->dprods, p->sdesc, p->sabs, p->h_items / p->opt.chunks_per_item, p->opt.chunks_per_item,
+                         p->chunk_cnt, p->row_nnz, p->sbits, p->wpc, st);
     }
     ST_TRY(launch_check());
     {
@@ -524,7 +541,8 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
         ST_TRY(scan(p, p->dnchv, p->dbase, p->nd));
         launch_expand(p->dbase, p->nd, p->ditem_row, st);
         launch_num_desc(p->dprods, ditems, p->ditem_row, p->dbase, nitems,
-                        p->opt.chunks_per_item, p->hslot, p->cbase, p->rptv, p->ndesc, st);
+                        p->opt.chunks_per_item, p->hslot, p->cbase, p->sbase, p->rptv, p->ndesc,
+                        st);
         ST_TRY(launch_check());
     }
     p->state = 2;
@@ -551,8 +569,9 @@ spgemm_status numeric_impl(spgemm_plan *p) {
     }
     if (p->nd > 0) {
         TimeScope ts(p, num_names[7]);
-        launch_num_chunk(p->wmax, p->fast, p->dprods, p->ndesc, p->d_items / p->opt.chunks_per_item,
-                         p->opt.chunks_per_item, p->chunk_cnt, p->chunk_pos, p->flags, st);
+        launch_num_chunk(p->wmax, p->fast, p->dprods, p->ndesc, p->sabs, p->d_items / p->opt.chunks_per_item,
+                         p->opt.chunks_per_item, p->chunk_cnt, p->chunk_pos, p->sbits,
+                         p->wpc, p->flags, st);
     }
     return launch_check();
 }

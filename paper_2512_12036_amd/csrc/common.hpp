@@ -47,6 +47,7 @@ struct ChunkDesc {
     int64_t a0;      // first A nonzero of the row
     int64_t out0;    // symbolic: batch row index; numeric: output offset of the row in C_p
     int64_t slot0;   // chunk-count slot of the row's chunk 0
+    int64_t sb;      // start of the row's sub-range table (fast path), else -1
     int32_t alen;    // A nonzeros of the row
     int32_t q;       // first chunk of the item
     int32_t prod;    // product index
@@ -123,12 +124,17 @@ void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int
 void launch_nch_of(const ProdDev *prods, const uint64_t *items, int64_t n, int div,
                    int64_t *nchv, hipStream_t s);
 void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s);
+void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *len,
+                         hipStream_t s);
+void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *sbase,
+                 uint32_t *sabs, hipStream_t s);
 void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
-                     const int64_t *ibase, const int64_t *cbase, int64_t nitems, int kper,
-                     ChunkDesc *desc, hipStream_t s);
+                     const int64_t *ibase, const int64_t *cbase, const int64_t *sbase,
+                     int64_t nitems, int kper, ChunkDesc *desc, hipStream_t s);
 void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t *item_of,
                      const int64_t *dbase, int64_t nitems, int kper, const int32_t *hslot,
-                     const int64_t *cbase, const int64_t *rptv, ChunkDesc *desc, hipStream_t s);
+                     const int64_t *cbase, const int64_t *sbase, const int64_t *rptv,
+                     ChunkDesc *desc, hipStream_t s);
 
 void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, int64_t *row_nnz, int *err, hipStream_t s);
@@ -136,15 +142,16 @@ void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t
                       const int64_t *ipv, int64_t count, int64_t *row_nnz, int *err,
                       hipStream_t s);
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
-                      int64_t nitems, int kper, int64_t *chunk_cnt, int64_t *row_nnz,
-                      hipStream_t s);
+                      const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
+                      int64_t *row_nnz, uint32_t *sbits, int wpc, hipStream_t s);
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
 void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
-                      int64_t nitems, int kper, const int64_t *chunk_cnt,
-                      const int64_t *chunk_pos, int *err, hipStream_t s);
+                      const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
+                      const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int *err,
+                      hipStream_t s);
 
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,

@@ -6,8 +6,9 @@
 // chunk) pair gets one workgroup with an LDS-resident structure covering the
 // chunk's columns directly (no hashing, no probing):
 //   * symbolic: a W-bit bitmap; the chunk's distinct count is its popcount;
-//   * numeric : a W-float dense accumulator plus the W-bit occupancy bitmap
-//     (so explicit zeros from cancellation are kept); the chunk is emitted in
+//   * numeric : a W-float dense accumulator; the chunk's structure is the
+//     bitmap the symbolic phase stored (so explicit zeros from cancellation
+//     are kept and no occupancy atomics are needed); the chunk is emitted in
 //     column order straight from the bitmap, so these rows need no sort.
 //
 // Latency: a workgroup handles K chunks of one row (an item) and keeps the
@@ -61,6 +62,45 @@ __global__ void k_expand(const int64_t *__restrict__ base, int64_t n, int32_t *_
     for (int64_t x = base[r]; x < base[r + 1]; ++x) out[x] = (int32_t)r;
 }
 
+// len[h] = A nonzeros of row h times (nch + 1): size of its sub-range table.
+__global__ void k_row_splitlen(const ProdDev *__restrict__ prods,
+                               const uint64_t *__restrict__ items, int64_t nh,
+                               int64_t *__restrict__ len) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= nh) return;
+    const uint64_t e = items[h];
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t i = item_row(e);
+    len[h] = (P.rptA[i + 1] - P.rptA[i]) * (int64_t)(P.nch + 1);
+}
+
+// Sub-range table of one group-7 row (fast path: sorted B, < 2^30 entries):
+// sabs[sbase[h] + c * alen + j] = absolute position in B of the first entry of
+// B row colA[a0 + j] with column >= c * W, for c = 0..nch.  Chunk c of the row
+// then reads, for every nonzero j, the range [sabs[c][j], sabs[c+1][j]) with
+// two coalesced loads.
+__global__ __launch_bounds__(256) void k_sabs(const ProdDev *__restrict__ prods,
+                                               const uint64_t *__restrict__ items, int64_t nh,
+                                               const int64_t *__restrict__ sbase,
+                                               uint32_t *__restrict__ sabs) {
+    const int64_t h = blockIdx.x;
+    const uint64_t e = items[h];
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t i = item_row(e);
+    const int64_t a0 = P.rptA[i];
+    const int64_t alen = P.rptA[i + 1] - a0;
+    const int per = P.nch + 1;
+    uint32_t *out = sabs + sbase[h];
+    for (int64_t jb = 0; jb < alen; jb += 256) {
+        const int64_t j = jb + threadIdx.x;
+        if (j >= alen) break;
+        const int k = gld(P.colA + a0 + j);
+        const int64_t b0 = gld(P.rptB + k);
+        const int32_t *bs = P.bsplit + (int64_t)k * per;
+        for (int c = 0; c < per; ++c) out[(int64_t)c * alen + j] = (uint32_t)(b0 + gld(bs + c));
+    }
+}
+
 // nchv[r] = chunks of row r divided by div (div = 1: chunks, div = K: items).
 __global__ void k_nch_of(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                          int64_t n, int div, int64_t *__restrict__ nchv) {
@@ -84,7 +124,8 @@ __device__ __forceinline__ int item_q(int64_t it, int64_t base, int64_t row, int
 // of the row.
 __global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                            const int32_t *__restrict__ item_of, const int64_t *__restrict__ ibase,
-                           const int64_t *__restrict__ cbase, int64_t nitems, int kper,
+                           const int64_t *__restrict__ cbase,
+                           const int64_t *__restrict__ sbase, int64_t nitems, int kper,
                            ChunkDesc *__restrict__ desc) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
@@ -100,6 +141,7 @@ __global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__
     d.q = item_q(it, ibase[h], h, P.nch / kper);
     d.prod = p;
     d.slot0 = cbase[h];
+    d.sb = sbase ? sbase[h] : -1;
     desc[it] = d;
 }
 
@@ -107,8 +149,8 @@ __global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__
 __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ ditems,
                            const int32_t *__restrict__ item_of, const int64_t *__restrict__ dbase,
                            int64_t nitems, int kper, const int32_t *__restrict__ hslot,
-                           const int64_t *__restrict__ cbase, const int64_t *__restrict__ rptv,
-                           ChunkDesc *__restrict__ desc) {
+                           const int64_t *__restrict__ cbase, const int64_t *__restrict__ sbase,
+                           const int64_t *__restrict__ rptv, ChunkDesc *__restrict__ desc) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
     const int64_t dr = item_of[it];
@@ -123,16 +165,12 @@ __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__
     d.out0 = rptv[g] - rptv[P.row_base];
     d.q = item_q(it, dbase[dr], dr, P.nch / kper);
     d.prod = p;
-    d.slot0 = cbase[hslot[g]];
+    const int64_t h = hslot[g];
+    d.slot0 = cbase[h];
+    d.sb = sbase ? sbase[h] : -1;
     desc[it] = d;
 }
 
-// One chunk of one row: stages the chunk's sub-range of every B row named
-// by the row's A nonzeros and enumerates the products flat over the
-// workgroup.  When the row has at most WG nonzeros (`resident`), the caller
-// has already loaded them: thread t holds nonzero t as (b0, a) and the
-// chunk bounds x0/x1 of its B row; otherwise the nonzeros are loaded here in
-// batches of WG.  f(col, a_value, b_value).
 // One chunk of one row: stages the chunk's sub-range of every B row named
 // by the row's A nonzeros and enumerates the products flat over the
 // workgroup.  When the row has at most WG nonzeros (`resident`), the caller
@@ -144,10 +182,11 @@ __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__
 // Otherwise 64-bit indices, and unsorted B rows are scanned whole and
 // filtered to the chunk.  f(col, a_value, b_value).
 template <int WG, int VT, bool VALUES, bool FAST, typename F>
-__device__ __forceinline__ void chunk_pass(const ProdDev &P, int64_t a0, int64_t alen, int c,
-                                           int lo, int hi, bool resident, int64_t rb0, float ra,
-                                           int32_t rx0, int32_t rx1, void *st_s_raw,
-                                           void *st_e_raw, float *st_a, void *wsum_raw, F &&f) {
+__device__ __forceinline__ void chunk_pass(const ProdDev &P, const ChunkDesc &d, int c, int lo,
+                                           int hi, const uint32_t *sabs, bool resident,
+                                           int64_t rb0, float ra, int32_t rx0, int32_t rx1,
+                                           void *st_s_raw, void *st_e_raw, float *st_a,
+                                           void *wsum_raw, F &&f) {
     using E = typename std::conditional<FAST, int, int64_t>::type;
     using S = typename std::conditional<FAST, uint32_t, int64_t>::type;
     S *st_s = (S *)st_s_raw;
@@ -156,14 +195,20 @@ __device__ __forceinline__ void chunk_pass(const ProdDev &P, int64_t a0, int64_t
     // st_e holds WG + 1 entries; st_e[WG] = batch total
     const bool sorted = FAST || P.b_sorted == 1;
     const int64_t per = P.nch + 1;
-    const int64_t a1 = a0 + alen;
+    const int64_t a0 = d.a0, alen = d.alen, a1 = a0 + alen;
+    const uint32_t *sc = FAST ? sabs + d.sb + (int64_t)c * alen : nullptr;
     for (int64_t jb = a0; jb < a1; jb += WG) {
         const int64_t j = jb + threadIdx.x;
         int64_t s = 0;
         E len = 0;
         float a = 0.f;
         if (j < a1) {
-            if (resident) {
+            if (FAST) {
+                const uint32_t x0 = gld(sc + (j - a0)), x1 = gld(sc + alen + (j - a0));
+                if (VALUES) a = gld(P.valA + j);
+                s = x0;
+                len = (E)(x1 - x0);
+            } else if (resident) {
                 s = rb0 + rx0;
                 len = (E)(rx1 - rx0);
                 a = ra;
@@ -235,9 +280,11 @@ __device__ __forceinline__ void resident_bounds(const ProdDev &P, int64_t alen, 
 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ prods,
-                                                   const ChunkDesc *__restrict__ desc, int kper,
+                                                   const ChunkDesc *__restrict__ desc,
+                                                   const uint32_t *__restrict__ sabs, int kper,
                                                    int64_t *__restrict__ chunk_cnt,
-                                                   int64_t *__restrict__ row_nnz) {
+                                                   int64_t *__restrict__ row_nnz,
+                                                   uint32_t *__restrict__ sbits, int wpc) {
     __shared__ uint32_t bm[WMAX / 32];
     __shared__ int64_t st_s[WG];
     __shared__ int64_t st_e[WG + 1];
@@ -245,10 +292,10 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
     const ChunkDesc d = desc[blockIdx.x];
     const ProdDev &P = prods[d.prod];
     const int Q = P.nch / kper;
-    const bool resident = d.alen <= WG;
-    int k;
-    int64_t b0;
-    float a;
+    const bool resident = !FAST && d.alen <= WG;
+    int k = 0;
+    int64_t b0 = 0;
+    float a = 0.f;
     if (resident) resident_load(P, d.a0, d.alen, false, k, b0, a);
     int32_t nx0 = 0, nx1 = 0;
     if (resident) resident_bounds(P, d.alen, k, d.q, nx0, nx1);
@@ -266,16 +313,19 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
         }
         const int nwords = (hi - lo + 31) >> 5;
         __syncthreads();  // bitmap clear (first chunk) / previous count done
-        chunk_pass<WG, 8, false, FAST>(P, d.a0, d.alen, c, lo, hi, resident, b0, 0.f, x0, x1,
+        chunk_pass<WG, 8, false, FAST>(P, d, c, lo, hi, sabs, resident, b0, 0.f, x0, x1,
                                        st_s, st_e, (float *)nullptr, wsum,
                                        [&](int col, float, float) {
                                            const int rel = col - lo;
                                            atomicOr(&bm[rel >> 5], 1u << (rel & 31));
                                        });
         int64_t cnt = 0;
+        uint32_t *keep = sbits ? sbits + (d.slot0 + c) * (int64_t)wpc : nullptr;
         for (int x = threadIdx.x; x < nwords; x += WG) {
-            cnt += __popc(bm[x]);
-            bm[x] = 0u;  // clear for the next chunk
+            const uint32_t wv = bm[x];
+            cnt += __popc(wv);
+            if (keep) gst(keep + x, wv);  // the chunk's structure, reused by the numeric phase
+            bm[x] = 0u;                   // clear for the next chunk
         }
         const int64_t tot = block_sum<WG, int64_t>(cnt, wsum);
         if (threadIdx.x == 0) chunk_cnt[d.slot0 + c] = tot;
@@ -289,12 +339,13 @@ constexpr int NVT = 8;  // products per lane per round in the numeric chunk kern
 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
-                                                   const ChunkDesc *__restrict__ desc, int kper,
+                                                   const ChunkDesc *__restrict__ desc,
+                                                   const uint32_t *__restrict__ sabs, int kper,
                                                    const int64_t *__restrict__ chunk_cnt,
                                                    const int64_t *__restrict__ chunk_pos,
+                                                   const uint32_t *__restrict__ sbits, int wpc,
                                                    int *__restrict__ err) {
     __shared__ float acc[WMAX];
-    __shared__ uint32_t bm[WMAX / 32];
     __shared__ int64_t st_s[WG];
     __shared__ int64_t st_e[WG + 1];
     __shared__ float st_a[WG];
@@ -302,16 +353,15 @@ __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ pr
     const ChunkDesc d = desc[blockIdx.x];
     const ProdDev &P = prods[d.prod];
     const int Q = P.nch / kper;
-    const bool resident = d.alen <= WG;
-    int k;
-    int64_t b0;
-    float a;
+    const bool resident = !FAST && d.alen <= WG;
+    int k = 0;
+    int64_t b0 = 0;
+    float a = 0.f;
     if (resident) resident_load(P, d.a0, d.alen, true, k, b0, a);
     int32_t nx0 = 0, nx1 = 0;
     if (resident) resident_bounds(P, d.alen, k, d.q, nx0, nx1);
     // clear once; the emission clears every slot it reads
     for (int q = threadIdx.x; q < WMAX; q += WG) acc[q] = 0.f;
-    for (int q = threadIdx.x; q < WMAX / 32; q += WG) bm[q] = 0u;
     const int64_t pos0 = chunk_pos[d.slot0];
     for (int t = 0; t < kper; ++t) {
         const int c = d.q + Q * t;
@@ -327,24 +377,27 @@ __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ pr
             if (threadIdx.x == 0) atomicOr(err, kErrRow);
             return;
         }
-        __syncthreads();  // clear (first chunk) / previous emission done
-        chunk_pass<WG, NVT, true, FAST>(P, d.a0, d.alen, c, lo, hi, resident, b0, a, x0, x1,
-                                        st_s, st_e, st_a, wsum, [&](int col, float av, float bv) {
-                                            const int rel = col - lo;
-                                            atomicAdd(&acc[rel], av * bv);
-                                            atomicOr(&bm[rel >> 5], 1u << (rel & 31));
-                                        });
-        // Emission in column order: one bitmap word (32 columns) per lane, the
-        // word's output position from a block scan of the popcounts; a lane
-        // walks only its set bits, and clears the slots it reads.
+        // The chunk's structure words are fetched before the products, so their
+        // latency hides behind the gathers (one word per lane when W <= 32*WG).
         const int nwords = (width + 31) >> 5;
+        const uint32_t *bits = sbits + (d.slot0 + c) * (int64_t)wpc;
+        const uint32_t first_word = threadIdx.x < nwords ? gld(bits + threadIdx.x) : 0u;
+        __syncthreads();  // clear (first chunk) / previous emission done
+        chunk_pass<WG, NVT, true, FAST>(P, d, c, lo, hi, sabs, resident, b0, a, x0, x1, st_s,
+                                        st_e, st_a, wsum, [&](int col, float av, float bv) {
+                                            atomicAdd(&acc[col - lo], av * bv);
+                                        });
+        // Emission in column order from the chunk's structure (the symbolic
+        // phase's bitmap, so no occupancy atomics here): one word (32
+        // columns) per lane, the word's output position from a block scan of
+        // the popcounts; a lane walks only its set bits and clears the
+        // accumulator slots it reads.
         int64_t base = 0;
         for (int w0 = 0; w0 < nwords; w0 += WG) {
             const int x = w0 + threadIdx.x;
-            uint32_t word = x < nwords ? bm[x] : 0u;
+            uint32_t word = w0 == 0 ? first_word : (x < nwords ? gld(bits + x) : 0u);
             int64_t total;
             const int64_t pre = block_excl_scan<WG, int64_t>(__popc(word), wsum, total);
-            if (word) bm[x] = 0u;
             int64_t r = base + pre;
             int32_t *colC = P.colC + out0;
             float *valC = P.valC + out0;
@@ -387,67 +440,98 @@ void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s) 
 }
 
 void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
-                     const int64_t *ibase, const int64_t *cbase, int64_t nitems, int kper,
-                     ChunkDesc *desc, hipStream_t s) {
+                     const int64_t *ibase, const int64_t *cbase, const int64_t *sbase,
+                     int64_t nitems, int kper, ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_sym_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
-                       items, item_of, ibase, cbase, nitems, kper, desc);
+                       items, item_of, ibase, cbase, sbase, nitems, kper, desc);
+}
+
+void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *len,
+                         hipStream_t s) {
+    if (nh <= 0) return;
+    hipLaunchKernelGGL(k_row_splitlen, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, prods,
+                       items, nh, len);
+}
+
+void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *sbase,
+                 uint32_t *sabs, hipStream_t s) {
+    if (nh <= 0) return;
+    hipLaunchKernelGGL(k_sabs, dim3((unsigned)nh), dim3(256), 0, s, prods, items, nh, sbase,
+                       sabs);
 }
 
 void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t *item_of,
                      const int64_t *dbase, int64_t nitems, int kper, const int32_t *hslot,
-                     const int64_t *cbase, const int64_t *rptv, ChunkDesc *desc, hipStream_t s) {
+                     const int64_t *cbase, const int64_t *sbase, const int64_t *rptv,
+                     ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_num_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
-                       ditems, item_of, dbase, nitems, kper, hslot, cbase, rptv, desc);
+                       ditems, item_of, dbase, nitems, kper, hslot, cbase, sbase, rptv, desc);
 }
 
 template <bool FAST>
 static void sym_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *desc,
-                             int64_t nitems, int kper, int64_t *chunk_cnt, int64_t *row_nnz,
-                             hipStream_t s) {
+                             const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
+                             int64_t *row_nnz, uint32_t *sbits, int wpc, hipStream_t s) {
     const dim3 grid((unsigned)nitems);
-    if (wmax <= 4096)
-        hipLaunchKernelGGL((k_sym_chunk<256, 4096, FAST>), grid, dim3(256), 0, s, prods, desc,
-                           kper, chunk_cnt, row_nnz);
+    if (wmax <= 2048)
+        hipLaunchKernelGGL((k_sym_chunk<64, 2048, FAST>), grid, dim3(64), 0, s, prods, desc,
+                           sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
+    else if (wmax <= 4096)
+        hipLaunchKernelGGL((k_sym_chunk<128, 4096, FAST>), grid, dim3(128), 0, s, prods, desc,
+                           sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
     else if (wmax <= 8192)
         hipLaunchKernelGGL((k_sym_chunk<256, 8192, FAST>), grid, dim3(256), 0, s, prods, desc,
-                           kper, chunk_cnt, row_nnz);
+                           sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
     else
         hipLaunchKernelGGL((k_sym_chunk<256, kMaxChunkCols, FAST>), grid, dim3(256), 0, s, prods,
-                           desc, kper, chunk_cnt, row_nnz);
+                           desc, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
 }
 
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
-                      int64_t nitems, int kper, int64_t *chunk_cnt, int64_t *row_nnz,
-                      hipStream_t s) {
+                      const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
+                      int64_t *row_nnz, uint32_t *sbits, int wpc, hipStream_t s) {
     if (nitems <= 0) return;
-    if (fast) sym_chunk_launch<true>(wmax, prods, desc, nitems, kper, chunk_cnt, row_nnz, s);
-    else sym_chunk_launch<false>(wmax, prods, desc, nitems, kper, chunk_cnt, row_nnz, s);
+    if (fast)
+        sym_chunk_launch<true>(wmax, prods, desc, sabs, nitems, kper, chunk_cnt, row_nnz, sbits,
+                               wpc, s);
+    else
+        sym_chunk_launch<false>(wmax, prods, desc, sabs, nitems, kper, chunk_cnt, row_nnz, sbits,
+                                wpc, s);
 }
 
 template <bool FAST>
 static void num_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *desc,
-                             int64_t nitems, int kper, const int64_t *chunk_cnt,
-                             const int64_t *chunk_pos, int *err, hipStream_t s) {
+                             const uint32_t *sabs, int64_t nitems, int kper,
+                             const int64_t *chunk_cnt, const int64_t *chunk_pos,
+                             const uint32_t *sbits, int wpc, int *err, hipStream_t s) {
     const dim3 grid((unsigned)nitems);
-    if (wmax <= 4096)
-        hipLaunchKernelGGL((k_num_chunk<256, 4096, FAST>), grid, dim3(256), 0, s, prods, desc,
-                           kper, chunk_cnt, chunk_pos, err);
+    if (wmax <= 2048)
+        hipLaunchKernelGGL((k_num_chunk<64, 2048, FAST>), grid, dim3(64), 0, s, prods, desc,
+                           sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
+    else if (wmax <= 4096)
+        hipLaunchKernelGGL((k_num_chunk<128, 4096, FAST>), grid, dim3(128), 0, s, prods, desc,
+                           sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
     else if (wmax <= 8192)
         hipLaunchKernelGGL((k_num_chunk<256, 8192, FAST>), grid, dim3(256), 0, s, prods, desc,
-                           kper, chunk_cnt, chunk_pos, err);
+                           sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
     else
         hipLaunchKernelGGL((k_num_chunk<512, kMaxChunkCols, FAST>), grid, dim3(512), 0, s,
-                           prods, desc, kper, chunk_cnt, chunk_pos, err);
+                           prods, desc, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
 }
 
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
-                      int64_t nitems, int kper, const int64_t *chunk_cnt,
-                      const int64_t *chunk_pos, int *err, hipStream_t s) {
+                      const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
+                      const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int *err,
+                      hipStream_t s) {
     if (nitems <= 0) return;
-    if (fast) num_chunk_launch<true>(wmax, prods, desc, nitems, kper, chunk_cnt, chunk_pos, err, s);
-    else num_chunk_launch<false>(wmax, prods, desc, nitems, kper, chunk_cnt, chunk_pos, err, s);
+    if (fast)
+        num_chunk_launch<true>(wmax, prods, desc, sabs, nitems, kper, chunk_cnt, chunk_pos, sbits,
+                               wpc, err, s);
+    else
+        num_chunk_launch<false>(wmax, prods, desc, sabs, nitems, kper, chunk_cnt, chunk_pos,
+                                sbits, wpc, err, s);
 }
 
 }  // namespace spg
