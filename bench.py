@@ -19,6 +19,7 @@ the CPU oracle timed on a bounded row sample on this host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,6 +38,37 @@ HBM_PEAK_GBS = 8000.0
 NUM_BYTES = dict(ip=8, nnz=8, alen=24, row=24)
 SYM_BYTES = dict(ip=4, nnz=0, alen=20, row=28)
 PLAN_BYTES = dict(ip=0, nnz=0, alen=20, row=24)
+
+
+# HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes over this benchmark, scaled by what the same counters read for a plain
+# device copy of known size.  Only used while the kernel sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "num_chunk_rmat18_traffic.json")
+KERNEL_SOURCES = ["paper_2512_12036_amd/csrc/k_chunk.hip", "paper_2512_12036_amd/csrc/dev.hpp",
+                  "paper_2512_12036_amd/csrc/common.hpp"]
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(group, chunk_cols):
+    """Bytes per launch of `group` from the committed counter summary, or None
+    when there is none for this kernel, these options and these sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("group") != group or t.get("chunk_cols") != chunk_cols:
+        return None
+    if t.get("source_sha256") != kernel_source_digest():
+        return None
+    return int(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"])
 
 
 def log(msg):
@@ -92,6 +124,16 @@ def run_plain(args):
     torch.cuda.synchronize()
     opt = spgemm.make_options(profile=1)
     stream = torch.cuda.current_stream(dev)
+    if args.calib_copy_mib:
+        # a plain copy of known size: the scale for the HBM byte counters
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.rand(n, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
 
     def step():
         plan = spgemm.Plan(da, da, opt, stream)
@@ -169,7 +211,8 @@ def run_plain(args):
                    "nnz_c": info.nnz_c, "flops": flops},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, opt.chunk_cols),
                      "alg_bytes_per_launch": int(nbytes),
                      "avg_launch_ms": round(per_launch[dom], 4)},
         "numeric_phase": {"ms": round(num_ms, 3), "alg_bytes": int(num_total_bytes),
@@ -189,6 +232,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the row-block "
