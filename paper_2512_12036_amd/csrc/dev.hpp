@@ -46,6 +46,22 @@ __device__ __forceinline__ int lds_owner(const T *e, int lo, int hi, T q) {
     return lo;
 }
 
+// FP32 add into LDS through a compare-and-swap loop.  On gfx950 the LDS
+// float atomic add (ds_add_f32) retires about a third of a lane per clock per
+// CU -- some 16x below the integer LDS atomics the loop is built from -- so
+// the loop is far faster whenever retries are rare (distinct addresses in a
+// wave, the common case of hash and dense accumulators).
+__device__ __forceinline__ void lds_fadd(float *p, float v) {
+    uint32_t *q = reinterpret_cast<uint32_t *>(p);
+    uint32_t cur = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const uint32_t next = __float_as_uint(__uint_as_float(cur) + v);
+        const uint32_t prev = atomicCAS(q, cur, next);
+        if (prev == cur) return;
+        cur = prev;
+    }
+}
+
 template <int NT, typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T *wsum, T &total) {
     constexpr int NW = NT / 64;

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ pr
         __syncthreads();  // clear (first chunk) / previous emission done
         chunk_pass<WG, NVT, true, FAST>(P, d, c, lo, hi, sabs, resident, b0, a, x0, x1, st_s,
                                         st_e, st_a, wsum, [&](int col, float av, float bv) {
-                                            atomicAdd(&acc[col - lo], av * bv);
+                                            lds_fadd(&acc[col - lo], av * bv);
                                         });
         // Emission in column order from the chunk's structure (the symbolic
         // phase's bitmap, so no occupancy atomics here): one word (32

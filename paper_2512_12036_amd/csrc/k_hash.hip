@@ -50,10 +50,10 @@ __device__ __forceinline__ void lds_add(int *tab, float *vals, uint32_t mask, in
     uint32_t h = hash_slot(c, log2T);
     for (uint32_t probe = 0; probe <= mask; ++probe) {
         int cur = tab[h];
-        if (cur == c) { atomicAdd(&vals[h], v); return; }
+        if (cur == c) { lds_fadd(&vals[h], v); return; }
         if (cur == kEmptyKey) {
             int old = atomicCAS(&tab[h], kEmptyKey, c);
-            if (old == kEmptyKey || old == c) { atomicAdd(&vals[h], v); return; }
+            if (old == kEmptyKey || old == c) { lds_fadd(&vals[h], v); return; }
         }
         h = (h + 1) & mask;
     }
