@@ -115,7 +115,22 @@ typedef struct {
     /* Chunks of one group-7 row handled by one workgroup (1, 2, 4 or 8):
      * more amortises the row's staging, fewer gives more parallelism. */
     int32_t chunks_per_item;
-    int32_t reserved[4];
+    /* Launch shape of the group-7 kernels when chunks_per_item = 1 and B has
+     * sorted rows: 0 = one workgroup per (row, chunk) item; k = 1..64 = k
+     * resident workgroups per compute unit, each walking the items with the
+     * next item's inputs loaded while the current one is processed. */
+    int32_t chunk_wgs_per_cu;
+    /* Threads per workgroup of the numeric group-7 kernel for dense chunks:
+     * 0 = by chunk width (64 up to 2048 columns, 128 up to 4096, 256 up to
+     * 8192, 512 wider), else 64, 128, 256 or 512. */
+    int32_t chunk_threads;
+    /* Same for the symbolic group-7 kernel (0 = 64). */
+    int32_t sym_chunk_threads;
+    /* Numeric chunks with at most this many outputs are accumulated by rank
+     * in a compact array, one wave per chunk (0 = off, else 512, 1024 or
+     * 2048); larger chunks use the dense accumulator. */
+    int32_t num_rank_cap;
+    int32_t reserved[2];
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;

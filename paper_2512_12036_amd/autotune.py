@@ -24,15 +24,15 @@ NUM_CAP = [0, 32, 64, 128, 256, 2048, 8192]
 
 
 def candidates(quick: bool = False):
-    """Candidate (chunk_cols, sym_upper, num_upper, chunks_per_item)."""
+    """Candidate option sets (keyword arguments of spgemm.make_options)."""
     small = [0, 32, 64, 128, 256]
     out = []
-    for cc, top, kper in itertools.product([1024, 2048, 4096, 8192, 16384], [4096, 8192], [1]):
-        sym = small + [4096, top]
-        num = small + [2048, top]
-        out.append((cc, sym, num, kper))
+    for cc, cap, sthr in itertools.product([4096, 8192, 16384], [0, 512, 1024, 2048], [64, 128]):
+        out.append(dict(chunk_cols=cc, sym_upper=small + [4096, 4096],
+                        num_upper=small + [2048, 4096], chunks_per_item=1, chunk_wgs_per_cu=0,
+                        chunk_threads=0, sym_chunk_threads=sthr, num_rank_cap=cap))
     if quick:
-        out = [c for c in out if c[0] in (2048, 8192)]
+        out = [c for c in out if c["chunk_cols"] == 8192 and c["sym_chunk_threads"] == 64]
     return out
 
 
@@ -64,12 +64,12 @@ def tune(a, b=None, quick=False, log=None):
     da = spgemm.to_device(a)
     db = da if b is None else spgemm.to_device(b)
     results = []
-    for cc, sym, num, kper in candidates(quick):
-        opt = spgemm.make_options(sym, num, chunk_cols=cc, profile=1, chunks_per_item=kper)
+    for cand in candidates(quick):
+        opt = spgemm.make_options(profile=1, **cand)
         ms, groups = time_product(da, db, opt)
-        rec = {"chunk_cols": cc, "sym_upper": sym, "num_upper": num, "chunks_per_item": kper,
-               "ms": round(ms, 3),
-               "groups_ms": {k: round(v, 3) for k, v in sorted(groups.items())}}
+        rec = dict(cand)
+        rec["ms"] = round(ms, 3)
+        rec["groups_ms"] = {k: round(v, 3) for k, v in sorted(groups.items())}
         results.append(rec)
         if log:
             log(json.dumps(rec))

@@ -203,6 +203,12 @@ spgemm_status check_options(const spgemm_options &o) {
     if (o.chunks_per_item != 1 && o.chunks_per_item != 2 && o.chunks_per_item != 4 &&
         o.chunks_per_item != 8)
         return SPGEMM_EINVAL;
+    if (o.chunk_wgs_per_cu < 0 || o.chunk_wgs_per_cu > 64) return SPGEMM_EINVAL;
+    for (int t : {o.chunk_threads, o.sym_chunk_threads})
+        if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512) return SPGEMM_EINVAL;
+    if (o.num_rank_cap != 0 && o.num_rank_cap != 512 && o.num_rank_cap != 1024 &&
+        o.num_rank_cap != 2048)
+        return SPGEMM_EINVAL;
     return SPGEMM_OK;
 }
 
@@ -481,7 +487,8 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     if (p->nh > 0) {
         TimeScope ts(p, sym_names[7]);
         launch_sym_chunk(p->wmax, p->fast, p->dprods, p->sdesc, p->sabs, p->h_items / p->opt.chunks_per_item, p->opt.chunks_per_item,
-                         p->chunk_cnt, p->row_nnz, p->sbits, p->wpc, st);
+                         p->chunk_cnt, p->row_nnz, p->sbits, p->wpc, p->opt.chunk_wgs_per_cu,
+                         p->opt.sym_chunk_threads ? p->opt.sym_chunk_threads : 64, st);
     }
     ST_TRY(launch_check());
     {
@@ -568,10 +575,21 @@ spgemm_status numeric_impl(spgemm_plan *p) {
                          p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st);
     }
     if (p->nd > 0) {
-        TimeScope ts(p, num_names[7]);
-        launch_num_chunk(p->wmax, p->fast, p->dprods, p->ndesc, p->sabs, p->d_items / p->opt.chunks_per_item,
-                         p->opt.chunks_per_item, p->chunk_cnt, p->chunk_pos, p->sbits,
-                         p->wpc, p->flags, st);
+        const int kper = p->opt.chunks_per_item;
+        const bool rank = num_chunk_rank_used(p->fast, kper, p->opt.num_rank_cap);
+        {
+            TimeScope ts(p, num_names[7]);
+            launch_num_chunk(p->wmax, p->fast, p->dprods, p->ndesc, p->sabs, p->d_items / kper,
+                             kper, p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc,
+                             p->opt.chunk_wgs_per_cu, p->opt.chunk_threads,
+                             rank ? p->opt.num_rank_cap : 0, p->flags, st);
+        }
+        if (rank) {
+            TimeScope ts(p, "num.g7r");
+            launch_num_chunk_rank(p->wmax, p->dprods, p->ndesc, p->sabs, p->d_items, p->chunk_cnt,
+                                  p->chunk_pos, p->sbits, p->wpc, p->opt.num_rank_cap, p->flags,
+                                  st);
+        }
     }
     return launch_check();
 }
@@ -593,6 +611,7 @@ void spgemm_default_options(spgemm_options *opt) {
     opt->chunk_cols = 8192;
     opt->validate = 0;
     opt->chunks_per_item = 1;
+    opt->num_rank_cap = 1024;
 }
 
 spgemm_status spgemm_plan_create(spgemm_plan **out, const spgemm_csr *A, const spgemm_csr *B,

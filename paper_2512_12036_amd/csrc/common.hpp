@@ -143,15 +143,22 @@ void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t
                       hipStream_t s);
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
-                      int64_t *row_nnz, uint32_t *sbits, int wpc, hipStream_t s);
+                      int64_t *row_nnz, uint32_t *sbits, int wpc, int wgs_per_cu, int threads,
+                      hipStream_t s);
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
 void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
-                      const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int *err,
-                      hipStream_t s);
+                      const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,
+                      int threads, int rank_cap, int *err, hipStream_t s);
+// Chunks with at most rank_cap outputs (fast path, one chunk per item only).
+bool num_chunk_rank_used(bool fast, int kper, int rank_cap);
+void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+                           const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
+                           const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
+                           int *err, hipStream_t s);
 
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,

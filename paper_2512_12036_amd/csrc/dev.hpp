@@ -100,6 +100,68 @@ __device__ __forceinline__ T block_sum(T v, T *wsum) {
     return tot;
 }
 
+// Workgroup barrier that orders LDS traffic only: waits for this wave's LDS
+// operations, then meets the other waves.  Unlike __syncthreads it does not
+// drain outstanding global loads, so loads issued ahead of time (the next
+// item's inputs) stay in flight across it.  Only for code whose cross-thread
+// communication goes entirely through LDS.
+__device__ __forceinline__ void lds_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// block_excl_scan / block_sum with LDS-only barriers (see lds_sync); a
+// single-wave workgroup needs no barrier at all.
+template <int NT, typename T>
+__device__ __forceinline__ T wg_excl_scan(T v, T *wsum, T &total) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (NW == 1) {
+        total = __shfl(incl, 63, 64);
+        return incl - v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    lds_sync();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        T x = wsum[i];
+        if (i < w) before += x;
+        tot += x;
+    }
+    lds_sync();
+    total = tot;
+    return before + incl - v;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T wg_sum(T v, T *wsum) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (NW == 1) return __shfl(v, 0, 64);
+    if (lane == 0) wsum[w] = v;
+    lds_sync();
+    T tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) tot += wsum[i];
+    lds_sync();
+    return tot;
+}
+
+// 64-bit value of lane l (l uniform), in scalar registers.
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Enumerates the products of one staged batch of A nonzeros, flat over the
 // workgroup: product q belongs to the staged entry o with st_e[o] <= q <
 // st_e[o+1] (st_e[nv] = total) and reads B entry st_s[o] + q - st_e[o].
@@ -154,6 +216,89 @@ __device__ __forceinline__ void staged_products(const S *st_s, const E *st_e, co
 #pragma unroll
         for (int v = 0; v < VT; ++v)
             if (ok[v]) f(cc[v], aa[v], vv[v]);
+    }
+}
+
+// Same contract as staged_products, but striped: a wave takes 64 * VT
+// consecutive products and lane l handles products l, l + 64, ... of them,
+// so one load instruction of the wave reads consecutive B entries (a few
+// cache lines instead of one line per lane) and the lanes of one
+// accumulation step mostly hit distinct columns of the same B row.  The
+// owner of the wave's first product comes from one (uniform) binary search;
+// each lane then walks forward across the B-row slices its products reach,
+// one LDS read per slice boundary.
+template <int WG, int VT, bool VALUES, typename E, typename S, typename F>
+__device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, const float *st_a,
+                                                 int nv, E total, const int32_t *colB,
+                                                 const float *valB, F &&f) {
+    constexpr bool kOff32 = sizeof(S) == 4;
+    const int32_t *ucol = uniform_ptr(colB);
+    const float *uval = VALUES ? uniform_ptr(valB) : valB;
+    const int lane = threadIdx.x & 63;
+    for (E c0 = (E)(threadIdx.x >> 6) * (64 * VT); c0 < total; c0 += (E)WG * VT) {
+        int o = __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, c0));
+        E e0 = st_e[o], e1 = st_e[o + 1];
+        S base = st_s[o];
+        float a = VALUES ? st_a[o] : 0.f;
+        int cc[VT];
+        float aa[VT], vv[VT];
+        bool ok[VT];
+#pragma unroll
+        for (int v = 0; v < VT; ++v) {
+            const E q = c0 + (E)(v * 64 + lane);
+            ok[v] = q < total;
+            cc[v] = 0;
+            aa[v] = 0.f;
+            vv[v] = 0.f;
+            if (ok[v]) {
+                while (q >= e1) {
+                    ++o;
+                    e0 = e1;
+                    e1 = st_e[o + 1];
+                    base = st_s[o];
+                    if (VALUES) a = st_a[o];
+                }
+                const S t = base + (S)(q - e0);
+                if (kOff32) {
+                    cc[v] = gld_off(ucol, (uint32_t)t);
+                    if (VALUES) vv[v] = gld_off(uval, (uint32_t)t);
+                } else {
+                    cc[v] = gld(colB + t);
+                    if (VALUES) vv[v] = gld(valB + t);
+                }
+                aa[v] = a;
+            }
+        }
+        f(cc, aa, vv, ok);
+    }
+}
+
+// Adds add[v] to acc[idx[v]] (LDS) for VT entries at once with the
+// compare-and-swap scheme of lds_fadd, but batched: all loads, then all
+// compare-and-swaps are issued before any result is waited for, so one
+// wave pays two LDS round trips per VT products instead of 2 * VT.  Entries
+// whose swap lost a race (another lane or step updated the same slot) retry
+// one by one.  idx[v] must be a valid slot for every v: callers point the
+// unused entries at a private dummy slot per lane with add = 0.
+template <int VT>
+__device__ __forceinline__ void lds_fadd_many(float *acc, const int *idx, const float *add) {
+    uint32_t *q = reinterpret_cast<uint32_t *>(acc);
+    uint32_t cur[VT], prev[VT];
+#pragma unroll
+    for (int v = 0; v < VT; ++v)
+        cur[v] = __hip_atomic_load(q + idx[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int v = 0; v < VT; ++v)
+        prev[v] = atomicCAS(q + idx[v], cur[v], __float_as_uint(__uint_as_float(cur[v]) + add[v]));
+#pragma unroll
+    for (int v = 0; v < VT; ++v) {
+        uint32_t c = prev[v];
+        bool pending = prev[v] != cur[v];
+        while (pending) {
+            const uint32_t p = atomicCAS(q + idx[v], c, __float_as_uint(__uint_as_float(c) + add[v]));
+            pending = p != c;
+            c = p;
+        }
     }
 }
 

@@ -419,6 +419,408 @@ __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ pr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined chunk kernels (sorted B with 32-bit positions, one chunk per
+// item).  A fixed grid of workgroups walks the items with a stride of the
+// grid size; while one item is processed, the inputs of the next one (its
+// descriptor, the slices of its B rows, its A values, its counts and first
+// structure word) are already in flight, and the workgroup's barriers order
+// LDS only, so those loads are not drained by them.  Per item, only the
+// gathers of B are then exposed to memory latency.  The accumulator / bitmap
+// is cleared once per workgroup; every item leaves it clear again.
+
+constexpr int kDescWords = (int)(sizeof(ChunkDesc) / 8);
+static_assert(sizeof(ChunkDesc) % 8 == 0 && kDescWords <= 64, "descriptor layout");
+
+// Lane l < kDescWords loads 8-byte word l of descriptor `it`.
+__device__ __forceinline__ uint64_t desc_word(const ChunkDesc *desc, int64_t it) {
+    const int lane = threadIdx.x & 63;
+    return lane < kDescWords ? gld((const uint64_t *)(desc + it) + lane) : 0ull;
+}
+
+__device__ __forceinline__ ChunkDesc desc_unpack(uint64_t w) {
+    ChunkDesc d;
+    d.a0 = (int64_t)readlane64(w, 0);
+    d.out0 = (int64_t)readlane64(w, 1);
+    d.slot0 = (int64_t)readlane64(w, 2);
+    d.sb = (int64_t)readlane64(w, 3);
+    const uint64_t w4 = readlane64(w, 4), w5 = readlane64(w, 5);
+    d.alen = (int32_t)(uint32_t)w4;
+    d.q = (int32_t)(uint32_t)(w4 >> 32);
+    d.prod = (int32_t)(uint32_t)w5;
+    d.pad = (int32_t)(uint32_t)(w5 >> 32);
+    return d;
+}
+
+// What a thread prefetches of one item: the slice of the B row named by the
+// row's A nonzero `threadIdx.x` (first staging round) and, for the numeric
+// phase, its A value, the chunk's output count and offsets and the thread's
+// first structure word.
+struct ItemIn {
+    uint32_t x0, x1;
+    float a;
+    uint32_t word;
+    int64_t cnt, pos, pos0;
+};
+
+template <bool NUMERIC>
+__device__ __forceinline__ ItemIn item_load(const ProdDev *prods, const ChunkDesc &d,
+                                            const uint32_t *sabs, const int64_t *chunk_cnt,
+                                            const int64_t *chunk_pos, const uint32_t *sbits,
+                                            int wpc) {
+    ItemIn in;
+    in.x0 = in.x1 = 0u;
+    in.a = 0.f;
+    in.word = 0u;
+    in.cnt = in.pos = in.pos0 = 0;
+    const int c = d.q;
+    const int j = threadIdx.x;
+    if (j < d.alen) {
+        const uint32_t *sc = sabs + d.sb + (int64_t)c * d.alen;
+        in.x0 = gld(sc + j);
+        in.x1 = gld(sc + d.alen + j);
+        if (NUMERIC) in.a = gld(prods[d.prod].valA + d.a0 + j);
+    }
+    if (NUMERIC) {
+        const int64_t slot = d.slot0 + c;
+        in.cnt = gld(chunk_cnt + slot);
+        in.pos = gld(chunk_pos + slot);
+        in.pos0 = gld(chunk_pos + d.slot0);
+        if (j < wpc) in.word = gld(sbits + slot * (int64_t)wpc + j);
+    }
+    return in;
+}
+
+// Stages the row's B slices for chunk [lo, hi) in rounds of WG A nonzeros
+// (the first round from the prefetched `in`) and hands every product to f.
+template <int WG, int VT, bool VALUES, typename F>
+__device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc &d,
+                                              const ItemIn &in, const uint32_t *sabs,
+                                              uint32_t *st_s, int *st_e, float *st_a, int *wsum,
+                                              F &&f) {
+    const int alen = d.alen;
+    const uint32_t *sc = sabs + d.sb + (int64_t)d.q * alen;
+    for (int jb = 0; jb < alen; jb += WG) {
+        const int j = jb + threadIdx.x;
+        uint32_t x0 = in.x0, x1 = in.x1;
+        float a = in.a;
+        if (jb > 0) {
+            x0 = x1 = 0u;
+            a = 0.f;
+            if (j < alen) {
+                x0 = gld(sc + j);
+                x1 = gld(sc + alen + j);
+                if (VALUES) a = gld(P.valA + d.a0 + j);
+            }
+        }
+        int total;
+        const int excl = wg_excl_scan<WG, int>((int)(x1 - x0), wsum, total);
+        st_s[threadIdx.x] = x0;
+        st_e[threadIdx.x] = excl;
+        if (VALUES) st_a[threadIdx.x] = a;
+        if (threadIdx.x == 0) st_e[WG] = total;
+        lds_sync();
+        const int nv = alen - jb < WG ? alen - jb : WG;
+        if (total > 0)
+            striped_products<WG, VT, VALUES, int, uint32_t>(st_s, st_e, st_a, nv, total, P.colB,
+                                                            P.valB, f);
+        lds_sync();
+    }
+}
+
+template <int WG, int WMAX>
+__global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict__ prods,
+                                                       const ChunkDesc *__restrict__ desc,
+                                                       int64_t nitems,
+                                                       const uint32_t *__restrict__ sabs,
+                                                       int64_t *__restrict__ chunk_cnt,
+                                                       int64_t *__restrict__ row_nnz,
+                                                       uint32_t *__restrict__ sbits, int wpc) {
+    __shared__ uint32_t bm[WMAX / 32];
+    __shared__ uint32_t st_s[WG];
+    __shared__ int st_e[WG + 1];
+    __shared__ int64_t wsum[WG / 64];
+    int64_t it = blockIdx.x;
+    const int64_t stride = gridDim.x;
+    if (it >= nitems) return;
+    for (int x = threadIdx.x; x < WMAX / 32; x += WG) bm[x] = 0u;
+    ChunkDesc d = desc_unpack(desc_word(desc, it));
+    ItemIn in = item_load<false>(prods, d, sabs, nullptr, nullptr, nullptr, 0);
+    uint64_t wnext = it + stride < nitems ? desc_word(desc, it + stride) : 0ull;
+    for (;;) {
+        const int64_t itn = it + stride;
+        const bool more = itn < nitems;
+        ChunkDesc dn;
+        ItemIn inn;
+        if (more) {
+            dn = desc_unpack(wnext);
+            inn = item_load<false>(prods, dn, sabs, nullptr, nullptr, nullptr, 0);
+            wnext = itn + stride < nitems ? desc_word(desc, itn + stride) : 0ull;
+        }
+        const ProdDev &P = prods[d.prod];
+        const int c = d.q;
+        const int lo = c * P.W;
+        const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+        int64_t cnt = 0;
+        if (hi > lo) {
+            lds_sync();  // bitmap clear (first item) done
+            pipe_products<WG, 8, false>(
+                P, d, in, sabs, st_s, st_e, nullptr, (int *)wsum,
+                [&](const int *cc, const float *, const float *, const bool *ok) {
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int rel = cc[v] - lo;
+                        if (ok[v]) atomicOr(&bm[rel >> 5], 1u << (rel & 31));
+                    }
+                });
+            const int nwords = (hi - lo + 31) >> 5;
+            uint32_t *keep = sbits + (d.slot0 + c) * (int64_t)wpc;
+            for (int x = threadIdx.x; x < nwords; x += WG) {
+                const uint32_t wv = bm[x];
+                cnt += __popc(wv);
+                gst(keep + x, wv);  // the chunk's structure, reused by the numeric phase
+                bm[x] = 0u;
+            }
+        }
+        const int64_t tot = wg_sum<WG, int64_t>(cnt, wsum);
+        if (threadIdx.x == 0) {
+            chunk_cnt[d.slot0 + c] = tot;
+            if (tot) atomicAdd((unsigned long long *)&row_nnz[d.out0], (unsigned long long)tot);
+        }
+        if (!more) break;
+        it = itn;
+        d = dn;
+        in = inn;
+    }
+}
+
+template <int WG, int WMAX>
+__global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict__ prods,
+                                                       const ChunkDesc *__restrict__ desc,
+                                                       int64_t nitems,
+                                                       const uint32_t *__restrict__ sabs,
+                                                       const int64_t *__restrict__ chunk_cnt,
+                                                       const int64_t *__restrict__ chunk_pos,
+                                                       const uint32_t *__restrict__ sbits,
+                                                       int wpc, int64_t min_expect,
+                                                       int *__restrict__ err) {
+    __shared__ float acc[WMAX + 64];  // + one dummy slot per lane for unused batch entries
+    __shared__ uint32_t st_s[WG];
+    __shared__ int st_e[WG + 1];
+    __shared__ float st_a[WG];
+    __shared__ int wsum[WG / 64];
+    int64_t it = blockIdx.x;
+    const int64_t stride = gridDim.x;
+    if (it >= nitems) return;
+    bool cleared = false;  // the accumulator is cleared before the first item taken
+    ChunkDesc d = desc_unpack(desc_word(desc, it));
+    ItemIn in = item_load<true>(prods, d, sabs, chunk_cnt, chunk_pos, sbits, wpc);
+    uint64_t wnext = it + stride < nitems ? desc_word(desc, it + stride) : 0ull;
+    for (;;) {
+        const int64_t itn = it + stride;
+        const bool more = itn < nitems;
+        ChunkDesc dn;
+        ItemIn inn;
+        if (more) {
+            dn = desc_unpack(wnext);
+            inn = item_load<true>(prods, dn, sabs, chunk_cnt, chunk_pos, sbits, wpc);
+            wnext = itn + stride < nitems ? desc_word(desc, itn + stride) : 0ull;
+        }
+        const ProdDev &P = prods[d.prod];
+        const int c = d.q;
+        const int lo = c * P.W;
+        const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+        const int width = hi - lo;
+        // the count is the same in every lane; make it a scalar
+        const int64_t expect = (int64_t)readlane64((uint64_t)in.cnt, 0);
+        if (width > WMAX) {  // the plan picks WMAX >= W; never taken
+            if (threadIdx.x == 0) atomicOr(err, kErrRow);
+            return;
+        }
+        if (expect > min_expect) {  // smaller chunks belong to k_num_chunk_rank
+            if (!cleared) {
+                for (int q = threadIdx.x; q < WMAX + 64; q += WG) acc[q] = 0.f;
+                cleared = true;
+            }
+            const int64_t out0 = d.out0 + (in.pos - in.pos0);
+            lds_sync();  // clear (first item) done
+            const int dummy = WMAX + (threadIdx.x & 63);
+            pipe_products<WG, NVT, true>(
+                P, d, in, sabs, st_s, st_e, st_a, wsum,
+                [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
+                    int idx[NVT];
+                    float add[NVT];
+#pragma unroll
+                    for (int v = 0; v < NVT; ++v) {
+                        idx[v] = ok[v] ? cc[v] - lo : dummy;
+                        add[v] = ok[v] ? aa[v] * vv[v] : 0.f;
+                    }
+                    lds_fadd_many<NVT>(acc, idx, add);
+                });
+            // Emission in column order from the chunk's structure: one word
+            // (32 columns) per thread, positions from a scan of the
+            // popcounts; a thread walks its set bits and clears the
+            // accumulator slots it reads.
+            const int nwords = (width + 31) >> 5;
+            const uint32_t *bits = sbits + (d.slot0 + c) * (int64_t)wpc;
+            int32_t *colC = P.colC + out0;
+            float *valC = P.valC + out0;
+            int base = 0;
+            for (int w0 = 0; w0 < nwords; w0 += WG) {
+                const int x = w0 + threadIdx.x;
+                uint32_t word = x < nwords ? (w0 == 0 ? in.word : gld(bits + x)) : 0u;
+                int total;
+                const int pre = wg_excl_scan<WG, int>(__popc(word), wsum, total);
+                int r = base + pre;
+                while (word) {
+                    const int b = __builtin_ctz(word);
+                    word &= word - 1u;
+                    const int rel = (x << 5) + b;
+                    const float v = acc[rel];
+                    acc[rel] = 0.f;
+                    if (r < expect) {
+                        gst(colC + r, lo + rel);
+                        gst(valC + r, v);
+                    }
+                    ++r;
+                }
+                base += total;
+            }
+            if (threadIdx.x == 0 && base != expect) atomicOr(err, kErrChunk);
+        }
+        if (!more) break;
+        it = itn;
+        d = dn;
+        in = inn;
+    }
+}
+
+// Numeric kernel for chunks with at most CAP outputs (most chunks of a
+// skewed product): one wave per chunk.  The chunk's structure (the bitmap the
+// symbolic phase stored) gives every output column its rank among the
+// chunk's outputs -- a perfect, collision-free hash -- so the accumulator is
+// a compact array of CAP floats rather than one slot per column, a chunk
+// needs a few KB of LDS and many chunks are resident per compute unit.  The
+// values leave as one contiguous (coalesced) copy, already in column order;
+// the columns are written from the bitmap.
+template <int WMAX, int CAP>
+__global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
+                                                       const ChunkDesc *__restrict__ desc,
+                                                       const uint32_t *__restrict__ sabs,
+                                                       const int64_t *__restrict__ chunk_cnt,
+                                                       const int64_t *__restrict__ chunk_pos,
+                                                       const uint32_t *__restrict__ sbits,
+                                                       int wpc, int *__restrict__ err) {
+    constexpr int NWD = WMAX / 32;  // structure words of a chunk
+    constexpr int K = NWD / 64;     // words per lane
+    static_assert(K >= 1 && NWD % 64 == 0, "chunk width");
+    __shared__ uint2 sw[NWD];        // {word, outputs before the word}
+    __shared__ float cacc[CAP + 64];  // + one dummy slot per lane for unused batch entries
+    __shared__ uint32_t st_s[64];
+    __shared__ int st_e[65];
+    __shared__ float st_a[64];
+    const int lane = threadIdx.x;
+    const ChunkDesc d = desc_unpack(desc_word(desc, blockIdx.x));
+    const int c = d.q;
+    const int64_t slot = d.slot0 + c;
+    const int64_t expect = (int64_t)readlane64((uint64_t)gld(chunk_cnt + slot), 0);
+    if (expect == 0 || expect > CAP) return;  // empty, or a dense chunk (k_num_chunk_pipe)
+    const ProdDev &P = prods[d.prod];
+    ItemIn in;
+    in.x0 = in.x1 = 0u;
+    in.a = 0.f;
+    if (lane < d.alen) {
+        const uint32_t *sc = sabs + d.sb + (int64_t)c * d.alen;
+        in.x0 = gld(sc + lane);
+        in.x1 = gld(sc + d.alen + lane);
+        in.a = gld(P.valA + d.a0 + lane);
+    }
+    const int64_t out0 = d.out0 + (gld(chunk_pos + slot) - gld(chunk_pos + d.slot0));
+    const int lo = c * P.W;
+    const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+    const int nwords = (hi - lo + 31) >> 5;
+    if (hi - lo > WMAX) {  // the plan picks WMAX >= W; never taken
+        if (lane == 0) atomicOr(err, kErrRow);
+        return;
+    }
+    // structure: lane l holds words l*K .. l*K + K - 1
+    const uint32_t *bits = sbits + slot * (int64_t)wpc;
+    uint32_t wv[K];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int x = lane * K + k;
+        wv[k] = x < nwords ? gld(bits + x) : 0u;
+        cnt += __popc(wv[k]);
+    }
+    int total;
+    int pre = wg_excl_scan<64, int>(cnt, nullptr, total);
+    const int pre0 = pre;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        sw[lane * K + k] = make_uint2(wv[k], (uint32_t)pre);
+        pre += __popc(wv[k]);
+    }
+    for (int r = lane; r < expect; r += 64) cacc[r] = 0.f;
+    cacc[CAP + lane] = 0.f;
+    if (lane == 0 && total != expect) atomicOr(err, kErrChunk);
+    lds_sync();
+    const int dummy = CAP + lane;
+    bool stray = false;
+    pipe_products<64, NVT, true>(
+        P, d, in, sabs, st_s, st_e, st_a, nullptr,
+        [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
+            int idx[NVT];
+            float add[NVT];
+#pragma unroll
+            for (int v = 0; v < NVT; ++v) {
+                const int rel = cc[v] - lo;
+                const uint2 e = sw[(ok[v] ? rel : 0) >> 5];
+                const uint32_t bit = 1u << (rel & 31);
+                const bool in_structure = (e.x & bit) != 0u;
+                stray |= ok[v] && !in_structure;
+                const bool take = ok[v] && in_structure;
+                idx[v] = take ? (int)e.y + __popc(e.x & (bit - 1u)) : dummy;
+                add[v] = take ? aa[v] * vv[v] : 0.f;
+            }
+            lds_fadd_many<NVT>(cacc, idx, add);
+        });
+    if (stray) atomicOr(err, kErrChunk);  // a product outside the symbolic structure
+    lds_sync();
+    float *valC = P.valC + out0;
+    for (int r = lane; r < expect; r += 64) gst(valC + r, cacc[r]);
+    int32_t *colC = P.colC + out0;
+    int r = pre0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        uint32_t w = wv[k];
+        const int base = lo + ((lane * K + k) << 5);
+        while (w) {
+            const int b = __builtin_ctz(w);
+            w &= w - 1u;
+            if (r < expect) gst(colC + r, base + b);
+            ++r;
+        }
+    }
+}
+
+// Workgroups of a pipelined launch: wgs_per_cu per compute unit (a multiple
+// of 8 in total, so that the grid covers the eight dies evenly), or one per
+// item when wgs_per_cu is 0; never more than there are items.
+static unsigned pipe_grid(int wgs_per_cu, int64_t nitems) {
+    if (wgs_per_cu <= 0) return (unsigned)nitems;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 8;
+    int64_t g = (int64_t)wgs_per_cu * cus;
+    g -= g % 8;
+    if (g < 8) g = 8;
+    if (g > nitems) g = nitems;
+    return (unsigned)g;
+}
+
 void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
                    int32_t *bsplit, hipStream_t s) {
     const int64_t n = k_rows * (nch + 1);
@@ -489,10 +891,58 @@ static void sym_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *de
                            desc, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
 }
 
+template <int WG, int WMAX>
+static void sym_pipe_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
+                            int64_t nitems, int64_t *chunk_cnt, int64_t *row_nnz,
+                            uint32_t *sbits, int wpc, int wgs_per_cu, hipStream_t s) {
+    const unsigned g = pipe_grid(wgs_per_cu, nitems);
+    hipLaunchKernelGGL((k_sym_chunk_pipe<WG, WMAX>), dim3(g), dim3(WG), 0, s, prods, desc, nitems,
+                       sabs, chunk_cnt, row_nnz, sbits, wpc);
+}
+
+template <int WMAX>
+static void sym_pipe_wg(int wg, const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
+                        int64_t nitems, int64_t *chunk_cnt, int64_t *row_nnz, uint32_t *sbits,
+                        int wpc, int wgs_per_cu, hipStream_t s) {
+    switch (wg) {
+    case 64:
+        sym_pipe_launch<64, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                                  wgs_per_cu, s);
+        break;
+    case 128:
+        sym_pipe_launch<128, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                                   wgs_per_cu, s);
+        break;
+    case 512:
+        sym_pipe_launch<512, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                                   wgs_per_cu, s);
+        break;
+    default:
+        sym_pipe_launch<256, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                                   wgs_per_cu, s);
+    }
+}
+
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
-                      int64_t *row_nnz, uint32_t *sbits, int wpc, hipStream_t s) {
+                      int64_t *row_nnz, uint32_t *sbits, int wpc, int wgs_per_cu, int threads,
+                      hipStream_t s) {
     if (nitems <= 0) return;
+    if (fast && kper == 1) {
+        if (wmax <= 2048)
+            sym_pipe_wg<2048>(threads ? threads : 64, prods, desc, sabs, nitems, chunk_cnt,
+                              row_nnz, sbits, wpc, wgs_per_cu, s);
+        else if (wmax <= 4096)
+            sym_pipe_wg<4096>(threads ? threads : 128, prods, desc, sabs, nitems, chunk_cnt,
+                              row_nnz, sbits, wpc, wgs_per_cu, s);
+        else if (wmax <= 8192)
+            sym_pipe_wg<8192>(threads ? threads : 256, prods, desc, sabs, nitems, chunk_cnt,
+                              row_nnz, sbits, wpc, wgs_per_cu, s);
+        else
+            sym_pipe_wg<kMaxChunkCols>(threads ? threads : 256, prods, desc, sabs, nitems,
+                                       chunk_cnt, row_nnz, sbits, wpc, wgs_per_cu, s);
+        return;
+    }
     if (fast)
         sym_chunk_launch<true>(wmax, prods, desc, sabs, nitems, kper, chunk_cnt, row_nnz, sbits,
                                wpc, s);
@@ -521,11 +971,100 @@ static void num_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *de
                            prods, desc, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
 }
 
+template <int WG, int WMAX>
+static void num_pipe_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
+                            int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
+                            const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap, int *err,
+                            hipStream_t s) {
+    const unsigned g = pipe_grid(wgs_per_cu, nitems);
+    hipLaunchKernelGGL((k_num_chunk_pipe<WG, WMAX>), dim3(g), dim3(WG), 0, s, prods, desc, nitems,
+                       sabs, chunk_cnt, chunk_pos, sbits, wpc, (int64_t)rank_cap, err);
+}
+
+template <int RW>
+static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
+                            int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
+                            const uint32_t *sbits, int wpc, int rank_cap, int *err,
+                            hipStream_t s) {
+    const dim3 grid((unsigned)nitems);
+    if (rank_cap <= 512)
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512>), grid, dim3(64), 0, s, prods, desc, sabs,
+                           chunk_cnt, chunk_pos, sbits, wpc, err);
+    else if (rank_cap <= 1024)
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024>), grid, dim3(64), 0, s, prods, desc, sabs,
+                           chunk_cnt, chunk_pos, sbits, wpc, err);
+    else
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048>), grid, dim3(64), 0, s, prods, desc, sabs,
+                           chunk_cnt, chunk_pos, sbits, wpc, err);
+}
+
+bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
+    return fast && kper == 1 && rank_cap > 0;
+}
+
+void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+                           const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
+                           const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
+                           int *err, hipStream_t s) {
+    if (nitems <= 0 || rank_cap <= 0) return;
+    if (wmax <= 2048)
+        num_rank_launch<2048>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                              rank_cap, err, s);
+    else if (wmax <= 4096)
+        num_rank_launch<4096>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                              rank_cap, err, s);
+    else if (wmax <= 8192)
+        num_rank_launch<8192>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                              rank_cap, err, s);
+    else
+        num_rank_launch<kMaxChunkCols>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits,
+                                       wpc, rank_cap, err, s);
+}
+
+template <int WMAX>
+static void num_pipe_wg(int wg, const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
+                        int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
+                        const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap, int *err,
+                        hipStream_t s) {
+    switch (wg) {
+    case 64:
+        num_pipe_launch<64, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                                  wgs_per_cu, rank_cap, err, s);
+        break;
+    case 128:
+        num_pipe_launch<128, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                                   wgs_per_cu, rank_cap, err, s);
+        break;
+    case 512:
+        num_pipe_launch<512, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                                   wgs_per_cu, rank_cap, err, s);
+        break;
+    default:
+        num_pipe_launch<256, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                                   wgs_per_cu, rank_cap, err, s);
+    }
+}
+
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
-                      const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int *err,
-                      hipStream_t s) {
+                      const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,
+                      int threads, int rank_cap, int *err, hipStream_t s) {
     if (nitems <= 0) return;
+    if (fast && kper == 1) {
+        if (wmax <= 2048)
+            num_pipe_wg<2048>(threads ? threads : 64, prods, desc, sabs, nitems, chunk_cnt,
+                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+        else if (wmax <= 4096)
+            num_pipe_wg<4096>(threads ? threads : 128, prods, desc, sabs, nitems, chunk_cnt,
+                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+        else if (wmax <= 8192)
+            num_pipe_wg<8192>(threads ? threads : 256, prods, desc, sabs, nitems, chunk_cnt,
+                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+        else
+            num_pipe_wg<kMaxChunkCols>(threads ? threads : 512, prods, desc, sabs, nitems,
+                                       chunk_cnt, chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+        return;
+    }
     if (fast)
         num_chunk_launch<true>(wmax, prods, desc, sabs, nitems, kper, chunk_cnt, chunk_pos, sbits,
                                wpc, err, s);

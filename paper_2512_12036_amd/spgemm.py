@@ -32,7 +32,9 @@ class Options(ctypes.Structure):
     _fields_ = [("sym_upper", _I64 * (NGROUPS - 1)), ("num_upper", _I64 * (NGROUPS - 1)),
                 ("chunk_cols", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("chunks_per_item", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("chunk_wgs_per_cu", ctypes.c_int32), ("chunk_threads", ctypes.c_int32),
+                ("sym_chunk_threads", ctypes.c_int32), ("num_rank_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Info(ctypes.Structure):
@@ -117,7 +119,8 @@ def default_options() -> Options:
 
 
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
-                 profile=None, chunks_per_item=None) -> Options:
+                 profile=None, chunks_per_item=None, chunk_wgs_per_cu=None,
+                 chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -133,6 +136,14 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.profile = int(profile)
     if chunks_per_item is not None:
         o.chunks_per_item = int(chunks_per_item)
+    if chunk_wgs_per_cu is not None:
+        o.chunk_wgs_per_cu = int(chunk_wgs_per_cu)
+    if chunk_threads is not None:
+        o.chunk_threads = int(chunk_threads)
+    if sym_chunk_threads is not None:
+        o.sym_chunk_threads = int(sym_chunk_threads)
+    if num_rank_cap is not None:
+        o.num_rank_cap = int(num_rank_cap)
     return o
 
 

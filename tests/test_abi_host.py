@@ -72,7 +72,10 @@ def _create(a, b, o):
 
 
 @pytest.mark.parametrize("field,value", [("chunk_cols", 100), ("chunk_cols", 0),
-                                         ("chunk_cols", 32768), ("validate", 7)])
+                                         ("chunk_cols", 32768), ("validate", 7),
+                                         ("chunks_per_item", 3), ("chunk_wgs_per_cu", -1),
+                                         ("chunk_wgs_per_cu", 65), ("chunk_threads", 96),
+                                         ("sym_chunk_threads", 32), ("num_rank_cap", 300)])
 def test_bad_options_rejected(field, value):
     o = spgemm.default_options()
     setattr(o, field, value)

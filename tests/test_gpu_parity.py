@@ -66,6 +66,44 @@ def test_chunks_per_item(kper):
                     label=f"kper{kper}-unsorted")
 
 
+@pytest.mark.parametrize("chunk_cols,wgs", [(256, 1), (2048, 2), (4096, 4), (8192, 8),
+                                             (16384, 3)])
+def test_chunk_resident_workgroups(chunk_cols, wgs):
+    # a fixed grid of resident workgroups walking the chunk items (several
+    # items per workgroup, next item's inputs prefetched)
+    a = gen.rmat(12, 16, seed=14)
+    run_and_compare(a, a, options=forced_options(7, chunk_cols, 1, wgs, None, 0),
+                    label=f"wgs{wgs}")
+    ai = gen.int_valued(a, 3)
+    run_and_compare(ai, ai, options=forced_options(7, chunk_cols, 1, wgs, None, 512), exact=True,
+                    label=f"wgs{wgs}-int")
+
+
+@pytest.mark.parametrize("chunk_cols,threads", [(2048, 256), (4096, 64), (8192, 64),
+                                                 (8192, 512), (16384, 128)])
+def test_chunk_workgroup_sizes(chunk_cols, threads):
+    a = gen.rmat(12, 16, seed=15)
+    # rank accumulator off: every chunk takes the dense kernel
+    run_and_compare(a, a, options=forced_options(7, chunk_cols, 1, None, threads, 0),
+                    label=f"thr{threads}")
+    run_and_compare(a, a, options=forced_options(7, chunk_cols, 1, 2, threads, 0),
+                    label=f"thr{threads}-wgs2")
+
+
+@pytest.mark.parametrize("chunk_cols,cap,sym_threads", [(256, 512, 64), (2048, 1024, 128),
+                                                        (8192, 2048, 256), (16384, 1024, 512),
+                                                        (4096, 512, 0)])
+def test_chunk_rank_accumulator(chunk_cols, cap, sym_threads):
+    # chunks with at most `cap` outputs go to the compact rank accumulator,
+    # the others to the dense one
+    a = gen.rmat(13, 16, seed=16)
+    run_and_compare(a, a, options=forced_options(7, chunk_cols, 1, None, None, cap, sym_threads),
+                    label=f"rank{cap}")
+    ai = gen.int_valued(gen.rmat(12, 16, seed=17), 4)
+    run_and_compare(ai, ai, options=forced_options(7, chunk_cols, 1, None, None, cap,
+                                                   sym_threads), exact=True, label=f"rank{cap}-int")
+
+
 def test_chunk_unsorted_b():
     a = gen.rmat(11, 16, seed=12)
     b = gen.shuffle_rows(a, 3)
