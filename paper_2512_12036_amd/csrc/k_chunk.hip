@@ -605,6 +605,7 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
                                                        int wpc, int64_t min_expect,
                                                        int *__restrict__ err) {
     __shared__ float acc[WMAX + 64];  // + one dummy slot per lane for unused batch entries
+    __shared__ uint2 sw[WMAX / 32];   // structure words and their first output slot
     __shared__ uint32_t st_s[WG];
     __shared__ int st_e[WG + 1];
     __shared__ float st_a[WG];
@@ -657,10 +658,13 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
                     }
                     lds_fadd_many<NVT>(acc, idx, add);
                 });
-            // Emission in column order from the chunk's structure: one word
-            // (32 columns) per thread, positions from a scan of the
-            // popcounts; a thread walks its set bits and clears the
-            // accumulator slots it reads.
+            // Emission from the chunk's structure (the symbolic bitmap): a scan
+            // of the words' popcounts gives each word its first output slot;
+            // then thread t takes columns t, t + WG, ...: the output slot of a
+            // set column is its word's slot plus the set bits below it, so
+            // consecutive set columns go to consecutive slots (coalesced
+            // writes, already in column order), and every slot of the
+            // accumulator is cleared for the next chunk.
             const int nwords = (width + 31) >> 5;
             const uint32_t *bits = sbits + (d.slot0 + c) * (int64_t)wpc;
             int32_t *colC = P.colC + out0;
@@ -668,23 +672,25 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
             int base = 0;
             for (int w0 = 0; w0 < nwords; w0 += WG) {
                 const int x = w0 + threadIdx.x;
-                uint32_t word = x < nwords ? (w0 == 0 ? in.word : gld(bits + x)) : 0u;
+                const uint32_t word = x < nwords ? (w0 == 0 ? in.word : gld(bits + x)) : 0u;
                 int total;
                 const int pre = wg_excl_scan<WG, int>(__popc(word), wsum, total);
-                int r = base + pre;
-                while (word) {
-                    const int b = __builtin_ctz(word);
-                    word &= word - 1u;
-                    const int rel = (x << 5) + b;
-                    const float v = acc[rel];
-                    acc[rel] = 0.f;
+                if (x < nwords) sw[x] = make_uint2(word, (uint32_t)(base + pre));
+                base += total;
+            }
+            lds_sync();
+            for (int col = threadIdx.x; col < nwords * 32; col += WG) {
+                const uint2 e = sw[col >> 5];
+                const uint32_t bit = 1u << (col & 31);
+                const float v = acc[col];
+                acc[col] = 0.f;
+                if (e.x & bit) {
+                    const int r = (int)e.y + __popc(e.x & (bit - 1u));
                     if (r < expect) {
-                        gst(colC + r, lo + rel);
+                        gst(colC + r, lo + col);
                         gst(valC + r, v);
                     }
-                    ++r;
                 }
-                base += total;
             }
             if (threadIdx.x == 0 && base != expect) atomicOr(err, kErrChunk);
         }
