@@ -92,10 +92,11 @@ typedef void (*spgemm_free_fn)(void *ctx, void *ptr, void *stream);
 
 typedef struct {
     /* Inclusive upper bounds of groups 1..6 (index 0 unused, must be 0).
-     * Symbolic groups are keyed by the intermediate-product count of the row,
-     * numeric groups by its output length (paper Section III-C: the table
-     * size is first set from the intermediate products, then from the
-     * distinct count).  Non-decreasing.  Capacities (maximum legal bound):
+     * Symbolic groups are keyed by min(intermediate products of the row,
+     * columns of B) -- both bound the row's distinct outputs; paper Table I
+     * uses the first -- and numeric groups by the row's output length (paper
+     * Section III-C: the table size is first set from the intermediate
+     * products, then from the distinct count).  Non-decreasing.  Capacities (maximum legal bound):
      *   symbolic: 63, 127, 255, 511, 8191, 32767
      *   numeric : 63, 127, 255, 511, 2047, 8191
      * and sym_upper[6] <= num_upper[6] (a row handled as chunks in the

@@ -347,7 +347,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         TimeScope ts(p, "plan.group");
         ST_TRY(scan(p, p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk));
         launch_scatter(p->dprods, p->dblks, p->nblk, gb, p->ip, p->blkoff, p->map_sym, p->hslot,
-                       p->stream);
+                       true, p->stream);
         launch_group_starts(p->blkoff, p->nblk, p->starts, p->stream);
     }
     ST_TRY(launch_check());
@@ -506,7 +506,7 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk));
         launch_scatter(p->dprods, p->dblks, p->nblk, gb, p->row_nnz, p->blkoff, p->map_num,
-                       nullptr, st);
+                       nullptr, false, st);
         launch_group_starts(p->blkoff, p->nblk, p->starts + (kGroups + 1), st);
     }
     ST_TRY(launch_check());

@@ -115,7 +115,8 @@ void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk,
                          ProdStats *stats, hipStream_t s);
 void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk,
                     GroupBounds gb, const int64_t *key, const int64_t *off,
-                    uint64_t *map, int32_t *hslot, hipStream_t s);
+                    uint64_t *map, int32_t *hslot, bool cap_to_ncols,
+                    hipStream_t s);
 void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStream_t s);
 
 // Chunk preparation (group 7).

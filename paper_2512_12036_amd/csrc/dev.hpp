@@ -219,14 +219,14 @@ __device__ __forceinline__ void staged_products(const S *st_s, const E *st_e, co
     }
 }
 
-// Same contract as staged_products, but striped: a wave takes 64 * VT
-// consecutive products and lane l handles products l, l + 64, ... of them,
-// so one load instruction of the wave reads consecutive B entries (a few
-// cache lines instead of one line per lane) and the lanes of one
-// accumulation step mostly hit distinct columns of the same B row.  The
-// owner of the wave's first product comes from one (uniform) binary search;
-// each lane then walks forward across the B-row slices its products reach,
-// one LDS read per slice boundary.
+// Same contract as staged_products, but striped: a wave takes consecutive
+// rows of 64 products and lane l handles product l of each row, so one load
+// instruction of the wave reads consecutive B entries (a few cache lines
+// instead of one line per lane) and the lanes of one accumulation step
+// mostly hit distinct columns of the same B row.  The owner of the wave's
+// first product comes from one (uniform) binary search; each lane then walks
+// forward across the B-row slices its products reach, one LDS read per slice
+// boundary.  f receives VT products per lane at a time (arrays + valid flags).
 template <int WG, int VT, bool VALUES, typename E, typename S, typename F>
 __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, const float *st_a,
                                                  int nv, E total, const int32_t *colB,
@@ -234,19 +234,25 @@ __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, c
     constexpr bool kOff32 = sizeof(S) == 4;
     const int32_t *ucol = uniform_ptr(colB);
     const float *uval = VALUES ? uniform_ptr(valB) : valB;
-    const int lane = threadIdx.x & 63;
-    for (E c0 = (E)(threadIdx.x >> 6) * (64 * VT); c0 < total; c0 += (E)WG * VT) {
-        int o = __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, c0));
-        E e0 = st_e[o], e1 = st_e[o + 1];
-        S base = st_s[o];
-        float a = VALUES ? st_a[o] : 0.f;
+    constexpr int NW = WG / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // wave w takes a contiguous range of 64-product rows, so its lanes only
+    // ever walk forward and one binary search per staged batch suffices
+    const E nrow = (total + 63) >> 6;
+    const E r0 = nrow * w / NW, r1 = nrow * (w + 1) / NW;
+    if (r0 >= r1) return;
+    int o = __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, r0 * 64));
+    E e0 = st_e[o], e1 = st_e[o + 1];
+    S base = st_s[o];
+    float a = VALUES ? st_a[o] : 0.f;
+    for (E r = r0; r < r1; r += VT) {
         int cc[VT];
         float aa[VT], vv[VT];
         bool ok[VT];
 #pragma unroll
         for (int v = 0; v < VT; ++v) {
-            const E q = c0 + (E)(v * 64 + lane);
-            ok[v] = q < total;
+            const E q = (r + v) * 64 + lane;
+            ok[v] = r + v < r1 && q < total;
             cc[v] = 0;
             aa[v] = 0.f;
             vv[v] = 0.f;

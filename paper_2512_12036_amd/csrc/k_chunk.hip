@@ -335,7 +335,8 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
         atomicAdd((unsigned long long *)&row_nnz[d.out0], (unsigned long long)row_total);
 }
 
-constexpr int NVT = 8;  // products per lane per round in the numeric chunk kernel
+constexpr int NVT = 8;        // products per lane per round in the numeric chunk kernels
+constexpr int kDenseVT = 16;  // same for dense chunks (more gathers in flight per wave)
 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
@@ -646,17 +647,17 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
             const int64_t out0 = d.out0 + (in.pos - in.pos0);
             lds_sync();  // clear (first item) done
             const int dummy = WMAX + (threadIdx.x & 63);
-            pipe_products<WG, NVT, true>(
+            pipe_products<WG, kDenseVT, true>(
                 P, d, in, sabs, st_s, st_e, st_a, wsum,
                 [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
-                    int idx[NVT];
-                    float add[NVT];
+                    int idx[kDenseVT];
+                    float add[kDenseVT];
 #pragma unroll
-                    for (int v = 0; v < NVT; ++v) {
+                    for (int v = 0; v < kDenseVT; ++v) {
                         idx[v] = ok[v] ? cc[v] - lo : dummy;
                         add[v] = ok[v] ? aa[v] * vv[v] : 0.f;
                     }
-                    lds_fadd_many<NVT>(acc, idx, add);
+                    lds_fadd_many<kDenseVT>(acc, idx, add);
                 });
             // Emission from the chunk's structure (the symbolic bitmap): a scan
             // of the words' popcounts gives each word its first output slot;

@@ -75,10 +75,18 @@ __device__ __forceinline__ int ceil_log2(int64_t x) {
 // Group kernels: G lanes per row.
 // ---------------------------------------------------------------------------
 // Walks every intermediate product of row i of P with the G lanes of a group
-// and calls f(col_b, a_value, b_value) for each.  Group-uniform control flow;
-// U windows of G products per round so that U gathers per lane are in flight.
+// and calls f(col_b, a_value, b_value) for each.  The row's A nonzeros are
+// staged G at a time in the group's LDS slice (B-row start, exclusive prefix
+// of the B-row lengths, A value); lane l then takes products l, l + G, ...
+// (consecutive lanes read consecutive B entries) and finds each product's B
+// row by walking forward through the staged prefix, one LDS read per B-row
+// boundary crossed.  A group lives inside one wave, so its LDS traffic is
+// ordered without a barrier.  Group-uniform control flow; U products per lane
+// per round so that U gathers per lane are in flight.
 template <int G, int U, bool VALUES, typename F>
-__device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int lane, F &&f) {
+__device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int lane,
+                                               int64_t *gs_s, int *gs_e, float *gs_a, F &&f) {
+    static_assert(64 % G == 0, "a group must live inside one wave");
     const int64_t a0 = gld(P.rptA + i), a1 = gld(P.rptA + i + 1);
     const int32_t *colB = P.colB;
     const float *valB = P.valB;
@@ -100,7 +108,15 @@ __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int 
             if (lane >= off) incl += o;
         }
         const int total = __shfl(incl, G - 1, G);
-        const int excl = incl - len;
+        gs_s[lane] = s;
+        gs_e[lane] = incl - len;
+        if (VALUES) gs_a[lane] = a;
+        if (lane == G - 1) gs_e[G] = total;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        int o = 0;
+        int e0 = 0, e1 = gs_e[1];
+        int64_t base = gs_s[0];
+        float av = VALUES ? gs_a[0] : 0.f;
         for (int qb = 0; qb < total; qb += G * U) {
             int cc[U];
             float aa[U], vv[U];
@@ -108,27 +124,28 @@ __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = qb + u * G + lane;
-                int o = 0;
-#pragma unroll
-                for (int step = G / 2; step > 0; step >>= 1) {
-                    int v = __shfl(excl, o + step, G);
-                    if (v <= q) o += step;
-                }
-                const int64_t so = __shfl(s, o, G);
-                const int eo = __shfl(excl, o, G);
-                aa[u] = VALUES ? __shfl(a, o, G) : 0.f;
                 ok[u] = q < total;
                 cc[u] = 0;
+                aa[u] = 0.f;
                 vv[u] = 0.f;
                 if (ok[u]) {
-                    cc[u] = gld(colB + so + (q - eo));
-                    if (VALUES) vv[u] = gld(valB + so + (q - eo));
+                    while (q >= e1) {
+                        ++o;
+                        e0 = e1;
+                        e1 = gs_e[o + 1];
+                        base = gs_s[o];
+                        if (VALUES) av = gs_a[o];
+                    }
+                    cc[u] = gld(colB + base + (q - e0));
+                    if (VALUES) vv[u] = gld(valB + base + (q - e0));
+                    aa[u] = av;
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (ok[u]) f(cc[u], aa[u], vv[u]);
         }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // staging reads done
     }
 }
 
@@ -139,6 +156,8 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
                                                     int *__restrict__ err) {
     constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v;
     __shared__ int keys[R * T];
+    __shared__ int64_t st_s[256];
+    __shared__ int st_e[R * (G + 1)];
     for (int s = threadIdx.x; s < R * T; s += 256) keys[s] = kEmptyKey;
     __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
@@ -149,9 +168,10 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     const int64_t i = item_row(e);
     int *tab = keys + gi * T;
     int cnt = 0;
-    group_products<G, 2, false>(P, i, lane, [&](int c, float, float) {
-        cnt += lds_insert(tab, T - 1, LOG2T, c, err);
-    });
+    group_products<G, 4, false>(P, i, lane, st_s + gi * G, st_e + gi * (G + 1), nullptr,
+                                [&](int c, float, float) {
+                                    cnt += lds_insert(tab, T - 1, LOG2T, c, err);
+                                });
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, G);
     if (lane == 0) row_nnz[P.row_base + i] = cnt;
@@ -165,6 +185,9 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v, PER = T / G;
     __shared__ int keys[R * T];
     __shared__ float vals[R * T];
+    __shared__ int64_t st_s[256];
+    __shared__ int st_e[R * (G + 1)];
+    __shared__ float st_a[256];
     for (int s = threadIdx.x; s < R * T; s += 256) { keys[s] = kEmptyKey; vals[s] = 0.f; }
     __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
@@ -176,9 +199,10 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     if (active) {
         e = items[it];
         const ProdDev &P = prods[item_prod(e)];
-        group_products<G, 2, true>(P, item_row(e), lane, [&](int c, float a, float b) {
-            lds_add(tab, tv, T - 1, LOG2T, c, a * b, err);
-        });
+        group_products<G, 4, true>(P, item_row(e), lane, st_s + gi * G, st_e + gi * (G + 1),
+                                   st_a + gi * G, [&](int c, float a, float b) {
+                                       lds_add(tab, tv, T - 1, LOG2T, c, a * b, err);
+                                   });
     }
     __syncthreads();
     // gather: each lane owns slots lane + G*r

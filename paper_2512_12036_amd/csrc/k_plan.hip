@@ -141,14 +141,18 @@ __device__ __forceinline__ int lds_upper_row(const int64_t *rp, int n, int64_t j
 // Histogram of groups over the block's rows (one key per thread, valid < nrows)
 // plus per-product sums: keys, max key, and the group-7 (chunked) rows with
 // their A nonzeros, split-table size and chunk count (nch per row).
+// The group is chosen by min(key, gcap): the symbolic grouping caps the
+// intermediate-product count at B's column count, a bound on the row's
+// distinct outputs at least as tight as the count itself.
 __device__ __forceinline__ void block_histogram(int64_t key, int64_t alen, bool valid,
                                                 const GroupBounds &gb, int nblk, int64_t *blkcnt,
-                                                ProdStats *st, int nch, bool ip_stats) {
+                                                ProdStats *st, int nch, bool ip_stats,
+                                                int64_t gcap) {
     __shared__ int hist[kGroups];
     __shared__ unsigned long long red[kRowBlock / 64][4];
     if (threadIdx.x < kGroups) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int g = valid ? group_of(key, gb) : -1;
+    const int g = valid ? group_of(key < gcap ? key : gcap, gb) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int b = 0; b < kGroups; ++b) {
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict
     const int64_t key = valid ? (int64_t)acc[threadIdx.x] : 0;
     const int64_t alen = valid ? rp[threadIdx.x + 1] - rp[threadIdx.x] : 0;
     if (valid) ip[P.row_base + blk.i0 + threadIdx.x] = key;
-    block_histogram(key, alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, true);
+    block_histogram(key, alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, true, P.n);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__restrict__ prods,
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__res
     const ProdDev &P = prods[blk.p];
     const bool valid = threadIdx.x < blk.nrows;
     const int64_t k = valid ? key[P.row_base + blk.i0 + threadIdx.x] : 0;
-    block_histogram(k, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false);
+    block_histogram(k, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false, INT64_MAX);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict__ prods,
@@ -271,13 +275,16 @@ __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict
                                                         const int64_t *__restrict__ key,
                                                         const int64_t *__restrict__ off,
                                                         uint64_t *__restrict__ map,
-                                                        int32_t *__restrict__ hslot) {
+                                                        int32_t *__restrict__ hslot,
+                                                        int cap_to_ncols) {
     __shared__ int wcnt[kRowBlock / 64][kGroups];
     const RowBlk blk = blks[blockIdx.x];
     const ProdDev &P = prods[blk.p];
     const bool valid = threadIdx.x < blk.nrows;
     const int64_t row = blk.i0 + threadIdx.x;
-    const int g = valid ? group_of(key[P.row_base + row], gb) : -1;
+    int64_t k = valid ? key[P.row_base + row] : 0;
+    if (cap_to_ncols && k > P.n) k = P.n;
+    const int g = valid ? group_of(k, gb) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int rank = 0;
@@ -400,10 +407,10 @@ void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk, Gro
 
 void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
                     const int64_t *key, const int64_t *off, uint64_t *map, int32_t *hslot,
-                    hipStream_t s) {
+                    bool cap_to_ncols, hipStream_t s) {
     if (nblk == 0) return;
     hipLaunchKernelGGL(k_scatter, dim3(nblk), dim3(kRowBlock), 0, s, prods, blks, nblk, gb, key,
-                       off, map, hslot);
+                       off, map, hslot, cap_to_ncols ? 1 : 0);
 }
 
 void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStream_t s) {

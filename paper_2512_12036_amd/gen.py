@@ -304,3 +304,115 @@ def skewed_csr(nrows: int, ncols: int, seed: int, max_len: int,
         cols = np.zeros(0, dtype=np.int64)
     vals = rng.uniform(-1.0, 1.0, size=rows.shape[0]).astype(np.float32)
     return from_coo(nrows, ncols, rows, cols, vals, merge=False)
+
+
+# ---------------------------------------------------------------------------
+# Device-agnostic generator for the served workload.  Built from torch integer
+# and float64 operations whose results are exact (wrapping 64-bit integer
+# arithmetic, correctly rounded float64 sqrt and division, exact conversions),
+# so the same seed yields bit-identical matrices on the CPU and on the GPU:
+# requests are generated in device memory for serving, and any of them can be
+# regenerated on the host for the oracle.
+
+def _i64(v: int) -> int:
+    """An unsigned 64-bit constant as the equal-bits signed value."""
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+_SM_GAMMA = _i64(0x9E3779B97F4A7C15)
+_SM_M1 = _i64(0xBF58476D1CE4E5B9)
+_SM_M2 = _i64(0x94D049BB133111EB)
+
+
+def _lsr(x, s: int):
+    """Logical right shift of an int64 tensor."""
+    return (x >> s) & ((1 << (64 - s)) - 1)
+
+
+def hash64(x):
+    """SplitMix64 finaliser of (x + golden gamma), elementwise on an int64
+    tensor (Steele, Lea and Flood, OOPSLA 2014)."""
+    z = x + _SM_GAMMA
+    z = (z ^ _lsr(z, 30)) * _SM_M1
+    z = (z ^ _lsr(z, 27)) * _SM_M2
+    return z ^ _lsr(z, 31)
+
+
+def _stream(seed: int, tag: int, n: int, device):
+    import torch
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    off = ((((seed & 0xFFFFFFFF) << 24) + (tag << 2) + 1) * 0x100000001) % (1 << 64)
+    return hash64(idx * 4 + _i64(off))
+
+
+def _unit_open_low_t(h):
+    """(0, 1] with 24 random bits: k / 2^24, k in [1, 2^24] (exact in FP32)."""
+    import torch
+    return ((_lsr(h, 40) + 1).to(torch.float64) * (1.0 / (1 << 24))).to(torch.float32)
+
+
+@dataclasses.dataclass
+class TorchCsr:
+    nrows: int
+    ncols: int
+    rpt: "object"  # int64 [nrows + 1]
+    col: "object"  # int32 [nnz]
+    val: "object"  # float32 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def to_host(self) -> Csr:
+        return Csr(self.nrows, self.ncols, self.rpt.cpu().numpy(), self.col.cpu().numpy(),
+                   self.val.cpu().numpy())
+
+
+def gnn_request_t(seed: int, device="cpu", n: int | None = None, d: float | None = None,
+                  f: int | None = None, rho: float | None = None):
+    """The served aggregation request C = A_hat X for `seed`, built on
+    `device`: A_hat = D^-1/2 (A + I) D^-1/2 of an undirected graph with
+    round(n d / 2) distinct random edges (the first distinct ones of a hashed
+    stream of vertex pairs), X with round(rho f) kept columns (dense, values in
+    (0, 1]) and all other columns zero.  Returns (A_hat, X, (n, d, f, rho))."""
+    import torch
+    pn, pd, pf, prho = gnn_request_params(seed)
+    n = pn if n is None else n
+    d = pd if d is None else d
+    f = pf if f is None else f
+    rho = prho if rho is None else rho
+    m_edges = min(int(round(n * d / 2.0)), n * (n - 1) // 2)
+    cand = int(m_edges * 1.15) + 64
+    hu = _stream(seed, 1, cand, device)
+    hv = _stream(seed, 2, cand, device)
+    u = _lsr(hu, 1) % n
+    v = _lsr(hv, 1) % n
+    ok = u != v
+    u, v = u[ok], v[ok]
+    key = torch.minimum(u, v) * n + torch.maximum(u, v)
+    uniq, inv = torch.unique(key, return_inverse=True)
+    pos = torch.arange(key.shape[0], dtype=torch.int64, device=device)
+    first = torch.full((uniq.shape[0],), key.shape[0], dtype=torch.int64, device=device)
+    first = first.scatter_reduce(0, inv, pos, reduce="amin")
+    order = torch.argsort(first)[:m_edges]
+    edges = uniq[order]
+    eu, ev = edges // n, edges % n
+    diag = torch.arange(n, dtype=torch.int64, device=device)
+    rows = torch.cat([eu, ev, diag])
+    cols = torch.cat([ev, eu, diag])
+    k2, _ = torch.sort(rows * n + cols)
+    rows, cols = k2 // n, k2 % n
+    cnt = torch.bincount(rows, minlength=n)
+    rpt = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rpt[1:] = torch.cumsum(cnt, 0)
+    deg = cnt.to(torch.float64)
+    val = (1.0 / torch.sqrt(deg[rows] * deg[cols])).to(torch.float32)
+    a_hat = TorchCsr(n, n, rpt, cols.to(torch.int32), val)
+    nk = max(1, int(round(rho * f)))
+    rank = torch.argsort(_stream(seed, 3, f, device))
+    kept = torch.sort(rank[:nk])[0].to(torch.int32)
+    xrpt = torch.arange(n + 1, dtype=torch.int64, device=device) * nk
+    xcol = kept.repeat(n)
+    xval = _unit_open_low_t(_stream(seed, 4, n * nk, device))
+    x = TorchCsr(n, f, xrpt, xcol, xval)
+    return a_hat, x, (n, d, f, rho)

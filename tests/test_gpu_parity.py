@@ -160,7 +160,9 @@ def test_ip_and_maps_bit_exact():
         ip, _ = plan.export(0)
         assert np.array_equal(ip.cpu().numpy(), oracle.ip(a, a))
         m, gs = plan.export(1)
-        _, order, offs = oracle.bins_reference(oracle.ip(a, a), list(opt.sym_upper))
+        # symbolic key: intermediate products capped at B's column count
+        key = np.minimum(oracle.ip(a, a), a.ncols)
+        _, order, offs = oracle.bins_reference(key, list(opt.sym_upper))
         mm = m.cpu().numpy()
         assert np.all((mm >> 32) == 0)
         assert np.array_equal(mm & 0xffffffff, order)
@@ -178,6 +180,26 @@ def test_ip_and_maps_bit_exact():
     finally:
         plan.free()
     torch.cuda.synchronize()
+
+
+def test_symbolic_key_capped_at_columns():
+    # B with few columns: rows with many intermediate products but at most
+    # ncols(B) outputs take a small-table group
+    a = gen.skewed_csr(3000, 2000, seed=51, max_len=40, heavy_rows=5, heavy_len=1500)
+    b = gen.random_csr(2000, 100, 0.3, 52)
+    da, db = spgemm.to_device(a), spgemm.to_device(b)
+    opt = spgemm.default_options()
+    plan = spgemm.Plan(da, db, opt)
+    try:
+        m, gs = plan.export(1)
+        key = np.minimum(oracle.ip(a, b), b.ncols)
+        _, order, offs = oracle.bins_reference(key, list(opt.sym_upper))
+        assert np.array_equal(m.cpu().numpy() & 0xffffffff, order)
+        assert gs == offs.tolist()
+        assert gs[7] == gs[8]      # no chunked rows although IP reaches ~10^4
+    finally:
+        plan.free()
+    run_and_compare(a, b, label="capped-key")
 
 
 def test_value_only_rerun():
