@@ -602,7 +602,7 @@ void spgemm_default_options(spgemm_options *opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     // tuned on gfx950 (R-MAT scale 18 self-product; see the autotuner)
-    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 4096, 4096};
+    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 4096};
     const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 4096};
     for (int g = 0; g < kGroups - 1; ++g) {
         opt->sym_upper[g] = sym[g];

@@ -60,6 +60,66 @@ __device__ __forceinline__ void lds_add(int *tab, float *vals, uint32_t mask, in
     atomicOr(err, kErrProbe);
 }
 
+// Slot of key c in the table, inserting it when absent (linear probing from
+// slot h); -1 after the probe guard tripped.
+__device__ __forceinline__ int lds_slot(int *tab, uint32_t mask, uint32_t h, int c, int *err) {
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const int cur = tab[h];
+        if (cur == c) return (int)h;
+        if (cur == kEmptyKey) {
+            const int old = atomicCAS(&tab[h], kEmptyKey, c);
+            if (old == kEmptyKey || old == c) return (int)h;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicOr(err, kErrProbe);
+    return -1;
+}
+
+// Batched forms of lds_insert / lds_add for U products of a lane: the home
+// slots of all U keys are read before any is compared, so the common case
+// (key already at its home slot) costs one LDS round trip for all U; the
+// rest take the probing path one by one.  For the accumulation the values
+// then go through lds_fadd_many; unused entries (ok false) add 0 to the
+// lane's private dummy slot `dummy` of vals.
+template <int U>
+__device__ __forceinline__ int lds_insert_many(int *tab, uint32_t mask, int log2T, const int *cc,
+                                               const bool *ok, int *err) {
+    int k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) k[u] = ok[u] ? tab[hash_slot(cc[u], log2T)] : 0;
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u] && k[u] != cc[u]) cnt += lds_insert(tab, mask, log2T, cc[u], err);
+    return cnt;
+}
+
+template <int U>
+__device__ __forceinline__ void lds_add_many(int *tab, float *vals, uint32_t mask, int log2T,
+                                             const int *cc, const float *add, const bool *ok,
+                                             int dummy, int *err) {
+    uint32_t h[U];
+    int k[U], slot[U];
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        h[u] = hash_slot(cc[u], log2T);
+        k[u] = ok[u] ? tab[h[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int sl = dummy;
+        if (ok[u]) {
+            sl = k[u] == cc[u] ? (int)h[u] : lds_slot(tab, mask, h[u], cc[u], err);
+            if (sl < 0) sl = dummy;
+        }
+        slot[u] = sl;
+        v[u] = sl != dummy ? add[u] : 0.f;
+    }
+    lds_fadd_many<U>(vals, slot, v);
+}
+
 template <int N>
 struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
 template <>
@@ -82,7 +142,7 @@ __device__ __forceinline__ int ceil_log2(int64_t x) {
 // row by walking forward through the staged prefix, one LDS read per B-row
 // boundary crossed.  A group lives inside one wave, so its LDS traffic is
 // ordered without a barrier.  Group-uniform control flow; U products per lane
-// per round so that U gathers per lane are in flight.
+// per round (U gathers in flight), handed to f(cc, aa, vv, ok) as arrays.
 template <int G, int U, bool VALUES, typename F>
 __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int lane,
                                                int64_t *gs_s, int *gs_e, float *gs_a, F &&f) {
@@ -141,9 +201,7 @@ __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int 
                     aa[u] = av;
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) f(cc[u], aa[u], vv[u]);
+            f(cc, aa, vv, ok);
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // staging reads done
     }
@@ -169,8 +227,8 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     int *tab = keys + gi * T;
     int cnt = 0;
     group_products<G, 4, false>(P, i, lane, st_s + gi * G, st_e + gi * (G + 1), nullptr,
-                                [&](int c, float, float) {
-                                    cnt += lds_insert(tab, T - 1, LOG2T, c, err);
+                                [&](const int *cc, const float *, const float *, const bool *ok) {
+                                    cnt += lds_insert_many<4>(tab, T - 1, LOG2T, cc, ok, err);
                                 });
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, G);
@@ -184,25 +242,30 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
                                                     int *__restrict__ err) {
     constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v, PER = T / G;
     __shared__ int keys[R * T];
-    __shared__ float vals[R * T];
+    __shared__ float vals[R * (T + G)];  // per group: T slots + G dummy slots
     __shared__ int64_t st_s[256];
     __shared__ int st_e[R * (G + 1)];
     __shared__ float st_a[256];
-    for (int s = threadIdx.x; s < R * T; s += 256) { keys[s] = kEmptyKey; vals[s] = 0.f; }
+    for (int s = threadIdx.x; s < R * T; s += 256) keys[s] = kEmptyKey;
+    for (int s = threadIdx.x; s < R * (T + G); s += 256) vals[s] = 0.f;
     __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t it = (int64_t)blockIdx.x * R + gi;
     const bool active = it < count;
     int *tab = keys + gi * T;
-    float *tv = vals + gi * T;
+    float *tv = vals + gi * (T + G);
     uint64_t e = 0;
     if (active) {
         e = items[it];
         const ProdDev &P = prods[item_prod(e)];
-        group_products<G, 4, true>(P, item_row(e), lane, st_s + gi * G, st_e + gi * (G + 1),
-                                   st_a + gi * G, [&](int c, float a, float b) {
-                                       lds_add(tab, tv, T - 1, LOG2T, c, a * b, err);
-                                   });
+        group_products<G, 4, true>(
+            P, item_row(e), lane, st_s + gi * G, st_e + gi * (G + 1), st_a + gi * G,
+            [&](const int *cc, const float *aa, const float *vb, const bool *ok) {
+                float add[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) add[u] = aa[u] * vb[u];
+                lds_add_many<4>(tab, tv, T - 1, LOG2T, cc, add, ok, T + lane, err);
+            });
     }
     __syncthreads();
     // gather: each lane owns slots lane + G*r
@@ -280,8 +343,8 @@ __device__ __forceinline__ void block_products(const ProdDev &P, int64_t i, int6
         if (VALUES) st_a[threadIdx.x] = a;
         __syncthreads();
         const int nv = (int)((a1 - jb) < WG ? (a1 - jb) : WG);
-        staged_products<WG, U, VALUES, int, int64_t>(st_s, st_e, st_a, nv, total, P.colB, P.valB,
-                                                     f);
+        striped_products<WG, U, VALUES, int, int64_t>(st_s, st_e, st_a, nv, total, P.colB,
+                                                      P.valB, f);
         __syncthreads();
     }
 }
@@ -313,8 +376,8 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
     __syncthreads();
     int cnt = 0;
     block_products<WG, 8, false>(P, i, st_s, st_e, (float *)nullptr, wsum,
-                                 [&](int c, float, float) {
-                                     cnt += lds_insert(keys, T - 1, log2T, c, err);
+                                 [&](const int *cc, const float *, const float *, const bool *ok) {
+                                     cnt += lds_insert_many<8>(keys, T - 1, log2T, cc, ok, err);
                                  });
     const int tot = block_sum<WG, int>(cnt, wsum);
     if (threadIdx.x == 0) row_nnz[g] = tot;
@@ -326,7 +389,7 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
                                                    const int64_t *__restrict__ rptv,
                                                    int *__restrict__ err) {
     __shared__ int keys[TMAX];
-    __shared__ float vals[TMAX];
+    __shared__ float vals[TMAX + 64];
     __shared__ int64_t st_s[WG];
     __shared__ int st_e[WG + 1];
     __shared__ float st_a[WG];
@@ -346,11 +409,18 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
         return;
     }
     for (int s = threadIdx.x; s < T; s += WG) { keys[s] = kEmptyKey; vals[s] = 0.f; }
+    if (threadIdx.x < 64) vals[T + threadIdx.x] = 0.f;  // dummy slots of the batched adds
     if (threadIdx.x == 0) fill = 0;
     __syncthreads();
-    block_products<WG, 8, true>(P, i, st_s, st_e, st_a, wsum, [&](int c, float a, float b) {
-        lds_add(keys, vals, T - 1, log2T, c, a * b, err);
-    });
+    const int dummy = T + (threadIdx.x & 63);
+    block_products<WG, 8, true>(
+        P, i, st_s, st_e, st_a, wsum,
+        [&](const int *cc, const float *aa, const float *vb, const bool *ok) {
+            float add[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) add[u] = aa[u] * vb[u];
+            lds_add_many<8>(keys, vals, T - 1, log2T, cc, add, ok, dummy, err);
+        });
     // gather occupied slots to the front, in place, one WG-wide round at a time
     const int lane = threadIdx.x & 63;
     const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
