@@ -96,7 +96,9 @@ typedef struct {
      * columns of B) -- both bound the row's distinct outputs; paper Table I
      * uses the first -- and numeric groups by the row's output length (paper
      * Section III-C: the table size is first set from the intermediate
-     * products, then from the distinct count).  Non-decreasing.  Capacities (maximum legal bound):
+     * products, then from the distinct count), raised to ceil(products / 16)
+     * capped at B's columns, so rows with many products per output get more
+     * lanes.  Non-decreasing.  Capacities (maximum legal bound):
      *   symbolic: 63, 127, 255, 511, 8191, 32767
      *   numeric : 63, 127, 255, 511, 2047, 8191
      * and sym_upper[6] <= num_upper[6] (a row handled as chunks in the

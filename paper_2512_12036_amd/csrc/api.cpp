@@ -347,7 +347,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         TimeScope ts(p, "plan.group");
         ST_TRY(scan(p, p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk));
         launch_scatter(p->dprods, p->dblks, p->nblk, gb, p->ip, p->blkoff, p->map_sym, p->hslot,
-                       true, p->stream);
+                       nullptr, p->stream);
         launch_group_starts(p->blkoff, p->nblk, p->starts, p->stream);
     }
     ST_TRY(launch_check());
@@ -501,12 +501,12 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     const GroupBounds gb = bounds_of(p->opt.num_upper);
     {
         TimeScope ts(p, "sym.regroup");
-        launch_count_groups(p->dprods, p->dblks, p->nblk, gb, p->row_nnz, p->blkcnt, p->stats,
+        launch_count_groups(p->dprods, p->dblks, p->nblk, gb, p->row_nnz, p->ip, p->blkcnt, p->stats,
                             st);
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk));
         launch_scatter(p->dprods, p->dblks, p->nblk, gb, p->row_nnz, p->blkoff, p->map_num,
-                       nullptr, false, st);
+                       nullptr, p->ip, st);
         launch_group_starts(p->blkoff, p->nblk, p->starts + (kGroups + 1), st);
     }
     ST_TRY(launch_check());

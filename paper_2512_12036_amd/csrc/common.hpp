@@ -10,7 +10,8 @@ namespace spg {
 
 constexpr int kGroups = 8;           // row groups, see spgemm.h
 constexpr int kChunkGroup = 7;       // column-chunked group
-constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 accumulator + 32 KiB flags
+constexpr int64_t kIpPerLane = 16;   // numeric grouping: target products per lane
+constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 dense accumulator
 constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
 // Largest key each group can take (tables at most half full).
 constexpr int64_t kSymCap[kGroups] = {0, 32, 64, 128, 256, 4096, 16384, 0};
@@ -110,13 +111,12 @@ void launch_validate_cols(const CsrCheck &c, int *bad, hipStream_t s);
 void launch_ipcount(const ProdDev *prods, const RowBlk *blks, int nblk,
                     GroupBounds gb, int64_t *ip, int64_t *blkcnt, ProdStats *stats,
                     hipStream_t s);
-void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk,
-                         GroupBounds gb, const int64_t *key, int64_t *blkcnt,
+void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
+                         const int64_t *key, const int64_t *ip, int64_t *blkcnt,
                          ProdStats *stats, hipStream_t s);
-void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk,
-                    GroupBounds gb, const int64_t *key, const int64_t *off,
-                    uint64_t *map, int32_t *hslot, bool cap_to_ncols,
-                    hipStream_t s);
+void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
+                    const int64_t *key, const int64_t *off, uint64_t *map, int32_t *hslot,
+                    const int64_t *ip, hipStream_t s);
 void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStream_t s);
 
 // Chunk preparation (group 7).

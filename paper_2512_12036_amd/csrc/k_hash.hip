@@ -120,6 +120,35 @@ __device__ __forceinline__ void lds_add_many(int *tab, float *vals, uint32_t mas
     lds_fadd_many<U>(vals, slot, v);
 }
 
+// Direct-mapped forms, for rows whose B has no more columns than the table
+// has slots: the slot of column c is c itself -- no hashing, no probing, and
+// the occupied slots are already in column order, so no sort follows.
+template <int U>
+__device__ __forceinline__ int lds_mark_many(int *tab, const int *cc, const bool *ok) {
+    int k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) k[u] = ok[u] ? tab[cc[u]] : 0;
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u] && k[u] != cc[u]) cnt += atomicCAS(&tab[cc[u]], kEmptyKey, cc[u]) == kEmptyKey;
+    return cnt;
+}
+
+template <int U>
+__device__ __forceinline__ void lds_add_direct_many(int *tab, float *vals, const int *cc,
+                                                    const float *add, const bool *ok, int dummy) {
+    int slot[U];
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        slot[u] = ok[u] ? cc[u] : dummy;
+        v[u] = ok[u] ? add[u] : 0.f;
+        if (ok[u]) tab[cc[u]] = cc[u];  // every writer stores the same key
+    }
+    lds_fadd_many<U>(vals, slot, v);
+}
+
 template <int N>
 struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
 template <>
@@ -226,9 +255,12 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     const int64_t i = item_row(e);
     int *tab = keys + gi * T;
     int cnt = 0;
+    const bool direct = P.n <= T;
     group_products<G, 4, false>(P, i, lane, st_s + gi * G, st_e + gi * (G + 1), nullptr,
                                 [&](const int *cc, const float *, const float *, const bool *ok) {
-                                    cnt += lds_insert_many<4>(tab, T - 1, LOG2T, cc, ok, err);
+                                    cnt += direct ? lds_mark_many<4>(tab, cc, ok)
+                                                  : lds_insert_many<4>(tab, T - 1, LOG2T, cc,
+                                                                       ok, err);
                                 });
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, G);
@@ -255,27 +287,34 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     int *tab = keys + gi * T;
     float *tv = vals + gi * (T + G);
     uint64_t e = 0;
+    bool direct = false;
     if (active) {
         e = items[it];
         const ProdDev &P = prods[item_prod(e)];
+        direct = P.n <= T;
         group_products<G, 4, true>(
             P, item_row(e), lane, st_s + gi * G, st_e + gi * (G + 1), st_a + gi * G,
             [&](const int *cc, const float *aa, const float *vb, const bool *ok) {
                 float add[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) add[u] = aa[u] * vb[u];
-                lds_add_many<4>(tab, tv, T - 1, LOG2T, cc, add, ok, T + lane, err);
+                if (direct)
+                    lds_add_direct_many<4>(tab, tv, cc, add, ok, T + lane);
+                else
+                    lds_add_many<4>(tab, tv, T - 1, LOG2T, cc, add, ok, T + lane, err);
             });
     }
     __syncthreads();
-    // gather: each lane owns slots lane + G*r
+    // gather: in hash mode each lane owns slots lane + G*r; direct-mapped, the
+    // contiguous slots lane*PER + r, so the scan below yields column order
     int kk[PER];
     float vv[PER];
     int mine = 0;
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        kk[r] = tab[lane + G * r];
-        vv[r] = tv[lane + G * r];
+        const int q = direct ? lane * PER + r : lane + G * r;
+        kk[r] = tab[q];
+        vv[r] = tv[q];
         mine += kk[r] != kEmptyKey;
     }
     int incl = mine;
@@ -287,7 +326,7 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     const int n = __shfl(incl, G - 1, G);
     int pos = incl - mine;
     __syncthreads();
-    if (active) {
+    if (active && !direct) {
 #pragma unroll
         for (int r = 0; r < PER; ++r)
             if (kk[r] != kEmptyKey) { tab[pos] = kk[r]; ++pos; }
@@ -298,6 +337,20 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     const int64_t g = P.row_base + item_row(e);
     const int64_t expect = rptv[g + 1] - rptv[g];
     if (lane == 0 && n != expect) atomicOr(err, kErrCount);
+    if (direct) {  // already in column order
+        const int64_t base = rptv[g] - rptv[P.row_base];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            if (kk[r] != kEmptyKey) {
+                if (pos < expect) {
+                    gst(P.colC + base + pos, kk[r]);
+                    gst(P.valC + base + pos, vv[r]);
+                }
+                ++pos;
+            }
+        }
+        return;
+    }
     // rank of each held key among the n gathered keys (keys are distinct)
     int rank[PER];
 #pragma unroll
@@ -364,11 +417,13 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
     const int64_t i = item_row(e);
     const int64_t g = P.row_base + i;
     int64_t bound = ipv[g] < P.n ? ipv[g] : P.n;
-    int log2T = ceil_log2(2 * bound);
+    // direct-mapped (slot = column) when B's columns fit the table
+    const bool direct = P.n <= TMAX;
+    int log2T = ceil_log2(direct ? P.n : 2 * bound);
     if (log2T < 8) log2T = 8;
     if (log2T > Log2<TMAX>::v) log2T = Log2<TMAX>::v;
     const int T = 1 << log2T;
-    if (bound >= T) {  // cannot happen with validated bounds
+    if (!direct && bound >= T) {  // cannot happen with validated bounds
         if (threadIdx.x == 0) atomicOr(err, kErrRow);
         return;
     }
@@ -377,7 +432,9 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
     int cnt = 0;
     block_products<WG, 8, false>(P, i, st_s, st_e, (float *)nullptr, wsum,
                                  [&](const int *cc, const float *, const float *, const bool *ok) {
-                                     cnt += lds_insert_many<8>(keys, T - 1, log2T, cc, ok, err);
+                                     cnt += direct ? lds_mark_many<8>(keys, cc, ok)
+                                                   : lds_insert_many<8>(keys, T - 1, log2T, cc,
+                                                                        ok, err);
                                  });
     const int tot = block_sum<WG, int>(cnt, wsum);
     if (threadIdx.x == 0) row_nnz[g] = tot;
@@ -400,11 +457,13 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     const int64_t i = item_row(e);
     const int64_t g = P.row_base + i;
     const int64_t expect = rptv[g + 1] - rptv[g];
-    int log2T = ceil_log2(2 * expect);
+    // direct-mapped (slot = column) when B's columns fit the table
+    const bool direct = P.n <= TMAX;
+    int log2T = ceil_log2(direct ? P.n : 2 * expect);
     if (log2T < 8) log2T = 8;
     if (log2T > Log2<TMAX>::v) log2T = Log2<TMAX>::v;
     const int T = 1 << log2T;
-    if (expect >= T) {
+    if (!direct && expect >= T) {
         if (threadIdx.x == 0) atomicOr(err, kErrRow);
         return;
     }
@@ -419,8 +478,31 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
             float add[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) add[u] = aa[u] * vb[u];
-            lds_add_many<8>(keys, vals, T - 1, log2T, cc, add, ok, dummy, err);
+            if (direct)
+                lds_add_direct_many<8>(keys, vals, cc, add, ok, dummy);
+            else
+                lds_add_many<8>(keys, vals, T - 1, log2T, cc, add, ok, dummy, err);
         });
+    if (direct) {
+        // the occupied slots are the row's columns in order: a scan of the
+        // occupancy places them, no compaction or sort
+        const int64_t base = rptv[g] - rptv[P.row_base];
+        int done = 0;
+        for (int r0 = 0; r0 < T; r0 += WG) {
+            const int q = r0 + threadIdx.x;
+            const bool occ = q < T && keys[q] != kEmptyKey;
+            const float v = occ ? vals[q] : 0.f;
+            int total;
+            const int at = done + block_excl_scan<WG, int>(occ ? 1 : 0, wsum, total);
+            if (occ && at < expect) {
+                gst(P.colC + base + at, q);
+                gst(P.valC + base + at, v);
+            }
+            done += total;
+        }
+        if (threadIdx.x == 0 && done != expect) atomicOr(err, kErrCount);
+        return;
+    }
     // gather occupied slots to the front, in place, one WG-wide round at a time
     const int lane = threadIdx.x & 63;
     const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;

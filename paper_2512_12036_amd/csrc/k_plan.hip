@@ -138,21 +138,35 @@ __device__ __forceinline__ int lds_upper_row(const int64_t *rp, int n, int64_t j
     return lo;
 }
 
-// Histogram of groups over the block's rows (one key per thread, valid < nrows)
-// plus per-product sums: keys, max key, and the group-7 (chunked) rows with
-// their A nonzeros, split-table size and chunk count (nch per row).
-// The group is chosen by min(key, gcap): the symbolic grouping caps the
-// intermediate-product count at B's column count, a bound on the row's
-// distinct outputs at least as tight as the count itself.
-__device__ __forceinline__ void block_histogram(int64_t key, int64_t alen, bool valid,
-                                                const GroupBounds &gb, int nblk, int64_t *blkcnt,
-                                                ProdStats *st, int nch, bool ip_stats,
-                                                int64_t gcap) {
+// Grouping keys.  Symbolic: the intermediate-product count capped at B's
+// column count (both bound the row's distinct outputs; the cap is the tighter
+// one when B is narrow).  Numeric: the output length, raised to
+// ceil(IP / kIpPerLane) (capped at B's columns) so that rows with many
+// products per output get more lanes; never above the symbolic key, so a row
+// chunked in the numeric phase was chunked in the symbolic one.
+__device__ __forceinline__ int64_t sym_key(int64_t ip, int64_t ncols) {
+    return ip < ncols ? ip : ncols;
+}
+
+__device__ __forceinline__ int64_t num_key(int64_t nnz, int64_t ip, int64_t ncols) {
+    int64_t k = (ip + kIpPerLane - 1) / kIpPerLane;
+    if (k > ncols) k = ncols;
+    return nnz > k ? nnz : k;
+}
+
+// Histogram of groups over the block's rows (grouped by gkey; one row per
+// thread, valid < nrows) plus per-product sums of `key`: total, max, and the
+// group-7 (chunked) rows with their A nonzeros, split-table size and chunk
+// count (nch per row).
+__device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64_t alen,
+                                                bool valid, const GroupBounds &gb, int nblk,
+                                                int64_t *blkcnt, ProdStats *st, int nch,
+                                                bool ip_stats) {
     __shared__ int hist[kGroups];
     __shared__ unsigned long long red[kRowBlock / 64][4];
     if (threadIdx.x < kGroups) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int g = valid ? group_of(key < gcap ? key : gcap, gb) : -1;
+    const int g = valid ? group_of(gkey, gb) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int b = 0; b < kGroups; ++b) {
@@ -253,20 +267,24 @@ __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict
     const int64_t key = valid ? (int64_t)acc[threadIdx.x] : 0;
     const int64_t alen = valid ? rp[threadIdx.x + 1] - rp[threadIdx.x] : 0;
     if (valid) ip[P.row_base + blk.i0 + threadIdx.x] = key;
-    block_histogram(key, alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, true, P.n);
+    block_histogram(key, sym_key(key, P.n), alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch,
+                    true);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__restrict__ prods,
                                                              const RowBlk *__restrict__ blks,
                                                              int nblk, GroupBounds gb,
                                                              const int64_t *__restrict__ key,
+                                                             const int64_t *__restrict__ ip,
                                                              int64_t *__restrict__ blkcnt,
                                                              ProdStats *__restrict__ stats) {
     const RowBlk blk = blks[blockIdx.x];
     const ProdDev &P = prods[blk.p];
     const bool valid = threadIdx.x < blk.nrows;
-    const int64_t k = valid ? key[P.row_base + blk.i0 + threadIdx.x] : 0;
-    block_histogram(k, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false, INT64_MAX);
+    const int64_t r = P.row_base + blk.i0 + threadIdx.x;
+    const int64_t k = valid ? key[r] : 0;
+    const int64_t gk = valid ? num_key(k, ip[r], P.n) : 0;
+    block_histogram(k, gk, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict__ prods,
@@ -276,14 +294,18 @@ __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict
                                                         const int64_t *__restrict__ off,
                                                         uint64_t *__restrict__ map,
                                                         int32_t *__restrict__ hslot,
-                                                        int cap_to_ncols) {
+                                                        const int64_t *__restrict__ ip) {
     __shared__ int wcnt[kRowBlock / 64][kGroups];
     const RowBlk blk = blks[blockIdx.x];
     const ProdDev &P = prods[blk.p];
     const bool valid = threadIdx.x < blk.nrows;
     const int64_t row = blk.i0 + threadIdx.x;
-    int64_t k = valid ? key[P.row_base + row] : 0;
-    if (cap_to_ncols && k > P.n) k = P.n;
+    int64_t k = 0;
+    if (valid) {
+        // ip NULL: key holds IP (symbolic map); else key holds output lengths
+        k = key[P.row_base + row];
+        k = ip ? num_key(k, ip[P.row_base + row], P.n) : sym_key(k, P.n);
+    }
     const int g = valid ? group_of(k, gb) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -399,18 +421,19 @@ void launch_ipcount(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBou
 }
 
 void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
-                         const int64_t *key, int64_t *blkcnt, ProdStats *stats, hipStream_t s) {
+                         const int64_t *key, const int64_t *ip, int64_t *blkcnt,
+                         ProdStats *stats, hipStream_t s) {
     if (nblk == 0) return;
     hipLaunchKernelGGL(k_count_groups, dim3(nblk), dim3(kRowBlock), 0, s, prods, blks, nblk, gb,
-                       key, blkcnt, stats);
+                       key, ip, blkcnt, stats);
 }
 
 void launch_scatter(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
                     const int64_t *key, const int64_t *off, uint64_t *map, int32_t *hslot,
-                    bool cap_to_ncols, hipStream_t s) {
+                    const int64_t *ip, hipStream_t s) {
     if (nblk == 0) return;
     hipLaunchKernelGGL(k_scatter, dim3(nblk), dim3(kRowBlock), 0, s, prods, blks, nblk, gb, key,
-                       off, map, hslot, cap_to_ncols ? 1 : 0);
+                       off, map, hslot, ip);
 }
 
 void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStream_t s) {

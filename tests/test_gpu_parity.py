@@ -170,7 +170,9 @@ def test_ip_and_maps_bit_exact():
         plan.symbolic()
         m2, gs2 = plan.export(2)
         counts = oracle.row_counts(a, a)
-        _, order2, offs2 = oracle.bins_reference(counts, list(opt.num_upper))
+        # numeric key: output length, raised to ceil(IP / 16) capped at B's columns
+        key2 = np.maximum(counts, np.minimum((oracle.ip(a, a) + 15) // 16, a.ncols))
+        _, order2, offs2 = oracle.bins_reference(key2, list(opt.num_upper))
         assert np.array_equal(m2.cpu().numpy() & 0xffffffff, order2)
         assert gs2 == offs2.tolist()
         assert np.array_equal(np.diff(plan.rpts[0].cpu().numpy()), counts)
@@ -200,6 +202,17 @@ def test_symbolic_key_capped_at_columns():
     finally:
         plan.free()
     run_and_compare(a, b, label="capped-key")
+
+
+@pytest.mark.parametrize("group", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("ncols", [48, 200, 1000])
+def test_direct_mapped_tables(group, ncols):
+    # B with few columns: tables indexed by the column itself where they fit
+    a = gen.int_valued(gen.skewed_csr(1200, 900, seed=60 + group, max_len=30, heavy_rows=2,
+                                      heavy_len=600), 3)
+    b = gen.int_valued(gen.random_csr(900, ncols, min(0.5, 40.0 / ncols), 61 + group), 4)
+    run_and_compare(a, b, options=forced_options(group), exact=True,
+                    label=f"direct g{group} n{ncols}")
 
 
 def test_value_only_rerun():
