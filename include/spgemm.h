@@ -231,6 +231,45 @@ spgemm_status spgemm_export(const spgemm_plan *p, int32_t what, void *dst,
 int32_t spgemm_timing_count(const spgemm_plan *p);
 spgemm_status spgemm_timing(spgemm_plan *p, int32_t idx, const char **name, float *ms);
 
+/* ------------------------------------------------------------------------
+ * Device steps of the applications that chain products (paper Section V).
+ * ------------------------------------------------------------------------ */
+
+/* Graph contraction (paper Algorithm 7) contracts with the selector S, n x k,
+ * S[v, labels[v]] = 1.  This builds its transpose S^T (k x n) by a counting
+ * sort of the labels: row_ptr (k + 1 int64), col_idx (n int32: the vertices
+ * of cluster l, in no fixed order inside the row, so the result is not
+ * SPGEMM_ROWS_SORTED), values (n FP32, all 1).  labels: n int32 in [0, k).
+ * All arrays are device memory owned by the caller; `workspace` is a device
+ * buffer of spgemm_selector_transpose_workspace(k) bytes.  Enqueued on
+ * `stream`, then synchronises it to report EINDEX for a label outside
+ * [0, k).  EINVAL for NULL pointers or negative sizes. */
+size_t spgemm_selector_transpose_workspace(int64_t k);
+spgemm_status spgemm_selector_transpose(const int32_t *labels, int64_t n, int64_t k,
+                                        int64_t *row_ptr, int32_t *col_idx, float *values,
+                                        void *workspace, void *stream);
+
+/* Markov clustering (paper Algorithm 6) after each expansion, on the
+ * row-stochastic transpose of the column-stochastic matrix (the paper's
+ * column operations become row operations): every entry x becomes x^power,
+ * each row is divided by its sum, entries below theta are dropped (strictly:
+ * y >= theta is kept) and each row is divided by the sum of what it keeps;
+ * kept entries stay in their input order.  Two calls share `workspace`
+ * (spgemm_mcl_prune_workspace(m) bytes of device memory):
+ *   _count writes the m + 1 output row pointers (device) and returns the
+ *          output length in *out_nnz (host; synchronises the stream);
+ *   _write fills out_col / out_val (device, out_nnz entries each).
+ * Arithmetic in FP32.  A row whose entries are all zero keeps nothing.
+ * EINVAL for NULL pointers, negative m, theta < 0 or power <= 0. */
+size_t spgemm_mcl_prune_workspace(int64_t m);
+spgemm_status spgemm_mcl_prune_count(int64_t m, const int64_t *row_ptr, const float *values,
+                                     float power, float theta, int64_t *out_row_ptr,
+                                     void *workspace, int64_t *out_nnz, void *stream);
+spgemm_status spgemm_mcl_prune_write(int64_t m, const int64_t *row_ptr, const int32_t *col_idx,
+                                     const float *values, float power, float theta,
+                                     const int64_t *out_row_ptr, void *workspace,
+                                     int32_t *out_col, float *out_val, void *stream);
+
 /* Releases a plan and its workspace.  NULL-safe.  Waits for the stream. */
 void spgemm_free(spgemm_plan *p);
 

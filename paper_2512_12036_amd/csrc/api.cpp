@@ -759,6 +759,70 @@ spgemm_status spgemm_timing(spgemm_plan *p, int32_t idx, const char **name, floa
     return SPGEMM_OK;
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t spgemm_selector_transpose_workspace(int64_t k) {
+    if (k < 0) return 0;
+    return 256 + align256(sizeof(int64_t) * (size_t)(k + 1)) + align256(scan_temp_bytes(k));
+}
+
+spgemm_status spgemm_selector_transpose(const int32_t *labels, int64_t n, int64_t k,
+                                        int64_t *row_ptr, int32_t *col_idx, float *values,
+                                        void *workspace, void *stream) {
+    if (n < 0 || k < 0 || !row_ptr || !workspace) return SPGEMM_EINVAL;
+    if (n > 0 && (!labels || !col_idx || !values)) return SPGEMM_EINVAL;
+    if (n >= (int64_t(1) << 31)) return SPGEMM_EDIM;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)workspace;
+    int *flag = (int *)w;
+    int64_t *work = (int64_t *)(w + 256);
+    void *tmp = w + 256 + align256(sizeof(int64_t) * (size_t)(k + 1));
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+    launch_selector_t(labels, n, k, row_ptr, col_idx, values, work, tmp, flag, st);
+    ST_TRY(launch_check());
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return h ? SPGEMM_EINDEX : SPGEMM_OK;
+}
+
+size_t spgemm_mcl_prune_workspace(int64_t m) {
+    if (m < 0) return 0;
+    return align256(sizeof(float) * 2 * (size_t)m) + align256(sizeof(int64_t) * (size_t)(m + 1)) +
+           align256(scan_temp_bytes(m));
+}
+
+spgemm_status spgemm_mcl_prune_count(int64_t m, const int64_t *row_ptr, const float *values,
+                                     float power, float theta, int64_t *out_row_ptr,
+                                     void *workspace, int64_t *out_nnz, void *stream) {
+    if (m < 0 || !row_ptr || !out_row_ptr || !workspace || !out_nnz) return SPGEMM_EINVAL;
+    if (!(power > 0.f) || !(theta >= 0.f)) return SPGEMM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)workspace;
+    float *rowsum = (float *)w;
+    int64_t *keep = (int64_t *)(w + align256(sizeof(float) * 2 * (size_t)m));
+    void *tmp = (char *)keep + align256(sizeof(int64_t) * (size_t)(m + 1));
+    launch_mcl_count(m, row_ptr, values, power, theta, rowsum, keep, st);
+    launch_scan_i64(keep, out_row_ptr, m, tmp, st);
+    ST_TRY(launch_check());
+    int64_t nnz = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out_nnz = nnz;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_mcl_prune_write(int64_t m, const int64_t *row_ptr, const int32_t *col_idx,
+                                     const float *values, float power, float theta,
+                                     const int64_t *out_row_ptr, void *workspace,
+                                     int32_t *out_col, float *out_val, void *stream) {
+    if (m < 0 || !row_ptr || !out_row_ptr || !workspace) return SPGEMM_EINVAL;
+    if (!(power > 0.f) || !(theta >= 0.f)) return SPGEMM_EINVAL;
+    launch_mcl_write(m, row_ptr, col_idx, values, power, theta, (const float *)workspace,
+                     out_row_ptr, out_col, out_val, (hipStream_t)stream);
+    return launch_check();
+}
+
 const char *spgemm_status_string(spgemm_status s) {
     switch (s) {
         case SPGEMM_OK: return "ok";

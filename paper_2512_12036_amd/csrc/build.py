@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libspgemm.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["k_plan.hip", "k_hash.hip", "k_chunk.hip", "api.cpp"]
+SOURCES = ["k_plan.hip", "k_hash.hip", "k_chunk.hip", "k_apps.hip", "api.cpp"]
 ARCH = os.environ.get("SPGEMM_ARCH", "gfx950")
 
 

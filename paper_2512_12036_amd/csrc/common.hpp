@@ -165,4 +165,14 @@ void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,
                        int64_t *dst, hipStream_t s);
 
+// Applications (k_apps.hip): transposed selector by counting sort; Markov
+// clustering prune step (count pass, then write pass).
+void launch_selector_t(const int32_t *labels, int64_t n, int64_t k, int64_t *rpt, int32_t *col,
+                       float *val, int64_t *work, void *scan_tmp, int *err, hipStream_t s);
+void launch_mcl_count(int64_t m, const int64_t *rpt, const float *val, float power, float theta,
+                      float *rowsum, int64_t *keep, hipStream_t s);
+void launch_mcl_write(int64_t m, const int64_t *rpt, const int32_t *col, const float *val,
+                      float power, float theta, const float *rowsum, const int64_t *out_rpt,
+                      int32_t *out_col, float *out_val, hipStream_t s);
+
 }  // namespace spg

@@ -54,7 +54,9 @@ STATUS = {0: "SPGEMM_OK", 1: "SPGEMM_EINVAL", 2: "SPGEMM_EDIM", 3: "SPGEMM_EINDE
 EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_batch",
             "spgemm_symbolic", "spgemm_symbolic_batch", "spgemm_numeric",
             "spgemm_numeric_batch", "spgemm_sync", "spgemm_get_info", "spgemm_export",
-            "spgemm_timing_count", "spgemm_timing", "spgemm_free", "spgemm_status_string"]
+            "spgemm_timing_count", "spgemm_timing", "spgemm_free", "spgemm_status_string",
+            "spgemm_selector_transpose_workspace", "spgemm_selector_transpose",
+            "spgemm_mcl_prune_workspace", "spgemm_mcl_prune_count", "spgemm_mcl_prune_write"]
 
 
 class SpgemmError(RuntimeError):
@@ -99,9 +101,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spgemm_free.restype = None
     lib.spgemm_status_string.argtypes = [ctypes.c_int]
     lib.spgemm_status_string.restype = ctypes.c_char_p
+    lib.spgemm_selector_transpose_workspace.argtypes = [_I64]
+    lib.spgemm_selector_transpose_workspace.restype = ctypes.c_size_t
+    lib.spgemm_selector_transpose.argtypes = [_VP, _I64, _I64, _VP, _VP, _VP, _VP, _VP]
+    lib.spgemm_mcl_prune_workspace.argtypes = [_I64]
+    lib.spgemm_mcl_prune_workspace.restype = ctypes.c_size_t
+    lib.spgemm_mcl_prune_count.argtypes = [_I64, _VP, _VP, ctypes.c_float, ctypes.c_float, _VP,
+                                           _VP, ctypes.POINTER(_I64), _VP]
+    lib.spgemm_mcl_prune_write.argtypes = [_I64, _VP, _VP, _VP, ctypes.c_float, ctypes.c_float,
+                                           _VP, _VP, _VP, _VP, _VP]
     for name in ("spgemm_plan_create", "spgemm_plan_create_batch", "spgemm_symbolic",
                  "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
-                 "spgemm_sync", "spgemm_get_info", "spgemm_export"):
+                 "spgemm_sync", "spgemm_get_info", "spgemm_export", "spgemm_selector_transpose",
+                 "spgemm_mcl_prune_count", "spgemm_mcl_prune_write"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -379,3 +391,54 @@ def matmul_batch(As, Bs, options: Options | None = None, stream=None):
         return plan.results(cols, vals)
     finally:
         plan.free()
+
+
+def _ptr(t):
+    return _VP(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def selector_transpose(labels, k: int, stream=None) -> DeviceCsr:
+    """S^T (k x n) of the selector S[v, labels[v]] = 1, built on the device
+    (graph contraction, paper Algorithm 7).  labels: int32 device tensor."""
+    torch = _torch()
+    lib = load()
+    dev = labels.device
+    n = int(labels.numel())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rpt = torch.empty(k + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    ws = torch.empty(int(lib.spgemm_selector_transpose_workspace(k)), dtype=torch.uint8,
+                     device=dev)
+    _check(lib.spgemm_selector_transpose(_ptr(labels), n, k, _VP(rpt.data_ptr()),
+                                         _VP(col.data_ptr()), _VP(val.data_ptr()),
+                                         _VP(ws.data_ptr()), _VP(st.cuda_stream)),
+           "spgemm_selector_transpose")
+    return DeviceCsr(k, n, rpt, col[:n], val[:n], False)
+
+
+def mcl_prune(E: DeviceCsr, power: float = 2.0, theta: float = 1e-4, stream=None) -> DeviceCsr:
+    """Markov-clustering step after an expansion, on row-stochastic storage:
+    x -> x^power, row-normalise, drop entries below theta, row-normalise."""
+    torch = _torch()
+    lib = load()
+    dev = E.rpt.device
+    m = E.nrows
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    ws = torch.empty(max(int(lib.spgemm_mcl_prune_workspace(m)), 1), dtype=torch.uint8,
+                     device=dev)
+    rpt = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    nnz = _I64()
+    _check(lib.spgemm_mcl_prune_count(m, _VP(E.rpt.data_ptr()), _ptr(E.val), float(power),
+                                      float(theta), _VP(rpt.data_ptr()), _VP(ws.data_ptr()),
+                                      ctypes.byref(nnz), _VP(st.cuda_stream)),
+           "spgemm_mcl_prune_count")
+    k = int(nnz.value)
+    col = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(k, 1), dtype=torch.float32, device=dev)
+    _check(lib.spgemm_mcl_prune_write(m, _VP(E.rpt.data_ptr()), _ptr(E.col), _ptr(E.val),
+                                      float(power), float(theta), _VP(rpt.data_ptr()),
+                                      _VP(ws.data_ptr()), _VP(col.data_ptr()),
+                                      _VP(val.data_ptr()), _VP(st.cuda_stream)),
+           "spgemm_mcl_prune_write")
+    return DeviceCsr(m, E.ncols, rpt, col[:k], val[:k], E.sorted_rows)
