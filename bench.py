@@ -255,7 +255,7 @@ def run_served(n_req: int):
     reqs = serve.gnn_requests(range(n_req), "cuda")
     torch.cuda.synchronize()
     ip_total = sum(r.ip for r in reqs)
-    srv = serve.Server(budget_bytes=200 << 30, max_batch=64, n_streams=2)
+    srv = serve.Server(budget_bytes=200 << 30, max_batch=64, max_batch_ip=8 << 30, n_streams=4)
     warm = reqs[:min(16, n_req)]
     srv.run(warm)
     serve.run_plain(warm)

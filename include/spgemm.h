@@ -98,7 +98,9 @@ typedef struct {
      * Section III-C: the table size is first set from the intermediate
      * products, then from the distinct count), raised to ceil(products / 16)
      * capped at B's columns, so rows with many products per output get more
-     * lanes.  Non-decreasing.  Capacities (maximum legal bound):
+     * lanes.  When B has at most 512 columns, a row whose key is at most 512
+     * never goes past group 4: its table is then indexed by the column
+     * itself (8 slots x 64 lanes = 512).  Non-decreasing.  Capacities (maximum legal bound):
      *   symbolic: 63, 127, 255, 511, 8191, 32767
      *   numeric : 63, 127, 255, 511, 2047, 8191
      * and sym_upper[6] <= num_upper[6] (a row handled as chunks in the

@@ -11,6 +11,7 @@ namespace spg {
 constexpr int kGroups = 8;           // row groups, see spgemm.h
 constexpr int kChunkGroup = 7;       // column-chunked group
 constexpr int64_t kIpPerLane = 16;   // numeric grouping: target products per lane
+constexpr int64_t kDirectG4 = 512;   // table slots of group 4 (64 lanes x 8)
 constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 dense accumulator
 constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
 // Largest key each group can take (tables at most half full).

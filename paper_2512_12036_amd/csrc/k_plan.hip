@@ -120,11 +120,17 @@ void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, void *temp, hip
 }
 
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int group_of(int64_t key, const GroupBounds &gb) {
+// Group of a row with grouping key `key` in a product whose B has `ncols`
+// columns.  A row that would go past group 4 but whose key and B both fit
+// group 4's table (8 slots x 64 lanes) takes group 4: its table is then
+// direct-mapped (slot = column), which needs no load-factor headroom.
+__device__ __forceinline__ int group_of(int64_t key, const GroupBounds &gb, int64_t ncols) {
     if (key == 0) return 0;
 #pragma unroll
-    for (int t = 1; t < kGroups - 1; ++t)
+    for (int t = 1; t < kGroups - 1; ++t) {
         if (key <= gb.up[t]) return t;
+        if (t == 4 && ncols <= kDirectG4 && key <= kDirectG4) return 4;
+    }
     return kGroups - 1;
 }
 
@@ -161,12 +167,12 @@ __device__ __forceinline__ int64_t num_key(int64_t nnz, int64_t ip, int64_t ncol
 __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64_t alen,
                                                 bool valid, const GroupBounds &gb, int nblk,
                                                 int64_t *blkcnt, ProdStats *st, int nch,
-                                                bool ip_stats) {
+                                                bool ip_stats, int64_t ncols) {
     __shared__ int hist[kGroups];
     __shared__ unsigned long long red[kRowBlock / 64][4];
     if (threadIdx.x < kGroups) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int g = valid ? group_of(gkey, gb) : -1;
+    const int g = valid ? group_of(gkey, gb, ncols) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int b = 0; b < kGroups; ++b) {
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict
     const int64_t alen = valid ? rp[threadIdx.x + 1] - rp[threadIdx.x] : 0;
     if (valid) ip[P.row_base + blk.i0 + threadIdx.x] = key;
     block_histogram(key, sym_key(key, P.n), alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch,
-                    true);
+                    true, P.n);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__restrict__ prods,
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__res
     const int64_t r = P.row_base + blk.i0 + threadIdx.x;
     const int64_t k = valid ? key[r] : 0;
     const int64_t gk = valid ? num_key(k, ip[r], P.n) : 0;
-    block_histogram(k, gk, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false);
+    block_histogram(k, gk, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false, P.n);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict__ prods,
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict
         k = key[P.row_base + row];
         k = ip ? num_key(k, ip[P.row_base + row], P.n) : sym_key(k, P.n);
     }
-    const int g = valid ? group_of(k, gb) : -1;
+    const int g = valid ? group_of(k, gb, P.n) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int rank = 0;

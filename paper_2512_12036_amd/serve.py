@@ -76,7 +76,7 @@ def footprint_bound(a: spgemm.DeviceCsr, b: spgemm.DeviceCsr):
 
 class Server:
     def __init__(self, budget_bytes: int = 200 << 30, max_batch: int = 64,
-                 max_batch_ip: int = 4 << 30, n_streams: int = 2,
+                 max_batch_ip: int = 8 << 30, n_streams: int = 4,
                  options: spgemm.Options | None = None, keep_results: bool = False,
                  device="cuda"):
         import torch
