@@ -69,6 +69,10 @@ struct spgemm_plan {
     int64_t *dnchv = nullptr, *dbase = nullptr;
     int32_t *ditem_row = nullptr;
     ChunkDesc *ndesc = nullptr;
+    // numeric items split by output count: dense ones first (n_dense of them)
+    ChunkDesc *ndesc_split = nullptr;
+    int64_t *dflag = nullptr, *dfpos = nullptr;
+    int64_t n_dense = -1;  // -1: not split
     int wmax = 0;       // widest chunk over the products
     bool fast = true;   // every B sorted with < 2^30 entries (32-bit chunk indexing)
 
@@ -551,6 +555,23 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
                         p->opt.chunks_per_item, p->hslot, p->cbase, p->sbase, p->rptv, p->ndesc,
                         st);
         ST_TRY(launch_check());
+        p->n_dense = -1;
+        if (num_chunk_rank_used(p->fast, p->opt.chunks_per_item, p->opt.num_rank_cap)) {
+            // dense chunks first, then the rank-accumulated ones, so that each
+            // kernel is launched over its own items only
+            ST_TRY(dalloc(p, &p->ndesc_split, nitems));
+            ST_TRY(dalloc(p, &p->dflag, nitems));
+            ST_TRY(dalloc(p, &p->dfpos, nitems + 1));
+            launch_desc_flag(p->ndesc, nitems, p->chunk_cnt, p->opt.num_rank_cap, p->dflag, st);
+            ST_TRY(launch_check());
+            ST_TRY(scan(p, p->dflag, p->dfpos, nitems));
+            launch_desc_split(p->ndesc, nitems, p->dflag, p->dfpos, p->ndesc_split, st);
+            ST_TRY(launch_check());
+            HIP_TRY(hipMemcpyAsync(p->hread, p->dfpos + nitems, sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            p->n_dense = p->hread[0];
+        }
     }
     p->state = 2;
     return SPGEMM_OK;
@@ -577,16 +598,21 @@ spgemm_status numeric_impl(spgemm_plan *p) {
     if (p->nd > 0) {
         const int kper = p->opt.chunks_per_item;
         const bool rank = num_chunk_rank_used(p->fast, kper, p->opt.num_rank_cap);
-        {
+        const bool split = rank && p->n_dense >= 0;
+        const ChunkDesc *dense_desc = split ? p->ndesc_split : p->ndesc;
+        const int64_t n_dense = split ? p->n_dense : p->d_items / kper;
+        if (n_dense > 0) {
             TimeScope ts(p, num_names[7]);
-            launch_num_chunk(p->wmax, p->fast, p->dprods, p->ndesc, p->sabs, p->d_items / kper,
-                             kper, p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc,
+            launch_num_chunk(p->wmax, p->fast, p->dprods, dense_desc, p->sabs, n_dense, kper,
+                             p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc,
                              p->opt.chunk_wgs_per_cu, p->opt.chunk_threads,
                              rank ? p->opt.num_rank_cap : 0, p->flags, st);
         }
         if (rank) {
             TimeScope ts(p, "num.g7r");
-            launch_num_chunk_rank(p->wmax, p->dprods, p->ndesc, p->sabs, p->d_items, p->chunk_cnt,
+            const ChunkDesc *rdesc = split ? p->ndesc_split + p->n_dense : p->ndesc;
+            const int64_t nr = split ? p->d_items - p->n_dense : p->d_items;
+            launch_num_chunk_rank(p->wmax, p->dprods, rdesc, p->sabs, nr, p->chunk_cnt,
                                   p->chunk_pos, p->sbits, p->wpc, p->opt.num_rank_cap, p->flags,
                                   st);
         }
@@ -602,8 +628,8 @@ void spgemm_default_options(spgemm_options *opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     // tuned on gfx950 (R-MAT scale 18 self-product; see the autotuner)
-    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 4096};
-    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 4096};
+    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 2048};
+    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 2048};
     for (int g = 0; g < kGroups - 1; ++g) {
         opt->sym_upper[g] = sym[g];
         opt->num_upper[g] = num[g];

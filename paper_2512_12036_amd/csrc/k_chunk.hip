@@ -828,6 +828,42 @@ static unsigned pipe_grid(int wgs_per_cu, int64_t nitems) {
     return (unsigned)g;
 }
 
+// Splits the numeric chunk items (one chunk per item) into those with more
+// than `cap` outputs, first, and the others, after, keeping the order within
+// each part: flag, exclusive scan of the flags, scatter.
+__global__ void k_desc_flag(const ChunkDesc *__restrict__ desc, int64_t nitems,
+                            const int64_t *__restrict__ chunk_cnt, int64_t cap,
+                            int64_t *__restrict__ flag) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    const ChunkDesc d = desc[it];
+    flag[it] = chunk_cnt[d.slot0 + d.q] > cap ? 1 : 0;
+}
+
+__global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
+                             const int64_t *__restrict__ flag, const int64_t *__restrict__ fpos,
+                             ChunkDesc *__restrict__ out) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    const int64_t ndense = fpos[nitems];
+    const int64_t pos = flag[it] ? fpos[it] : ndense + (it - fpos[it]);
+    out[pos] = desc[it];
+}
+
+void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
+                      int64_t cap, int64_t *flag, hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_desc_flag, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, desc,
+                       nitems, chunk_cnt, cap, flag);
+}
+
+void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
+                       const int64_t *fpos, ChunkDesc *out, hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_desc_split, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s,
+                       desc, nitems, flag, fpos, out);
+}
+
 void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
                    int32_t *bsplit, hipStream_t s) {
     const int64_t n = k_rows * (nch + 1);
