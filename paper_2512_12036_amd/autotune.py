@@ -28,8 +28,8 @@ def candidates(quick: bool = False):
     small = [0, 32, 64, 128, 256]
     out = []
     for cc, cap, sthr in itertools.product([4096, 8192, 16384], [0, 512, 1024, 2048], [64, 128]):
-        out.append(dict(chunk_cols=cc, sym_upper=small + [2048, 2048],
-                        num_upper=small + [2048, 2048], chunks_per_item=1, chunk_wgs_per_cu=0,
+        out.append(dict(chunk_cols=cc, sym_upper=small + [1024, 1024],
+                        num_upper=small + [1024, 1024], chunks_per_item=1, chunk_wgs_per_cu=0,
                         chunk_threads=0, sym_chunk_threads=sthr, num_rank_cap=cap))
     if quick:
         out = [c for c in out if c["chunk_cols"] == 8192 and c["sym_chunk_threads"] == 64]

@@ -565,7 +565,8 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
             launch_desc_flag(p->ndesc, nitems, p->chunk_cnt, p->opt.num_rank_cap, p->dflag, st);
             ST_TRY(launch_check());
             ST_TRY(scan(p, p->dflag, p->dfpos, nitems));
-            launch_desc_split(p->ndesc, nitems, p->dflag, p->dfpos, p->ndesc_split, st);
+            launch_desc_split(p->ndesc, nitems, p->dflag, p->dfpos, p->chunk_cnt, p->chunk_pos,
+                              p->ndesc_split, st);
             ST_TRY(launch_check());
             HIP_TRY(hipMemcpyAsync(p->hread, p->dfpos + nitems, sizeof(int64_t),
                                    hipMemcpyDeviceToHost, st));
@@ -606,15 +607,15 @@ spgemm_status numeric_impl(spgemm_plan *p) {
             launch_num_chunk(p->wmax, p->fast, p->dprods, dense_desc, p->sabs, n_dense, kper,
                              p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc,
                              p->opt.chunk_wgs_per_cu, p->opt.chunk_threads,
-                             rank ? p->opt.num_rank_cap : 0, p->flags, st);
+                             rank ? p->opt.num_rank_cap : 0, split, p->flags, st);
         }
         if (rank) {
             TimeScope ts(p, "num.g7r");
             const ChunkDesc *rdesc = split ? p->ndesc_split + p->n_dense : p->ndesc;
             const int64_t nr = split ? p->d_items - p->n_dense : p->d_items;
             launch_num_chunk_rank(p->wmax, p->dprods, rdesc, p->sabs, nr, p->chunk_cnt,
-                                  p->chunk_pos, p->sbits, p->wpc, p->opt.num_rank_cap, p->flags,
-                                  st);
+                                  p->chunk_pos, p->sbits, p->wpc, p->opt.num_rank_cap, split,
+                                  p->flags, st);
         }
     }
     return launch_check();
@@ -628,8 +629,8 @@ void spgemm_default_options(spgemm_options *opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     // tuned on gfx950 (R-MAT scale 18 self-product; see the autotuner)
-    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 2048};
-    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 2048, 2048};
+    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 1024, 1024};
+    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 1024, 1024};
     for (int g = 0; g < kGroups - 1; ++g) {
         opt->sym_upper[g] = sym[g];
         opt->num_upper[g] = num[g];

@@ -154,18 +154,19 @@ void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
                       const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,
-                      int threads, int rank_cap, int *err, hipStream_t s);
+                      int threads, int rank_cap, bool resolved, int *err, hipStream_t s);
 // Numeric chunk items split by output count (more than cap first).
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
                       int64_t cap, int64_t *flag, hipStream_t s);
 void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
-                       const int64_t *fpos, ChunkDesc *out, hipStream_t s);
+                       const int64_t *fpos, const int64_t *chunk_cnt, const int64_t *chunk_pos,
+                       ChunkDesc *out, hipStream_t s);
 // Chunks with at most rank_cap outputs (fast path, one chunk per item only).
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap);
 void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
                            const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
                            const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
-                           int *err, hipStream_t s);
+                           bool resolved, int *err, hipStream_t s);
 
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,

@@ -468,7 +468,7 @@ template <bool NUMERIC>
 __device__ __forceinline__ ItemIn item_load(const ProdDev *prods, const ChunkDesc &d,
                                             const uint32_t *sabs, const int64_t *chunk_cnt,
                                             const int64_t *chunk_pos, const uint32_t *sbits,
-                                            int wpc) {
+                                            int wpc, bool resolved = false) {
     ItemIn in;
     in.x0 = in.x1 = 0u;
     in.a = 0.f;
@@ -484,9 +484,14 @@ __device__ __forceinline__ ItemIn item_load(const ProdDev *prods, const ChunkDes
     }
     if (NUMERIC) {
         const int64_t slot = d.slot0 + c;
-        in.cnt = gld(chunk_cnt + slot);
-        in.pos = gld(chunk_pos + slot);
-        in.pos0 = gld(chunk_pos + d.slot0);
+        if (resolved) {  // count and offset already in the descriptor
+            in.cnt = d.pad;
+            in.pos = in.pos0 = 0;
+        } else {
+            in.cnt = gld(chunk_cnt + slot);
+            in.pos = gld(chunk_pos + slot);
+            in.pos0 = gld(chunk_pos + d.slot0);
+        }
         if (j < wpc) in.word = gld(sbits + slot * (int64_t)wpc + j);
     }
     return in;
@@ -603,7 +608,7 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
                                                        const int64_t *__restrict__ chunk_cnt,
                                                        const int64_t *__restrict__ chunk_pos,
                                                        const uint32_t *__restrict__ sbits,
-                                                       int wpc, int64_t min_expect,
+                                                       int wpc, int64_t min_expect, int resolved,
                                                        int *__restrict__ err) {
     __shared__ float acc[WMAX + 64];  // + one dummy slot per lane for unused batch entries
     __shared__ uint2 sw[WMAX / 32];   // structure words and their first output slot
@@ -616,7 +621,7 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
     if (it >= nitems) return;
     bool cleared = false;  // the accumulator is cleared before the first item taken
     ChunkDesc d = desc_unpack(desc_word(desc, it));
-    ItemIn in = item_load<true>(prods, d, sabs, chunk_cnt, chunk_pos, sbits, wpc);
+    ItemIn in = item_load<true>(prods, d, sabs, chunk_cnt, chunk_pos, sbits, wpc, resolved);
     uint64_t wnext = it + stride < nitems ? desc_word(desc, it + stride) : 0ull;
     for (;;) {
         const int64_t itn = it + stride;
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
         ItemIn inn;
         if (more) {
             dn = desc_unpack(wnext);
-            inn = item_load<true>(prods, dn, sabs, chunk_cnt, chunk_pos, sbits, wpc);
+            inn = item_load<true>(prods, dn, sabs, chunk_cnt, chunk_pos, sbits, wpc, resolved);
             wnext = itn + stride < nitems ? desc_word(desc, itn + stride) : 0ull;
         }
         const ProdDev &P = prods[d.prod];
@@ -717,7 +722,8 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
                                                        const int64_t *__restrict__ chunk_cnt,
                                                        const int64_t *__restrict__ chunk_pos,
                                                        const uint32_t *__restrict__ sbits,
-                                                       int wpc, int *__restrict__ err) {
+                                                       int wpc, int resolved,
+                                                       int *__restrict__ err) {
     constexpr int NWD = WMAX / 32;  // structure words of a chunk
     constexpr int K = NWD / 64;     // words per lane
     static_assert(K >= 1 && NWD % 64 == 0, "chunk width");
@@ -730,7 +736,8 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
     const ChunkDesc d = desc_unpack(desc_word(desc, blockIdx.x));
     const int c = d.q;
     const int64_t slot = d.slot0 + c;
-    const int64_t expect = (int64_t)readlane64((uint64_t)gld(chunk_cnt + slot), 0);
+    const int64_t expect =
+        resolved ? (int64_t)d.pad : (int64_t)readlane64((uint64_t)gld(chunk_cnt + slot), 0);
     if (expect == 0 || expect > CAP) return;  // empty, or a dense chunk (k_num_chunk_pipe)
     const ProdDev &P = prods[d.prod];
     ItemIn in;
@@ -742,7 +749,8 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
         in.x1 = gld(sc + d.alen + lane);
         in.a = gld(P.valA + d.a0 + lane);
     }
-    const int64_t out0 = d.out0 + (gld(chunk_pos + slot) - gld(chunk_pos + d.slot0));
+    const int64_t out0 =
+        resolved ? d.out0 : d.out0 + (gld(chunk_pos + slot) - gld(chunk_pos + d.slot0));
     const int lo = c * P.W;
     const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
     const int nwords = (hi - lo + 31) >> 5;
@@ -840,14 +848,22 @@ __global__ void k_desc_flag(const ChunkDesc *__restrict__ desc, int64_t nitems,
     flag[it] = chunk_cnt[d.slot0 + d.q] > cap ? 1 : 0;
 }
 
+// The split descriptors are resolved: out0 is the chunk's own first output
+// slot in C_p and pad its output count, so the numeric kernels need no
+// further look-ups of the chunk counts and offsets.
 __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
                              const int64_t *__restrict__ flag, const int64_t *__restrict__ fpos,
-                             ChunkDesc *__restrict__ out) {
+                             const int64_t *__restrict__ chunk_cnt,
+                             const int64_t *__restrict__ chunk_pos, ChunkDesc *__restrict__ out) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
     const int64_t ndense = fpos[nitems];
     const int64_t pos = flag[it] ? fpos[it] : ndense + (it - fpos[it]);
-    out[pos] = desc[it];
+    ChunkDesc d = desc[it];
+    const int64_t slot = d.slot0 + d.q;
+    d.out0 += chunk_pos[slot] - chunk_pos[d.slot0];
+    d.pad = (int32_t)chunk_cnt[slot];
+    out[pos] = d;
 }
 
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
@@ -858,10 +874,11 @@ void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chun
 }
 
 void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
-                       const int64_t *fpos, ChunkDesc *out, hipStream_t s) {
+                       const int64_t *fpos, const int64_t *chunk_cnt, const int64_t *chunk_pos,
+                       ChunkDesc *out, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_desc_split, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s,
-                       desc, nitems, flag, fpos, out);
+                       desc, nitems, flag, fpos, chunk_cnt, chunk_pos, out);
 }
 
 void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
@@ -1017,28 +1034,30 @@ static void num_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *de
 template <int WG, int WMAX>
 static void num_pipe_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
                             int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                            const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap, int *err,
-                            hipStream_t s) {
+                            const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap,
+                            bool resolved, int *err, hipStream_t s) {
     const unsigned g = pipe_grid(wgs_per_cu, nitems);
     hipLaunchKernelGGL((k_num_chunk_pipe<WG, WMAX>), dim3(g), dim3(WG), 0, s, prods, desc, nitems,
-                       sabs, chunk_cnt, chunk_pos, sbits, wpc, (int64_t)rank_cap, err);
+                       sabs, chunk_cnt, chunk_pos, sbits, wpc, (int64_t)rank_cap,
+                       resolved ? 1 : 0, err);
 }
 
 template <int RW>
 static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
                             int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                            const uint32_t *sbits, int wpc, int rank_cap, int *err,
+                            const uint32_t *sbits, int wpc, int rank_cap, bool resolved, int *err,
                             hipStream_t s) {
+    const int res = resolved ? 1 : 0;
     const dim3 grid((unsigned)nitems);
     if (rank_cap <= 512)
         hipLaunchKernelGGL((k_num_chunk_rank<RW, 512>), grid, dim3(64), 0, s, prods, desc, sabs,
-                           chunk_cnt, chunk_pos, sbits, wpc, err);
+                           chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else if (rank_cap <= 1024)
         hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024>), grid, dim3(64), 0, s, prods, desc, sabs,
-                           chunk_cnt, chunk_pos, sbits, wpc, err);
+                           chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else
         hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048>), grid, dim3(64), 0, s, prods, desc, sabs,
-                           chunk_cnt, chunk_pos, sbits, wpc, err);
+                           chunk_cnt, chunk_pos, sbits, wpc, res, err);
 }
 
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
@@ -1048,64 +1067,64 @@ bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
 void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
                            const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
                            const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
-                           int *err, hipStream_t s) {
+                           bool resolved, int *err, hipStream_t s) {
     if (nitems <= 0 || rank_cap <= 0) return;
     if (wmax <= 2048)
         num_rank_launch<2048>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                              rank_cap, err, s);
+                              rank_cap, resolved, err, s);
     else if (wmax <= 4096)
         num_rank_launch<4096>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                              rank_cap, err, s);
+                              rank_cap, resolved, err, s);
     else if (wmax <= 8192)
         num_rank_launch<8192>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                              rank_cap, err, s);
+                              rank_cap, resolved, err, s);
     else
         num_rank_launch<kMaxChunkCols>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits,
-                                       wpc, rank_cap, err, s);
+                                       wpc, rank_cap, resolved, err, s);
 }
 
 template <int WMAX>
 static void num_pipe_wg(int wg, const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
                         int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                        const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap, int *err,
-                        hipStream_t s) {
+                        const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap,
+                        bool resolved, int *err, hipStream_t s) {
     switch (wg) {
     case 64:
         num_pipe_launch<64, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                                  wgs_per_cu, rank_cap, err, s);
+                                  wgs_per_cu, rank_cap, resolved, err, s);
         break;
     case 128:
         num_pipe_launch<128, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                                   wgs_per_cu, rank_cap, err, s);
+                                   wgs_per_cu, rank_cap, resolved, err, s);
         break;
     case 512:
         num_pipe_launch<512, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                                   wgs_per_cu, rank_cap, err, s);
+                                   wgs_per_cu, rank_cap, resolved, err, s);
         break;
     default:
         num_pipe_launch<256, WMAX>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
-                                   wgs_per_cu, rank_cap, err, s);
+                                   wgs_per_cu, rank_cap, resolved, err, s);
     }
 }
 
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
                       const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,
-                      int threads, int rank_cap, int *err, hipStream_t s) {
+                      int threads, int rank_cap, bool resolved, int *err, hipStream_t s) {
     if (nitems <= 0) return;
     if (fast && kper == 1) {
         if (wmax <= 2048)
             num_pipe_wg<2048>(threads ? threads : 64, prods, desc, sabs, nitems, chunk_cnt,
-                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, resolved, err, s);
         else if (wmax <= 4096)
             num_pipe_wg<4096>(threads ? threads : 128, prods, desc, sabs, nitems, chunk_cnt,
-                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, resolved, err, s);
         else if (wmax <= 8192)
             num_pipe_wg<8192>(threads ? threads : 256, prods, desc, sabs, nitems, chunk_cnt,
-                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+                              chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, resolved, err, s);
         else
             num_pipe_wg<kMaxChunkCols>(threads ? threads : 512, prods, desc, sabs, nitems,
-                                       chunk_cnt, chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, err, s);
+                                       chunk_cnt, chunk_pos, sbits, wpc, wgs_per_cu, rank_cap, resolved, err, s);
         return;
     }
     if (fast)
