@@ -109,6 +109,12 @@ __device__ __forceinline__ void lds_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Orders the LDS traffic of one wave (its LDS operations complete in issue
+// order; this waits for them and keeps the compiler from moving memory
+// accesses across).  For waves that work independently of the rest of their
+// workgroup.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // block_excl_scan / block_sum with LDS-only barriers (see lds_sync); a
 // single-wave workgroup needs no barrier at all.
 template <int NT, typename T>
@@ -230,12 +236,13 @@ __device__ __forceinline__ void staged_products(const S *st_s, const E *st_e, co
 template <int WG, int VT, bool VALUES, typename E, typename S, typename F>
 __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, const float *st_a,
                                                  int nv, E total, const int32_t *colB,
-                                                 const float *valB, F &&f) {
+                                                 const float *valB, F &&f,
+                                                 int tid = threadIdx.x) {
     constexpr bool kOff32 = sizeof(S) == 4;
     const int32_t *ucol = uniform_ptr(colB);
     const float *uval = VALUES ? uniform_ptr(valB) : valB;
     constexpr int NW = WG / 64;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = tid & 63, w = tid >> 6;
     // wave w takes a contiguous range of 64-product rows, so its lanes only
     // ever walk forward and one binary search per staged batch suffices
     const E nrow = (total + 63) >> 6;

@@ -337,6 +337,10 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
 
 constexpr int NVT = 8;        // products per lane per round in the numeric chunk kernels
 constexpr int kDenseVT = 16;  // same for dense chunks (more gathers in flight per wave)
+#ifndef SPG_RANK_WAVES
+#define SPG_RANK_WAVES 1
+#endif
+constexpr int kRankWaves = SPG_RANK_WAVES;  // independent chunks (waves) per workgroup
 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
@@ -499,15 +503,18 @@ __device__ __forceinline__ ItemIn item_load(const ProdDev *prods, const ChunkDes
 
 // Stages the row's B slices for chunk [lo, hi) in rounds of WG A nonzeros
 // (the first round from the prefetched `in`) and hands every product to f.
-template <int WG, int VT, bool VALUES, typename F>
+// WAVE: a single wave working on its own (tid = lane), ordering its LDS
+// traffic by itself instead of with workgroup barriers.
+template <int WG, int VT, bool VALUES, bool WAVE = false, typename F>
 __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc &d,
                                               const ItemIn &in, const uint32_t *sabs,
                                               uint32_t *st_s, int *st_e, float *st_a, int *wsum,
-                                              F &&f) {
+                                              F &&f, int tid = threadIdx.x) {
+    static_assert(!WAVE || WG == 64, "a wave-local pass is 64 lanes wide");
     const int alen = d.alen;
     const uint32_t *sc = sabs + d.sb + (int64_t)d.q * alen;
     for (int jb = 0; jb < alen; jb += WG) {
-        const int j = jb + threadIdx.x;
+        const int j = jb + tid;
         uint32_t x0 = in.x0, x1 = in.x1;
         float a = in.a;
         if (jb > 0) {
@@ -521,16 +528,16 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
         }
         int total;
         const int excl = wg_excl_scan<WG, int>((int)(x1 - x0), wsum, total);
-        st_s[threadIdx.x] = x0;
-        st_e[threadIdx.x] = excl;
-        if (VALUES) st_a[threadIdx.x] = a;
-        if (threadIdx.x == 0) st_e[WG] = total;
-        lds_sync();
+        st_s[tid] = x0;
+        st_e[tid] = excl;
+        if (VALUES) st_a[tid] = a;
+        if (tid == 0) st_e[WG] = total;
+        if (WAVE) wave_lds_sync(); else lds_sync();
         const int nv = alen - jb < WG ? alen - jb : WG;
         if (total > 0)
             striped_products<WG, VT, VALUES, int, uint32_t>(st_s, st_e, st_a, nv, total, P.colB,
-                                                            P.valB, f);
-        lds_sync();
+                                                            P.valB, f, tid);
+        if (WAVE) wave_lds_sync(); else lds_sync();
     }
 }
 
@@ -715,9 +722,10 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
 // needs a few KB of LDS and many chunks are resident per compute unit.  The
 // values leave as one contiguous (coalesced) copy, already in column order;
 // the columns are written from the bitmap.
-template <int WMAX, int CAP>
-__global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
+template <int WMAX, int CAP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
                                                        const ChunkDesc *__restrict__ desc,
+                                                       int64_t nitems,
                                                        const uint32_t *__restrict__ sabs,
                                                        const int64_t *__restrict__ chunk_cnt,
                                                        const int64_t *__restrict__ chunk_pos,
@@ -727,13 +735,21 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
     constexpr int NWD = WMAX / 32;  // structure words of a chunk
     constexpr int K = NWD / 64;     // words per lane
     static_assert(K >= 1 && NWD % 64 == 0, "chunk width");
-    __shared__ uint2 sw[NWD];        // {word, outputs before the word}
-    __shared__ float cacc[CAP + 64];  // + one dummy slot per lane for unused batch entries
-    __shared__ uint32_t st_s[64];
-    __shared__ int st_e[65];
-    __shared__ float st_a[64];
-    const int lane = threadIdx.x;
-    const ChunkDesc d = desc_unpack(desc_word(desc, blockIdx.x));
+    // each wave of the workgroup takes its own chunk, with its own LDS slices
+    __shared__ uint2 sw_all[WAVES][NWD];        // {word, outputs before the word}
+    __shared__ float cacc_all[WAVES][CAP + 64];  // + one dummy slot per lane for unused entries
+    __shared__ uint32_t st_s_all[WAVES][64];
+    __shared__ int st_e_all[WAVES][65];
+    __shared__ float st_a_all[WAVES][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t item = (int64_t)blockIdx.x * WAVES + wave;
+    if (item >= nitems) return;  // wave-uniform; the waves never meet at a barrier
+    uint2 *sw = sw_all[wave];
+    float *cacc = cacc_all[wave];
+    uint32_t *st_s = st_s_all[wave];
+    int *st_e = st_e_all[wave];
+    float *st_a = st_a_all[wave];
+    const ChunkDesc d = desc_unpack(desc_word(desc, item));
     const int c = d.q;
     const int64_t slot = d.slot0 + c;
     const int64_t expect =
@@ -779,10 +795,10 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
     for (int r = lane; r < expect; r += 64) cacc[r] = 0.f;
     cacc[CAP + lane] = 0.f;
     if (lane == 0 && total != expect) atomicOr(err, kErrChunk);
-    lds_sync();
+    wave_lds_sync();
     const int dummy = CAP + lane;
     bool stray = false;
-    pipe_products<64, NVT, true>(
+    pipe_products<64, NVT, true, true>(
         P, d, in, sabs, st_s, st_e, st_a, nullptr,
         [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
             int idx[NVT];
@@ -799,9 +815,10 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
                 add[v] = take ? aa[v] * vv[v] : 0.f;
             }
             lds_fadd_many<NVT>(cacc, idx, add);
-        });
+        },
+        lane);
     if (stray) atomicOr(err, kErrChunk);  // a product outside the symbolic structure
-    lds_sync();
+    wave_lds_sync();
     float *valC = P.valC + out0;
     for (int r = lane; r < expect; r += 64) gst(valC + r, cacc[r]);
     int32_t *colC = P.colC + out0;
@@ -1048,16 +1065,17 @@ static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const u
                             const uint32_t *sbits, int wpc, int rank_cap, bool resolved, int *err,
                             hipStream_t s) {
     const int res = resolved ? 1 : 0;
-    const dim3 grid((unsigned)nitems);
+    constexpr int WV = kRankWaves;
+    const dim3 grid((unsigned)((nitems + WV - 1) / WV));
     if (rank_cap <= 512)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512>), grid, dim3(64), 0, s, prods, desc, sabs,
-                           chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512, WV>), grid, dim3(64 * WV), 0, s, prods,
+                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else if (rank_cap <= 1024)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024>), grid, dim3(64), 0, s, prods, desc, sabs,
-                           chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024, WV>), grid, dim3(64 * WV), 0, s, prods,
+                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048>), grid, dim3(64), 0, s, prods, desc, sabs,
-                           chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048, WV>), grid, dim3(64 * WV), 0, s, prods,
+                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
 }
 
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
