@@ -135,7 +135,15 @@ typedef struct {
      * in a compact array, one wave per chunk (0 = off, else 512, 1024 or
      * 2048); larger chunks use the dense accumulator. */
     int32_t num_rank_cap;
-    int32_t reserved[2];
+    /* Largest number of adjacent chunks of one group-7 row merged into one
+     * work item (0 = default 2, else 1 = no merging, 2, 4 or 8).  Adjacent
+     * chunks are merged, in column order, while their intermediate products
+     * together stay within num_rank_cap; a merged item then has at most that
+     * many outputs and always takes the rank path.  Needs sorted B rows,
+     * chunks_per_item = 1 and num_rank_cap > 0 (else no merging); an item
+     * spans at most 65536 columns. */
+    int32_t chunk_merge;
+    int32_t reserved[1];
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;

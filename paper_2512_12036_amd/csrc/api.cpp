@@ -64,6 +64,11 @@ struct spgemm_plan {
     uint32_t *sabs = nullptr;
     uint32_t *sbits = nullptr;  // per-chunk structure bitmaps from the symbolic phase
     int wpc = 0;                // bitmap words per chunk
+    // merging of adjacent light chunks into one item (merge > 1)
+    int merge = 1;
+    int wmax_item = 0;          // widest item: wmax * merge
+    int32_t *mstart = nullptr;  // per chunk slot: first chunk of each item of the row
+    int64_t s_items = 0;        // symbolic items
     // numeric group 7
     int64_t nd = 0, d_items = 0;
     int64_t *dnchv = nullptr, *dbase = nullptr;
@@ -73,6 +78,8 @@ struct spgemm_plan {
     ChunkDesc *ndesc_split = nullptr;
     int64_t *dflag = nullptr, *dfpos = nullptr;
     int64_t n_dense = -1;  // -1: not split
+    int64_t n_items = 0;   // numeric items (exact)
+    int64_t n_merged = 0;  // of which merged (the last ones of the split list)
     int wmax = 0;       // widest chunk over the products
     bool fast = true;   // every B sorted with < 2^30 entries (32-bit chunk indexing)
 
@@ -212,6 +219,9 @@ spgemm_status check_options(const spgemm_options &o) {
         if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512) return SPGEMM_EINVAL;
     if (o.num_rank_cap != 0 && o.num_rank_cap != 512 && o.num_rank_cap != 1024 &&
         o.num_rank_cap != 2048)
+        return SPGEMM_EINVAL;
+    if (o.chunk_merge != 0 && o.chunk_merge != 1 && o.chunk_merge != 2 && o.chunk_merge != 4 &&
+        o.chunk_merge != 8)
         return SPGEMM_EINVAL;
     return SPGEMM_OK;
 }
@@ -387,10 +397,19 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
 
     // chunk-group preparation: chunk bases, item -> row map, chunk bounds of
     // every B row, item descriptors
+    // merging of adjacent light chunks: fast path with one chunk per item and
+    // the rank accumulator only (a merged item never exceeds the rank cap)
+    p->merge = 1;
+    if (num_chunk_rank_used(p->fast, p->opt.chunks_per_item, p->opt.num_rank_cap)) {
+        p->merge = p->opt.chunk_merge ? p->opt.chunk_merge : 2;
+        while (p->merge > 1 && (int64_t)p->wmax * p->merge > kMaxItemCols) p->merge >>= 1;
+    }
+    p->wmax_item = p->wmax * p->merge;
+    p->s_items = p->h_items / p->opt.chunks_per_item;
     if (p->nh > 0) {
         const int64_t nh = p->nh;
         const uint64_t *hitems = p->map_sym + p->sym_start[kGroups - 1];
-        const int64_t nitems = p->h_items / p->opt.chunks_per_item;
+        const int64_t nitems = p->h_items / p->opt.chunks_per_item;  // upper bound when merging
         ST_TRY(dalloc(p, &p->nchv, nh));
         ST_TRY(dalloc(p, &p->ibase, nh + 1));
         ST_TRY(dalloc(p, &p->cbase, nh + 1));
@@ -412,6 +431,10 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
             reupload = true;
         }
         if (reupload) ST_TRY(upload_descriptors(p));
+        launch_nch_of(p->dprods, hitems, nh, 1, p->nchv, p->stream);
+        ST_TRY(launch_check());
+        ST_TRY(scan(p, p->nchv, p->cbase, nh));
+        if (p->merge > 1) ST_TRY(dalloc(p, &p->mstart, p->h_items));
         if (p->fast) {
             ST_TRY(dalloc(p, &p->slen, nh));
             ST_TRY(dalloc(p, &p->sbase, nh + 1));
@@ -419,19 +442,28 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
             launch_row_splitlen(p->dprods, hitems, nh, p->slen, p->stream);
             ST_TRY(launch_check());
             ST_TRY(scan(p, p->slen, p->sbase, nh));
-            launch_sabs(p->dprods, hitems, nh, p->sbase, p->sabs, p->stream);
+            // with merging, also the items of every row (nchv = items per row)
+            launch_sabs(p->dprods, hitems, nh, p->sbase, p->sabs, p->merge,
+                        p->opt.num_rank_cap, p->cbase, p->mstart, p->nchv, p->stream);
             ST_TRY(launch_check());
         }
-        launch_nch_of(p->dprods, hitems, nh, 1, p->nchv, p->stream);
-        ST_TRY(launch_check());
-        ST_TRY(scan(p, p->nchv, p->cbase, nh));
-        launch_nch_of(p->dprods, hitems, nh, p->opt.chunks_per_item, p->nchv, p->stream);
-        ST_TRY(launch_check());
+        if (p->merge == 1) {
+            launch_nch_of(p->dprods, hitems, nh, p->opt.chunks_per_item, p->nchv, p->stream);
+            ST_TRY(launch_check());
+        }
         ST_TRY(scan(p, p->nchv, p->ibase, nh));
         launch_expand(p->ibase, nh, p->hitem_row, p->stream);
         launch_sym_desc(p->dprods, hitems, p->hitem_row, p->ibase, p->cbase, p->sbase, nitems,
-                        p->opt.chunks_per_item, p->sdesc, p->stream);
+                        p->opt.chunks_per_item, p->mstart,
+                        p->merge > 1 ? p->ibase + nh : nullptr, p->sdesc, p->stream);
         ST_TRY(launch_check());
+        if (p->merge > 1) {  // the item count is data-dependent: read it back
+            HIP_TRY(hipMemcpyAsync(p->hread, p->ibase + nh, sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, p->stream));
+            HIP_TRY(hipStreamSynchronize(p->stream));
+            p->s_items = p->hread[0];
+            if (p->s_items < 0 || p->s_items > nitems) return SPGEMM_EINTERNAL;
+        }
     }
     p->state = 1;
     return SPGEMM_OK;
@@ -490,9 +522,10 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     }
     if (p->nh > 0) {
         TimeScope ts(p, sym_names[7]);
-        launch_sym_chunk(p->wmax, p->fast, p->dprods, p->sdesc, p->sabs, p->h_items / p->opt.chunks_per_item, p->opt.chunks_per_item,
-                         p->chunk_cnt, p->row_nnz, p->sbits, p->wpc, p->opt.chunk_wgs_per_cu,
-                         p->opt.sym_chunk_threads ? p->opt.sym_chunk_threads : 64, st);
+        launch_sym_chunk(p->wmax_item, p->fast, p->dprods, p->sdesc, p->sabs, p->s_items,
+                         p->opt.chunks_per_item, p->chunk_cnt, p->row_nnz, p->sbits, p->wpc,
+                         p->opt.chunk_wgs_per_cu,
+                         p->opt.sym_chunk_threads ? p->opt.sym_chunk_threads : 64, p->flags, st);
     }
     ST_TRY(launch_check());
     {
@@ -540,38 +573,52 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     }
     if (p->nd != p->num_start[kGroups] - p->num_start[kGroups - 1]) return SPGEMM_EINTERNAL;
     if (p->d_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
+    p->n_items = p->d_items / p->opt.chunks_per_item;
+    p->n_merged = 0;
     if (p->nd > 0) {
         const uint64_t *ditems = p->map_num + p->num_start[kGroups - 1];
+        // with merging an upper bound; the exact count is dbase[nd]
         const int64_t nitems = p->d_items / p->opt.chunks_per_item;
         ST_TRY(dalloc(p, &p->dnchv, p->nd));
         ST_TRY(dalloc(p, &p->dbase, p->nd + 1));
         ST_TRY(dalloc(p, &p->ditem_row, nitems));
         ST_TRY(dalloc(p, &p->ndesc, nitems));
-        launch_nch_of(p->dprods, ditems, p->nd, p->opt.chunks_per_item, p->dnchv, st);
+        const int64_t *nlim = p->merge > 1 ? p->dbase + p->nd : nullptr;
+        if (p->merge > 1)
+            launch_num_nitems(p->dprods, ditems, p->nd, p->hslot, p->nchv, p->dnchv, st);
+        else
+            launch_nch_of(p->dprods, ditems, p->nd, p->opt.chunks_per_item, p->dnchv, st);
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->dnchv, p->dbase, p->nd));
         launch_expand(p->dbase, p->nd, p->ditem_row, st);
         launch_num_desc(p->dprods, ditems, p->ditem_row, p->dbase, nitems,
-                        p->opt.chunks_per_item, p->hslot, p->cbase, p->sbase, p->rptv, p->ndesc,
-                        st);
+                        p->opt.chunks_per_item, p->hslot, p->cbase, p->sbase, p->rptv, p->mstart,
+                        nlim, p->ndesc, st);
         ST_TRY(launch_check());
         p->n_dense = -1;
         if (num_chunk_rank_used(p->fast, p->opt.chunks_per_item, p->opt.num_rank_cap)) {
-            // dense chunks first, then the rank-accumulated ones, so that each
-            // kernel is launched over its own items only
+            // dense chunks first, then single and merged rank-accumulated
+            // items, so that each kernel is launched over its own items only
             ST_TRY(dalloc(p, &p->ndesc_split, nitems));
             ST_TRY(dalloc(p, &p->dflag, nitems));
             ST_TRY(dalloc(p, &p->dfpos, nitems + 1));
-            launch_desc_flag(p->ndesc, nitems, p->chunk_cnt, p->opt.num_rank_cap, p->dflag, st);
+            launch_desc_flag(p->ndesc, nitems, p->chunk_cnt, p->opt.num_rank_cap, nlim, p->dflag,
+                             st);
             ST_TRY(launch_check());
             ST_TRY(scan(p, p->dflag, p->dfpos, nitems));
             launch_desc_split(p->ndesc, nitems, p->dflag, p->dfpos, p->chunk_cnt, p->chunk_pos,
-                              p->ndesc_split, st);
+                              nlim, p->ndesc_split, st);
             ST_TRY(launch_check());
             HIP_TRY(hipMemcpyAsync(p->hread, p->dfpos + nitems, sizeof(int64_t),
                                    hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(p->hread + 1, p->dbase + p->nd, sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
-            p->n_dense = p->hread[0];
+            p->n_dense = p->hread[0] & 0xffffffffll;
+            p->n_merged = p->hread[0] >> 32;
+            p->n_items = p->hread[1];
+            if (p->n_items < 0 || p->n_items > nitems || p->n_dense + p->n_merged > p->n_items)
+                return SPGEMM_EINTERNAL;
         }
     }
     p->state = 2;
@@ -580,8 +627,8 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
 
 spgemm_status numeric_impl(spgemm_plan *p) {
     if (p->state != 2) return SPGEMM_ESTATE;
-    ST_TRY(upload_descriptors(p));
     hipStream_t st = p->stream;
+    ST_TRY(upload_descriptors(p));
     static const char *const num_names[kGroups] = {"num.g0", "num.g1", "num.g2", "num.g3",
                                                    "num.g4", "num.g5", "num.g6", "num.g7"};
     for (int g = 1; g <= 4; ++g) {
@@ -610,12 +657,18 @@ spgemm_status numeric_impl(spgemm_plan *p) {
                              rank ? p->opt.num_rank_cap : 0, split, p->flags, st);
         }
         if (rank) {
+            // single chunks, then merged items (their own launch: wider structure)
             TimeScope ts(p, "num.g7r");
             const ChunkDesc *rdesc = split ? p->ndesc_split + p->n_dense : p->ndesc;
-            const int64_t nr = split ? p->d_items - p->n_dense : p->d_items;
+            const int64_t nm = split ? p->n_merged : 0;
+            const int64_t nr = (split ? p->n_items - p->n_dense : p->d_items) - nm;
             launch_num_chunk_rank(p->wmax, p->dprods, rdesc, p->sabs, nr, p->chunk_cnt,
                                   p->chunk_pos, p->sbits, p->wpc, p->opt.num_rank_cap, split,
                                   p->flags, st);
+            if (nm > 0)
+                launch_num_chunk_rank(p->wmax_item, p->dprods, rdesc + nr, p->sabs, nm,
+                                      p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc,
+                                      p->opt.num_rank_cap, split, p->flags, st);
         }
     }
     return launch_check();

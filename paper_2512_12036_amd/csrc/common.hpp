@@ -13,6 +13,8 @@ constexpr int kChunkGroup = 7;       // column-chunked group
 constexpr int64_t kIpPerLane = 16;   // numeric grouping: target products per lane
 constexpr int64_t kDirectG4 = 512;   // table slots of group 4 (64 lanes x 8)
 constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 dense accumulator
+constexpr int kMaxItemCols = 65536;  // widest merged item (8 KiB LDS bitmap)
+constexpr int kMaxMergeChunks = 256; // rows with more chunks are not merged
 constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
 // Largest key each group can take (tables at most half full).
 constexpr int64_t kSymCap[kGroups] = {0, 32, 64, 128, 256, 4096, 16384, 0};
@@ -44,7 +46,8 @@ struct ProdDev {
     int32_t pad;
 };
 
-// One work item of group 7: the chunks q, q + Q, ... (K of them) of one row.
+// One work item of group 7: the chunks q, q + Q, ... (K of them) of one row,
+// or (K = 1) the `span` adjacent chunks q .. q + span - 1 taken as one.
 struct ChunkDesc {
     int64_t a0;      // first A nonzero of the row
     int64_t out0;    // symbolic: batch row index; numeric: output offset of the row in C_p
@@ -53,7 +56,9 @@ struct ChunkDesc {
     int32_t alen;    // A nonzeros of the row
     int32_t q;       // first chunk of the item
     int32_t prod;    // product index
-    int32_t pad;
+    int32_t pad;     // resolved numeric descriptors: the item's output count
+    int32_t span;    // adjacent chunks taken as one (1 unless merged)
+    int32_t pad2;
 };
 
 // A block of up to kRowBlock consecutive rows of one product.
@@ -129,14 +134,18 @@ void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s);
 void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *len,
                          hipStream_t s);
 void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *sbase,
-                 uint32_t *sabs, hipStream_t s);
+                 uint32_t *sabs, int merge, int64_t cap, const int64_t *cbase, int32_t *mstart,
+                 int64_t *nitem, hipStream_t s);
+void launch_num_nitems(const ProdDev *prods, const uint64_t *ditems, int64_t n,
+                       const int32_t *hslot, const int64_t *nitem, int64_t *dnch, hipStream_t s);
 void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
                      const int64_t *ibase, const int64_t *cbase, const int64_t *sbase,
-                     int64_t nitems, int kper, ChunkDesc *desc, hipStream_t s);
+                     int64_t nitems, int kper, const int32_t *mstart, const int64_t *nlim,
+                     ChunkDesc *desc, hipStream_t s);
 void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t *item_of,
                      const int64_t *dbase, int64_t nitems, int kper, const int32_t *hslot,
                      const int64_t *cbase, const int64_t *sbase, const int64_t *rptv,
-                     ChunkDesc *desc, hipStream_t s);
+                     const int32_t *mstart, const int64_t *nlim, ChunkDesc *desc, hipStream_t s);
 
 void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, int64_t *row_nnz, int *err, hipStream_t s);
@@ -146,7 +155,7 @@ void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
                       int64_t *row_nnz, uint32_t *sbits, int wpc, int wgs_per_cu, int threads,
-                      hipStream_t s);
+                      int *err, hipStream_t s);
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s);
 void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
@@ -155,12 +164,14 @@ void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
                       const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,
                       int threads, int rank_cap, bool resolved, int *err, hipStream_t s);
-// Numeric chunk items split by output count (more than cap first).
+// Numeric chunk items split by output count and span: more than cap outputs
+// first, then single chunks, then merged items.  flag/fpos entries pack the
+// dense count (low 32 bits) and the merged count (high 32 bits).
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
-                      int64_t cap, int64_t *flag, hipStream_t s);
+                      int64_t cap, const int64_t *nlim, int64_t *flag, hipStream_t s);
 void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
                        const int64_t *fpos, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                       ChunkDesc *out, hipStream_t s);
+                       const int64_t *nlim, ChunkDesc *out, hipStream_t s);
 // Chunks with at most rank_cap outputs (fast path, one chunk per item only).
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap);
 void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,

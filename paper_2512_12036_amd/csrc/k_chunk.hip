@@ -79,26 +79,95 @@ __global__ void k_row_splitlen(const ProdDev *__restrict__ prods,
 // B row colA[a0 + j] with column >= c * W, for c = 0..nch.  Chunk c of the row
 // then reads, for every nonzero j, the range [sabs[c][j], sabs[c+1][j]) with
 // two coalesced loads.
+//
+// With mstart set, the row's work items are formed here as well.  The
+// intermediate products of every chunk are summed (a wave sum per chunk, one
+// LDS atomic per wave), then adjacent chunks are merged in column order while
+// their products together stay within `cap` and at most `merge` of them are
+// taken: mstart[cbase[h] + k] = first chunk of item k and nitem[h] = the
+// row's item count.  A merged item has at most cap outputs.  Rows with more
+// than kMaxMergeChunks chunks keep one item per chunk.
 __global__ __launch_bounds__(256) void k_sabs(const ProdDev *__restrict__ prods,
                                                const uint64_t *__restrict__ items, int64_t nh,
                                                const int64_t *__restrict__ sbase,
-                                               uint32_t *__restrict__ sabs) {
+                                               uint32_t *__restrict__ sabs, int merge,
+                                               int64_t cap, const int64_t *__restrict__ cbase,
+                                               int32_t *__restrict__ mstart,
+                                               int64_t *__restrict__ nitem) {
+    __shared__ unsigned long long ipc[kMaxMergeChunks];
     const int64_t h = blockIdx.x;
     const uint64_t e = items[h];
     const ProdDev &P = prods[item_prod(e)];
     const int64_t i = item_row(e);
     const int64_t a0 = P.rptA[i];
     const int64_t alen = P.rptA[i + 1] - a0;
-    const int per = P.nch + 1;
+    const int nch = P.nch;
+    const int per = nch + 1;
+    const bool mg = mstart != nullptr && merge > 1 && nch <= kMaxMergeChunks;
+    const int lane = threadIdx.x & 63;
+    if (mg) {
+        for (int c = threadIdx.x; c < nch; c += 256) ipc[c] = 0ull;
+        __syncthreads();
+    }
     uint32_t *out = sabs + sbase[h];
     for (int64_t jb = 0; jb < alen; jb += 256) {
         const int64_t j = jb + threadIdx.x;
-        if (j >= alen) break;
-        const int k = gld(P.colA + a0 + j);
-        const int64_t b0 = gld(P.rptB + k);
-        const int32_t *bs = P.bsplit + (int64_t)k * per;
-        for (int c = 0; c < per; ++c) out[(int64_t)c * alen + j] = (uint32_t)(b0 + gld(bs + c));
+        const bool valid = j < alen;
+        // wave-uniform: some lane of this wave holds a nonzero
+        const bool wave_live = jb + (threadIdx.x & ~63) < alen;
+        int64_t b0 = 0;
+        const int32_t *bs = nullptr;
+        if (valid) {
+            const int k = gld(P.colA + a0 + j);
+            b0 = gld(P.rptB + k);
+            bs = P.bsplit + (int64_t)k * per;
+        }
+        uint32_t prev = 0u;
+        for (int c = 0; c < per; ++c) {
+            uint32_t v = 0u;
+            if (valid) {
+                v = (uint32_t)(b0 + gld(bs + c));
+                out[(int64_t)c * alen + j] = v;
+            }
+            if (mg && c > 0 && wave_live) {
+                unsigned long long len = valid ? (unsigned long long)(v - prev) : 0ull;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) len += __shfl_xor(len, off, 64);
+                if (lane == 0 && len) atomicAdd(&ipc[c - 1], len);
+            }
+            prev = v;
+        }
     }
+    if (mstart == nullptr) return;
+    int32_t *ms = mstart + cbase[h];
+    if (!mg) {
+        for (int c = threadIdx.x; c < nch; c += 256) ms[c] = c;
+        if (threadIdx.x == 0) nitem[h] = nch;
+        return;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int k = 0;
+        for (int c = 0; c < nch;) {
+            unsigned long long sum = ipc[c];
+            int e2 = c + 1;
+            while (e2 < nch && e2 - c < merge && sum + ipc[e2] <= (unsigned long long)cap)
+                sum += ipc[e2++];
+            ms[k++] = c;
+            c = e2;
+        }
+        nitem[h] = k;
+    }
+}
+
+// dnch[r] = items of numeric group-7 row r: those its symbolic row was given.
+__global__ void k_num_nitems(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ ditems,
+                             int64_t n, const int32_t *__restrict__ hslot,
+                             const int64_t *__restrict__ nitem, int64_t *__restrict__ dnch) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t e = ditems[r];
+    dnch[r] = nitem[hslot[prods[item_prod(e)].row_base + item_row(e)]];
 }
 
 // nchv[r] = chunks of row r divided by div (div = 1: chunks, div = K: items).
@@ -121,14 +190,16 @@ __device__ __forceinline__ int item_q(int64_t it, int64_t base, int64_t row, int
 }
 
 // Symbolic items: desc.out0 = batch row, desc.slot0 = first chunk-count slot
-// of the row.
+// of the row.  With merged items the launch covers an upper bound of the item
+// count and *nlim is the exact one.
 __global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                            const int32_t *__restrict__ item_of, const int64_t *__restrict__ ibase,
                            const int64_t *__restrict__ cbase,
                            const int64_t *__restrict__ sbase, int64_t nitems, int kper,
+                           const int32_t *__restrict__ mstart, const int64_t *__restrict__ nlim,
                            ChunkDesc *__restrict__ desc) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= nitems) return;
+    if (it >= nitems || (nlim && it >= *nlim)) return;
     const int64_t h = item_of[it];
     const uint64_t e = items[h];
     const int p = item_prod(e);
@@ -138,21 +209,35 @@ __global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__
     d.a0 = P.rptA[i];
     d.alen = (int32_t)(P.rptA[i + 1] - d.a0);
     d.out0 = P.row_base + i;
-    d.q = item_q(it, ibase[h], h, P.nch / kper);
     d.prod = p;
     d.slot0 = cbase[h];
     d.sb = sbase ? sbase[h] : -1;
+    d.pad = 0;
+    d.pad2 = 0;
+    if (mstart) {  // merged items: item k covers chunks mstart[k] .. mstart[k + 1] - 1
+        const int nr = (int)(ibase[h + 1] - ibase[h]);
+        const int k = item_q(it, ibase[h], h, nr);
+        const int32_t *ms = mstart + cbase[h];
+        d.q = ms[k];
+        d.span = (k + 1 < nr ? ms[k + 1] : P.nch) - d.q;
+    } else {
+        d.q = item_q(it, ibase[h], h, P.nch / kper);
+        d.span = 1;
+    }
     desc[it] = d;
 }
 
-// Numeric items: desc.out0 = output offset of the row inside C_p.
+// Numeric items: desc.out0 = output offset of the row inside C_p.  With
+// merged items the launch covers an upper bound of the item count and *nlim
+// is the exact one.
 __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ ditems,
                            const int32_t *__restrict__ item_of, const int64_t *__restrict__ dbase,
                            int64_t nitems, int kper, const int32_t *__restrict__ hslot,
                            const int64_t *__restrict__ cbase, const int64_t *__restrict__ sbase,
-                           const int64_t *__restrict__ rptv, ChunkDesc *__restrict__ desc) {
+                           const int64_t *__restrict__ rptv, const int32_t *__restrict__ mstart,
+                           const int64_t *__restrict__ nlim, ChunkDesc *__restrict__ desc) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= nitems) return;
+    if (it >= nitems || (nlim && it >= *nlim)) return;
     const int64_t dr = item_of[it];
     const uint64_t e = ditems[dr];
     const int p = item_prod(e);
@@ -163,11 +248,22 @@ __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__
     d.a0 = P.rptA[i];
     d.alen = (int32_t)(P.rptA[i + 1] - d.a0);
     d.out0 = rptv[g] - rptv[P.row_base];
-    d.q = item_q(it, dbase[dr], dr, P.nch / kper);
     d.prod = p;
     const int64_t h = hslot[g];
     d.slot0 = cbase[h];
     d.sb = sbase ? sbase[h] : -1;
+    d.pad = 0;
+    d.pad2 = 0;
+    if (mstart) {
+        const int nr = (int)(dbase[dr + 1] - dbase[dr]);
+        const int k = item_q(it, dbase[dr], dr, nr);
+        const int32_t *ms = mstart + cbase[h];
+        d.q = ms[k];
+        d.span = (k + 1 < nr ? ms[k + 1] : P.nch) - d.q;
+    } else {
+        d.q = item_q(it, dbase[dr], dr, P.nch / kper);
+        d.span = 1;
+    }
     desc[it] = d;
 }
 
@@ -337,6 +433,7 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
 
 constexpr int NVT = 8;        // products per lane per round in the numeric chunk kernels
 constexpr int kDenseVT = 16;  // same for dense chunks (more gathers in flight per wave)
+constexpr int kEmitU = 8;     // columns per thread per round of the dense emission
 #ifndef SPG_RANK_WAVES
 #define SPG_RANK_WAVES 1
 #endif
@@ -454,6 +551,9 @@ __device__ __forceinline__ ChunkDesc desc_unpack(uint64_t w) {
     d.q = (int32_t)(uint32_t)(w4 >> 32);
     d.prod = (int32_t)(uint32_t)w5;
     d.pad = (int32_t)(uint32_t)(w5 >> 32);
+    const uint64_t w6 = readlane64(w, 6);
+    d.span = (int32_t)(uint32_t)w6;
+    d.pad2 = (int32_t)(uint32_t)(w6 >> 32);
     return d;
 }
 
@@ -483,7 +583,7 @@ __device__ __forceinline__ ItemIn item_load(const ProdDev *prods, const ChunkDes
     if (j < d.alen) {
         const uint32_t *sc = sabs + d.sb + (int64_t)c * d.alen;
         in.x0 = gld(sc + j);
-        in.x1 = gld(sc + d.alen + j);
+        in.x1 = gld(sc + (int64_t)d.span * d.alen + j);
         if (NUMERIC) in.a = gld(prods[d.prod].valA + d.a0 + j);
     }
     if (NUMERIC) {
@@ -513,6 +613,7 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
     static_assert(!WAVE || WG == 64, "a wave-local pass is 64 lanes wide");
     const int alen = d.alen;
     const uint32_t *sc = sabs + d.sb + (int64_t)d.q * alen;
+    const int64_t send = (int64_t)d.span * alen;  // the item's end bound
     for (int jb = 0; jb < alen; jb += WG) {
         const int j = jb + tid;
         uint32_t x0 = in.x0, x1 = in.x1;
@@ -522,7 +623,7 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
             a = 0.f;
             if (j < alen) {
                 x0 = gld(sc + j);
-                x1 = gld(sc + alen + j);
+                x1 = gld(sc + send + j);
                 if (VALUES) a = gld(P.valA + d.a0 + j);
             }
         }
@@ -548,7 +649,8 @@ __global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict
                                                        const uint32_t *__restrict__ sabs,
                                                        int64_t *__restrict__ chunk_cnt,
                                                        int64_t *__restrict__ row_nnz,
-                                                       uint32_t *__restrict__ sbits, int wpc) {
+                                                       uint32_t *__restrict__ sbits, int wpc,
+                                                       int *__restrict__ err) {
     __shared__ uint32_t bm[WMAX / 32];
     __shared__ uint32_t st_s[WG];
     __shared__ int st_e[WG + 1];
@@ -556,7 +658,7 @@ __global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict
     int64_t it = blockIdx.x;
     const int64_t stride = gridDim.x;
     if (it >= nitems) return;
-    for (int x = threadIdx.x; x < WMAX / 32; x += WG) bm[x] = 0u;
+    int clean = 0;  // bitmap words [0, clean) are zero (each item re-zeroes what it used)
     ChunkDesc d = desc_unpack(desc_word(desc, it));
     ItemIn in = item_load<false>(prods, d, sabs, nullptr, nullptr, nullptr, 0);
     uint64_t wnext = it + stride < nitems ? desc_word(desc, it + stride) : 0ull;
@@ -573,10 +675,20 @@ __global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict
         const ProdDev &P = prods[d.prod];
         const int c = d.q;
         const int lo = c * P.W;
-        const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+        const int64_t end = (int64_t)lo + (int64_t)d.span * P.W;
+        const int hi = (int)(end < P.n ? end : P.n);
+        if (hi - lo > WMAX) {  // the plan picks WMAX >= the widest item; never taken
+            if (threadIdx.x == 0) atomicOr(err, kErrRow);
+            return;
+        }
         int64_t cnt = 0;
         if (hi > lo) {
-            lds_sync();  // bitmap clear (first item) done
+            const int nw = (hi - lo + 31) >> 5;
+            if (nw > clean) {
+                for (int x = clean + (int)threadIdx.x; x < nw; x += WG) bm[x] = 0u;
+                clean = nw;
+            }
+            lds_sync();  // bitmap clear done
             pipe_products<WG, 8, false>(
                 P, d, in, sabs, st_s, st_e, nullptr, (int *)wsum,
                 [&](const int *cc, const float *, const float *, const bool *ok) {
@@ -588,6 +700,7 @@ __global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict
                 });
             const int nwords = (hi - lo + 31) >> 5;
             uint32_t *keep = sbits + (d.slot0 + c) * (int64_t)wpc;
+#pragma unroll 4
             for (int x = threadIdx.x; x < nwords; x += WG) {
                 const uint32_t wv = bm[x];
                 cnt += __popc(wv);
@@ -599,6 +712,8 @@ __global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict
         if (threadIdx.x == 0) {
             chunk_cnt[d.slot0 + c] = tot;
             if (tot) atomicAdd((unsigned long long *)&row_nnz[d.out0], (unsigned long long)tot);
+        } else if ((int)threadIdx.x < d.span) {
+            chunk_cnt[d.slot0 + c + threadIdx.x] = 0;  // chunks merged into this item
         }
         if (!more) break;
         it = itn;
@@ -643,7 +758,8 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
         const ProdDev &P = prods[d.prod];
         const int c = d.q;
         const int lo = c * P.W;
-        const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+        const int64_t end = (int64_t)lo + (int64_t)d.span * P.W;
+        const int hi = (int)(end < P.n ? end : P.n);
         const int width = hi - lo;
         // the count is the same in every lane; make it a scalar
         const int64_t expect = (int64_t)readlane64((uint64_t)in.cnt, 0);
@@ -677,7 +793,9 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
             // set column is its word's slot plus the set bits below it, so
             // consecutive set columns go to consecutive slots (coalesced
             // writes, already in column order), and every slot of the
-            // accumulator is cleared for the next chunk.
+            // accumulator is cleared for the next chunk.  kEmitU columns per
+            // thread are read from LDS together, so that one LDS round trip
+            // serves all of them.
             const int nwords = (width + 31) >> 5;
             const uint32_t *bits = sbits + (d.slot0 + c) * (int64_t)wpc;
             int32_t *colC = P.colC + out0;
@@ -692,16 +810,30 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
                 base += total;
             }
             lds_sync();
-            for (int col = threadIdx.x; col < nwords * 32; col += WG) {
-                const uint2 e = sw[col >> 5];
-                const uint32_t bit = 1u << (col & 31);
-                const float v = acc[col];
-                acc[col] = 0.f;
-                if (e.x & bit) {
-                    const int r = (int)e.y + __popc(e.x & (bit - 1u));
-                    if (r < expect) {
-                        gst(colC + r, lo + col);
-                        gst(valC + r, v);
+            const int ncol = nwords * 32;
+            const int ex = (int)expect;
+            for (int c0 = threadIdx.x; c0 < ncol; c0 += kEmitU * WG) {
+                uint2 e[kEmitU];
+                float v[kEmitU];
+#pragma unroll
+                for (int u = 0; u < kEmitU; ++u) {
+                    const int col = c0 + u * WG;
+                    const int cc = col < ncol ? col : 0;
+                    e[u] = sw[cc >> 5];
+                    v[u] = acc[cc];
+                    if (col >= ncol) e[u].x = 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < kEmitU; ++u) {
+                    const int col = c0 + u * WG;
+                    if (col < ncol) acc[col] = 0.f;
+                    const uint32_t bit = 1u << (col & 31);
+                    if (e[u].x & bit) {
+                        const int r = (int)e[u].y + __popc(e[u].x & (bit - 1u));
+                        if (r < ex) {
+                            gst(colC + r, lo + col);
+                            gst(valC + r, v[u]);
+                        }
                     }
                 }
             }
@@ -732,9 +864,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
                                                        const uint32_t *__restrict__ sbits,
                                                        int wpc, int resolved,
                                                        int *__restrict__ err) {
-    constexpr int NWD = WMAX / 32;  // structure words of a chunk
-    constexpr int K = NWD / 64;     // words per lane
-    static_assert(K >= 1 && NWD % 64 == 0, "chunk width");
+    constexpr int NWD = WMAX / 32;  // structure words of the widest item
+    static_assert(NWD >= 64 && NWD % 64 == 0, "chunk width");
     // each wave of the workgroup takes its own chunk, with its own LDS slices
     __shared__ uint2 sw_all[WAVES][NWD];        // {word, outputs before the word}
     __shared__ float cacc_all[WAVES][CAP + 64];  // + one dummy slot per lane for unused entries
@@ -762,35 +893,49 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
     if (lane < d.alen) {
         const uint32_t *sc = sabs + d.sb + (int64_t)c * d.alen;
         in.x0 = gld(sc + lane);
-        in.x1 = gld(sc + d.alen + lane);
+        in.x1 = gld(sc + (int64_t)d.span * d.alen + lane);
         in.a = gld(P.valA + d.a0 + lane);
     }
     const int64_t out0 =
         resolved ? d.out0 : d.out0 + (gld(chunk_pos + slot) - gld(chunk_pos + d.slot0));
     const int lo = c * P.W;
-    const int hi = (int)((int64_t)lo + P.W < P.n ? (int64_t)lo + P.W : P.n);
+    const int64_t end = (int64_t)lo + (int64_t)d.span * P.W;
+    const int hi = (int)(end < P.n ? end : P.n);
     const int nwords = (hi - lo + 31) >> 5;
-    if (hi - lo > WMAX) {  // the plan picks WMAX >= W; never taken
+    if (hi - lo > WMAX) {  // the plan picks WMAX >= the widest item; never taken
         if (lane == 0) atomicOr(err, kErrRow);
         return;
     }
-    // structure: lane l holds words l*K .. l*K + K - 1
+    // structure: lane l takes words l*K .. l*K + K - 1 (K = nwords / 64
+    // rounded up); sw[x] = {word x, outputs before word x}
     const uint32_t *bits = sbits + slot * (int64_t)wpc;
-    uint32_t wv[K];
+    const int K = (nwords + 63) >> 6;
     int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int x = lane * K + k;
-        wv[k] = x < nwords ? gld(bits + x) : 0u;
-        cnt += __popc(wv[k]);
+    if ((K & 3) == 0 && nwords == K * 64 && (wpc & 3) == 0) {  // 16-byte loads
+        for (int k = 0; k < K; k += 4) {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 w4 = gld((const u32x4 *)(bits + lane * K + k));
+            uint2 *o = sw + lane * K + k;
+            o[0].x = w4.x;
+            o[1].x = w4.y;
+            o[2].x = w4.z;
+            o[3].x = w4.w;
+            cnt += __popc(w4.x) + __popc(w4.y) + __popc(w4.z) + __popc(w4.w);
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            const int x = lane * K + k;
+            const uint32_t w = x < nwords ? gld(bits + x) : 0u;
+            sw[x].x = w;
+            cnt += __popc(w);
+        }
     }
     int total;
     int pre = wg_excl_scan<64, int>(cnt, nullptr, total);
-    const int pre0 = pre;
-#pragma unroll
     for (int k = 0; k < K; ++k) {
-        sw[lane * K + k] = make_uint2(wv[k], (uint32_t)pre);
-        pre += __popc(wv[k]);
+        uint2 &e = sw[lane * K + k];
+        e.y = (uint32_t)pre;
+        pre += __popc(e.x);
     }
     for (int r = lane; r < expect; r += 64) cacc[r] = 0.f;
     cacc[CAP + lane] = 0.f;
@@ -819,21 +964,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
         lane);
     if (stray) atomicOr(err, kErrChunk);  // a product outside the symbolic structure
     wave_lds_sync();
+    const int ex = (int)expect;
     float *valC = P.valC + out0;
-    for (int r = lane; r < expect; r += 64) gst(valC + r, cacc[r]);
-    int32_t *colC = P.colC + out0;
-    int r = pre0;
-#pragma unroll
+    for (int r = lane; r < ex; r += 64) gst(valC + r, cacc[r]);
+    // the columns: every lane expands its words' set bits into the (now
+    // free) accumulator at their ranks, then one coalesced copy
+    wave_lds_sync();
     for (int k = 0; k < K; ++k) {
-        uint32_t w = wv[k];
-        const int base = lo + ((lane * K + k) << 5);
+        const int x = lane * K + k;
+        const uint2 e = sw[x];
+        uint32_t w = e.x;
+        int r = (int)e.y;
+        const int base = lo + (x << 5);
         while (w) {
             const int b = __builtin_ctz(w);
             w &= w - 1u;
-            if (r < expect) gst(colC + r, base + b);
+            if (r < ex) cacc[r] = __int_as_float(base + b);
             ++r;
         }
     }
+    wave_lds_sync();
+    int32_t *colC = P.colC + out0;
+    for (int r = lane; r < ex; r += 64) gst(colC + r, __float_as_int(cacc[r]));
 }
 
 // Workgroups of a pipelined launch: wgs_per_cu per compute unit (a multiple
@@ -853,29 +1005,45 @@ static unsigned pipe_grid(int wgs_per_cu, int64_t nitems) {
     return (unsigned)g;
 }
 
-// Splits the numeric chunk items (one chunk per item) into those with more
-// than `cap` outputs, first, and the others, after, keeping the order within
-// each part: flag, exclusive scan of the flags, scatter.
+// Splits the numeric chunk items (one chunk per item) into three parts,
+// keeping the order within each: items with more than `cap` outputs (dense),
+// then single chunks with at most cap outputs, then merged items (which
+// never have more than cap).  The flag packs two counters, dense in the low
+// 32 bits and merged in the high 32 bits, so one exclusive scan of the flags
+// gives each item its position.  The launches cover an upper bound of the
+// item count; nlim (if set) points at the exact count.
 __global__ void k_desc_flag(const ChunkDesc *__restrict__ desc, int64_t nitems,
                             const int64_t *__restrict__ chunk_cnt, int64_t cap,
-                            int64_t *__restrict__ flag) {
+                            const int64_t *__restrict__ nlim, int64_t *__restrict__ flag) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
+    if (nlim && it >= *nlim) {
+        flag[it] = 0;
+        return;
+    }
     const ChunkDesc d = desc[it];
-    flag[it] = chunk_cnt[d.slot0 + d.q] > cap ? 1 : 0;
+    flag[it] = chunk_cnt[d.slot0 + d.q] > cap ? 1 : (d.span > 1 ? (int64_t(1) << 32) : 0);
 }
 
-// The split descriptors are resolved: out0 is the chunk's own first output
+// The split descriptors are resolved: out0 is the item's own first output
 // slot in C_p and pad its output count, so the numeric kernels need no
 // further look-ups of the chunk counts and offsets.
 __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
                              const int64_t *__restrict__ flag, const int64_t *__restrict__ fpos,
                              const int64_t *__restrict__ chunk_cnt,
-                             const int64_t *__restrict__ chunk_pos, ChunkDesc *__restrict__ out) {
+                             const int64_t *__restrict__ chunk_pos,
+                             const int64_t *__restrict__ nlim, ChunkDesc *__restrict__ out) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
-    const int64_t ndense = fpos[nitems];
-    const int64_t pos = flag[it] ? fpos[it] : ndense + (it - fpos[it]);
+    const int64_t n = nlim ? *nlim : nitems;
+    if (it >= n) return;
+    const int64_t tot = fpos[nitems];
+    const int64_t ndense = tot & 0xffffffffll, nmerged = tot >> 32;
+    const int64_t f = fpos[it];
+    const int64_t fd = f & 0xffffffffll, fm = f >> 32;
+    const int64_t fl = flag[it];
+    const int64_t pos = (fl & 0xffffffffll) ? fd : (fl >> 32) ? n - nmerged + fm
+                                                              : ndense + (it - fd - fm);
     ChunkDesc d = desc[it];
     const int64_t slot = d.slot0 + d.q;
     d.out0 += chunk_pos[slot] - chunk_pos[d.slot0];
@@ -884,18 +1052,18 @@ __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
 }
 
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
-                      int64_t cap, int64_t *flag, hipStream_t s) {
+                      int64_t cap, const int64_t *nlim, int64_t *flag, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_desc_flag, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, desc,
-                       nitems, chunk_cnt, cap, flag);
+                       nitems, chunk_cnt, cap, nlim, flag);
 }
 
 void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
                        const int64_t *fpos, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                       ChunkDesc *out, hipStream_t s) {
+                       const int64_t *nlim, ChunkDesc *out, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_desc_split, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s,
-                       desc, nitems, flag, fpos, chunk_cnt, chunk_pos, out);
+                       desc, nitems, flag, fpos, chunk_cnt, chunk_pos, nlim, out);
 }
 
 void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
@@ -920,10 +1088,11 @@ void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s) 
 
 void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
                      const int64_t *ibase, const int64_t *cbase, const int64_t *sbase,
-                     int64_t nitems, int kper, ChunkDesc *desc, hipStream_t s) {
+                     int64_t nitems, int kper, const int32_t *mstart, const int64_t *nlim,
+                     ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_sym_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
-                       items, item_of, ibase, cbase, sbase, nitems, kper, desc);
+                       items, item_of, ibase, cbase, sbase, nitems, kper, mstart, nlim, desc);
 }
 
 void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *len,
@@ -934,19 +1103,28 @@ void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh
 }
 
 void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *sbase,
-                 uint32_t *sabs, hipStream_t s) {
+                 uint32_t *sabs, int merge, int64_t cap, const int64_t *cbase, int32_t *mstart,
+                 int64_t *nitem, hipStream_t s) {
     if (nh <= 0) return;
     hipLaunchKernelGGL(k_sabs, dim3((unsigned)nh), dim3(256), 0, s, prods, items, nh, sbase,
-                       sabs);
+                       sabs, merge, cap, cbase, mstart, nitem);
+}
+
+void launch_num_nitems(const ProdDev *prods, const uint64_t *ditems, int64_t n,
+                       const int32_t *hslot, const int64_t *nitem, int64_t *dnch, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_num_nitems, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prods,
+                       ditems, n, hslot, nitem, dnch);
 }
 
 void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t *item_of,
                      const int64_t *dbase, int64_t nitems, int kper, const int32_t *hslot,
                      const int64_t *cbase, const int64_t *sbase, const int64_t *rptv,
-                     ChunkDesc *desc, hipStream_t s) {
+                     const int32_t *mstart, const int64_t *nlim, ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_num_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
-                       ditems, item_of, dbase, nitems, kper, hslot, cbase, sbase, rptv, desc);
+                       ditems, item_of, dbase, nitems, kper, hslot, cbase, sbase, rptv, mstart,
+                       nlim, desc);
 }
 
 template <bool FAST>
@@ -971,53 +1149,61 @@ static void sym_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *de
 template <int WG, int WMAX>
 static void sym_pipe_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
                             int64_t nitems, int64_t *chunk_cnt, int64_t *row_nnz,
-                            uint32_t *sbits, int wpc, int wgs_per_cu, hipStream_t s) {
+                            uint32_t *sbits, int wpc, int wgs_per_cu, int *err, hipStream_t s) {
     const unsigned g = pipe_grid(wgs_per_cu, nitems);
     hipLaunchKernelGGL((k_sym_chunk_pipe<WG, WMAX>), dim3(g), dim3(WG), 0, s, prods, desc, nitems,
-                       sabs, chunk_cnt, row_nnz, sbits, wpc);
+                       sabs, chunk_cnt, row_nnz, sbits, wpc, err);
 }
 
 template <int WMAX>
 static void sym_pipe_wg(int wg, const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
                         int64_t nitems, int64_t *chunk_cnt, int64_t *row_nnz, uint32_t *sbits,
-                        int wpc, int wgs_per_cu, hipStream_t s) {
+                        int wpc, int wgs_per_cu, int *err, hipStream_t s) {
     switch (wg) {
     case 64:
         sym_pipe_launch<64, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
-                                  wgs_per_cu, s);
+                                  wgs_per_cu, err, s);
         break;
     case 128:
         sym_pipe_launch<128, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
-                                   wgs_per_cu, s);
+                                   wgs_per_cu, err, s);
         break;
     case 512:
         sym_pipe_launch<512, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
-                                   wgs_per_cu, s);
+                                   wgs_per_cu, err, s);
         break;
     default:
         sym_pipe_launch<256, WMAX>(prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
-                                   wgs_per_cu, s);
+                                   wgs_per_cu, err, s);
     }
 }
 
+// wmax: widest item (merged items included).
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
                       int64_t *row_nnz, uint32_t *sbits, int wpc, int wgs_per_cu, int threads,
-                      hipStream_t s) {
+                      int *err, hipStream_t s) {
     if (nitems <= 0) return;
     if (fast && kper == 1) {
+        const int t = threads ? threads : 64;
         if (wmax <= 2048)
-            sym_pipe_wg<2048>(threads ? threads : 64, prods, desc, sabs, nitems, chunk_cnt,
-                              row_nnz, sbits, wpc, wgs_per_cu, s);
+            sym_pipe_wg<2048>(t, prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                              wgs_per_cu, err, s);
         else if (wmax <= 4096)
-            sym_pipe_wg<4096>(threads ? threads : 128, prods, desc, sabs, nitems, chunk_cnt,
-                              row_nnz, sbits, wpc, wgs_per_cu, s);
+            sym_pipe_wg<4096>(t, prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                              wgs_per_cu, err, s);
         else if (wmax <= 8192)
-            sym_pipe_wg<8192>(threads ? threads : 256, prods, desc, sabs, nitems, chunk_cnt,
-                              row_nnz, sbits, wpc, wgs_per_cu, s);
+            sym_pipe_wg<8192>(t, prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                              wgs_per_cu, err, s);
+        else if (wmax <= 16384)
+            sym_pipe_wg<16384>(t, prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                               wgs_per_cu, err, s);
+        else if (wmax <= 32768)
+            sym_pipe_wg<32768>(t, prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits, wpc,
+                               wgs_per_cu, err, s);
         else
-            sym_pipe_wg<kMaxChunkCols>(threads ? threads : 256, prods, desc, sabs, nitems,
-                                       chunk_cnt, row_nnz, sbits, wpc, wgs_per_cu, s);
+            sym_pipe_wg<kMaxItemCols>(t, prods, desc, sabs, nitems, chunk_cnt, row_nnz, sbits,
+                                      wpc, wgs_per_cu, err, s);
         return;
     }
     if (fast)
@@ -1082,6 +1268,7 @@ bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
     return fast && kper == 1 && rank_cap > 0;
 }
 
+// wmax: widest item of the launch.
 void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
                            const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
                            const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
@@ -1096,9 +1283,15 @@ void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc
     else if (wmax <= 8192)
         num_rank_launch<8192>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
                               rank_cap, resolved, err, s);
+    else if (wmax <= 16384)
+        num_rank_launch<16384>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                               rank_cap, resolved, err, s);
+    else if (wmax <= 32768)
+        num_rank_launch<32768>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
+                               rank_cap, resolved, err, s);
     else
-        num_rank_launch<kMaxChunkCols>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits,
-                                       wpc, rank_cap, resolved, err, s);
+        num_rank_launch<kMaxItemCols>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits,
+                                      wpc, rank_cap, resolved, err, s);
 }
 
 template <int WMAX>

@@ -34,7 +34,7 @@ class Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("chunks_per_item", ctypes.c_int32),
                 ("chunk_wgs_per_cu", ctypes.c_int32), ("chunk_threads", ctypes.c_int32),
                 ("sym_chunk_threads", ctypes.c_int32), ("num_rank_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("chunk_merge", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Info(ctypes.Structure):
@@ -132,7 +132,8 @@ def default_options() -> Options:
 
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
                  profile=None, chunks_per_item=None, chunk_wgs_per_cu=None,
-                 chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None) -> Options:
+                 chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None,
+                 chunk_merge=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -156,6 +157,8 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.sym_chunk_threads = int(sym_chunk_threads)
     if num_rank_cap is not None:
         o.num_rank_cap = int(num_rank_cap)
+    if chunk_merge is not None:
+        o.chunk_merge = int(chunk_merge)
     return o
 
 

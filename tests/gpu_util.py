@@ -14,7 +14,8 @@ NUM_CAP = [0, 32, 64, 128, 256, 2048, 8192]
 
 def forced_options(group: int, chunk_cols: int | None = None, chunks_per_item: int | None = None,
                    chunk_wgs_per_cu: int | None = None, chunk_threads: int | None = None,
-                   num_rank_cap: int | None = None, sym_chunk_threads: int | None = None):
+                   num_rank_cap: int | None = None, sym_chunk_threads: int | None = None,
+                   chunk_merge: int | None = None):
     """Options that send every row whose key fits to `group` (1..7)."""
     sym = [0] * 7
     num = [0] * 7
@@ -29,7 +30,8 @@ def forced_options(group: int, chunk_cols: int | None = None, chunks_per_item: i
         num[g] = max(num[g], num[g - 1])
     return spgemm.make_options(sym, num, chunk_cols=chunk_cols, chunks_per_item=chunks_per_item,
                                chunk_wgs_per_cu=chunk_wgs_per_cu, chunk_threads=chunk_threads,
-                               num_rank_cap=num_rank_cap, sym_chunk_threads=sym_chunk_threads)
+                               num_rank_cap=num_rank_cap, sym_chunk_threads=sym_chunk_threads,
+                               chunk_merge=chunk_merge)
 
 
 def log(msg):

@@ -75,7 +75,8 @@ def _create(a, b, o):
                                          ("chunk_cols", 32768), ("validate", 7),
                                          ("chunks_per_item", 3), ("chunk_wgs_per_cu", -1),
                                          ("chunk_wgs_per_cu", 65), ("chunk_threads", 96),
-                                         ("sym_chunk_threads", 32), ("num_rank_cap", 300)])
+                                         ("sym_chunk_threads", 32), ("num_rank_cap", 300),
+                                         ("chunk_merge", 3), ("chunk_merge", 16)])
 def test_bad_options_rejected(field, value):
     o = spgemm.default_options()
     setattr(o, field, value)

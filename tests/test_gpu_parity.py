@@ -104,6 +104,49 @@ def test_chunk_rank_accumulator(chunk_cols, cap, sym_threads):
                                                    sym_threads), exact=True, label=f"rank{cap}-int")
 
 
+@pytest.mark.parametrize("chunk_cols,cap,merge", [(256, 512, 2), (256, 1024, 4), (512, 2048, 8),
+                                                   (2048, 1024, 8), (8192, 1024, 4),
+                                                   (16384, 2048, 8), (4096, 512, 1)])
+def test_chunk_merging(chunk_cols, cap, merge):
+    # adjacent light chunks of a row merged into one item (products within the
+    # rank cap, at most `merge` chunks, at most 65536 columns)
+    a = gen.rmat(13, 16, seed=18)
+    run_and_compare(a, a, options=forced_options(7, chunk_cols, 1, None, None, cap,
+                                                 chunk_merge=merge), label=f"merge{merge}")
+    ai = gen.int_valued(gen.rmat(12, 16, seed=19), 5)
+    run_and_compare(ai, ai, options=forced_options(7, chunk_cols, 1, None, None, cap,
+                                                   chunk_merge=merge), exact=True,
+                    label=f"merge{merge}-int")
+    # ragged: B's columns not a multiple of the chunk width
+    b = gen.skewed_csr(a.ncols, 7001, seed=20, max_len=40, heavy_rows=5, heavy_len=3000)
+    run_and_compare(a, b, options=forced_options(7, chunk_cols, 1, None, None, cap,
+                                                 chunk_merge=merge), label=f"merge{merge}-ragged")
+
+
+def test_chunk_merging_many_chunks():
+    # rows with more chunks than the merge table holds (512 chunks of 64
+    # columns) keep one item per chunk, next to merged rows of a second
+    # product (64 chunks) in the same batch
+    import torch
+    a1 = gen.rmat(15, 8, seed=21)
+    a2 = gen.rmat(12, 16, seed=22)
+    opt = forced_options(7, 64, 1, None, None, 1024, chunk_merge=8)
+    log("[gpu] merge batch: rmat15 (512 chunks per row) + rmat12 (64 chunks per row)")
+    d1, d2 = spgemm.to_device(a1), spgemm.to_device(a2)
+    plan = spgemm.Plan([d1, d2], [d1, d2], opt)
+    plan.symbolic()
+    cols, vals = plan.allocate_outputs()
+    plan.numeric(cols, vals)
+    torch.cuda.synchronize()
+    for a, rpt, col, val, rows in ((a1, plan.rpts[0], cols[0], vals[0], np.arange(0, a1.nrows, 97)),
+                                   (a2, plan.rpts[1], cols[1], vals[1], None)):
+        ref = oracle.product(a, a, rows)
+        msg = oracle.compare(ref, rpt.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(),
+                             rows=rows)
+        assert msg is None, msg
+    plan.free()
+
+
 def test_chunk_unsorted_b():
     a = gen.rmat(11, 16, seed=12)
     b = gen.shuffle_rows(a, 3)
