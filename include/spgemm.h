@@ -141,7 +141,8 @@ typedef struct {
      * together stay within num_rank_cap; a merged item then has at most that
      * many outputs and always takes the rank path.  Needs sorted B rows,
      * chunks_per_item = 1 and num_rank_cap > 0 (else no merging); an item
-     * spans at most 65536 columns. */
+     * spans at most 65536 columns, and rows of more than 64 chunks are not
+     * merged. */
     int32_t chunk_merge;
     int32_t reserved[1];
 } spgemm_options;

@@ -55,7 +55,7 @@ struct spgemm_plan {
     size_t scan_tmp_bytes = 0;
 
     // chunk group (symbolic group 7)
-    int64_t nh = 0, h_items = 0, h_split = 0;
+    int64_t nh = 0, h_items = 0, h_split = 0, h_tiles = 0;
     int64_t *nchv = nullptr, *ibase = nullptr, *cbase = nullptr, *chunk_cnt = nullptr;
     int64_t *chunk_pos = nullptr;
     int32_t *hitem_row = nullptr;
@@ -354,7 +354,8 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
     const GroupBounds gb = bounds_of(p->opt.sym_upper);
     {
         TimeScope ts(p, "plan.ipcount");
-        launch_ipcount(p->dprods, p->dblks, p->nblk, gb, p->ip, p->blkcnt, p->stats, p->stream);
+        launch_ipcount(p->dprods, p->dblks, p->nblk, gb, p->ip, p->blkcnt, p->stats, M,
+                       p->stream);
     }
     ST_TRY(launch_check());
     {
@@ -389,6 +390,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         p->nh += (int64_t)ps[q].h_rows;
         p->h_split += (int64_t)ps[q].h_split;
         p->h_items += (int64_t)ps[q].h_items;
+        p->h_tiles += (int64_t)ps[q].h_tiles;
         if (p->hprods[q].b_sorted == 2) p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
         if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
     }
@@ -442,10 +444,29 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
             launch_row_splitlen(p->dprods, hitems, nh, p->slen, p->stream);
             ST_TRY(launch_check());
             ST_TRY(scan(p, p->slen, p->sbase, nh));
-            // with merging, also the items of every row (nchv = items per row)
-            launch_sabs(p->dprods, hitems, nh, p->sbase, p->sabs, p->merge,
-                        p->opt.num_rank_cap, p->cbase, p->mstart, p->nchv, p->stream);
+            // one workgroup per tile of A nonzeros of every row
+            int64_t *ntile = nullptr, *tbase = nullptr;
+            int32_t *tile_row = nullptr;
+            unsigned long long *ipc = nullptr;
+            ST_TRY(dalloc(p, &ntile, nh));
+            ST_TRY(dalloc(p, &tbase, nh + 1));
+            ST_TRY(dalloc(p, &tile_row, p->h_tiles));
+            launch_sabs_tiles(p->dprods, hitems, nh, ntile, p->stream);
             ST_TRY(launch_check());
+            ST_TRY(scan(p, ntile, tbase, nh));
+            launch_expand(tbase, nh, tile_row, p->stream);
+            if (p->merge > 1) {
+                ST_TRY(dalloc(p, &ipc, p->h_items));
+                launch_fill_i64((int64_t *)ipc, p->h_items, 0, p->stream);
+            }
+            launch_sabs(p->dprods, hitems, p->h_tiles, tile_row, tbase, p->sbase, p->sabs,
+                        p->cbase, ipc, p->stream);
+            ST_TRY(launch_check());
+            if (p->merge > 1) {  // the items of every row (nchv = items per row)
+                launch_chunk_items(p->dprods, hitems, nh, p->merge, p->opt.num_rank_cap,
+                                   p->cbase, ipc, p->mstart, p->nchv, p->stream);
+                ST_TRY(launch_check());
+            }
         }
         if (p->merge == 1) {
             launch_nch_of(p->dprods, hitems, nh, p->opt.chunks_per_item, p->nchv, p->stream);

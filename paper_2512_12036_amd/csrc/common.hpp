@@ -14,7 +14,10 @@ constexpr int64_t kIpPerLane = 16;   // numeric grouping: target products per la
 constexpr int64_t kDirectG4 = 512;   // table slots of group 4 (64 lanes x 8)
 constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 dense accumulator
 constexpr int kMaxItemCols = 65536;  // widest merged item (8 KiB LDS bitmap)
-constexpr int kMaxMergeChunks = 256; // rows with more chunks are not merged
+constexpr int kSabsJ = 64;           // A nonzeros per workgroup of the sub-range tables
+constexpr int kSabsC = 64;           // chunk bounds per LDS tile of them; rows of more
+                                     // chunks are not merged
+constexpr int kIpSlices = 16;        // workgroups per row block in the IP count
 constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
 // Largest key each group can take (tables at most half full).
 constexpr int64_t kSymCap[kGroups] = {0, 32, 64, 128, 256, 4096, 16384, 0};
@@ -80,7 +83,8 @@ struct ProdStats {
     unsigned long long h_items;   // sum of nch
     unsigned long long d_rows;    // numeric group-7 rows
     unsigned long long d_items;   // sum of nch over them
-    unsigned long long pad[6];
+    unsigned long long h_tiles;   // sum of ceil(alen / kSabsJ) over symbolic group-7 rows
+    unsigned long long pad[5];
 };
 
 __device__ __forceinline__ uint64_t pack_item(int p, int64_t i) {
@@ -114,9 +118,12 @@ void launch_detect_sorted(ProdDev *prods, int nprod, const ProdDev *host_prods,
 void launch_validate_rows(const CsrCheck &c, int *bad, hipStream_t s);
 void launch_validate_cols(const CsrCheck &c, int *bad, hipStream_t s);
 
+// ip[row] of every row (zeroed, then accumulated), then the symbolic group
+// histograms and statistics.
 void launch_ipcount(const ProdDev *prods, const RowBlk *blks, int nblk,
                     GroupBounds gb, int64_t *ip, int64_t *blkcnt, ProdStats *stats,
-                    hipStream_t s);
+                    int64_t nrows, hipStream_t s);
+// Numeric group histograms (key = output lengths).
 void launch_count_groups(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
                          const int64_t *key, const int64_t *ip, int64_t *blkcnt,
                          ProdStats *stats, hipStream_t s);
@@ -133,9 +140,19 @@ void launch_nch_of(const ProdDev *prods, const uint64_t *items, int64_t n, int d
 void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s);
 void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *len,
                          hipStream_t s);
-void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *sbase,
-                 uint32_t *sabs, int merge, int64_t cap, const int64_t *cbase, int32_t *mstart,
-                 int64_t *nitem, hipStream_t s);
+// Sub-range tables of the group-7 rows (fast path), one workgroup per tile of
+// kSabsJ A nonzeros: ntile / tbase / tile_row give the tiles of every row.
+// With ipc (zeroed, one entry per chunk slot), the chunks' intermediate
+// products are accumulated too, and launch_chunk_items then forms the merged
+// work items of every row (mstart / nitem).
+void launch_sabs_tiles(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *ntile,
+                       hipStream_t s);
+void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t ntiles,
+                 const int32_t *tile_row, const int64_t *tbase, const int64_t *sbase,
+                 uint32_t *sabs, const int64_t *cbase, unsigned long long *ipc, hipStream_t s);
+void launch_chunk_items(const ProdDev *prods, const uint64_t *items, int64_t nh, int merge,
+                        int64_t cap, const int64_t *cbase, const unsigned long long *ipc,
+                        int32_t *mstart, int64_t *nitem, hipStream_t s);
 void launch_num_nitems(const ProdDev *prods, const uint64_t *ditems, int64_t n,
                        const int32_t *hslot, const int64_t *nitem, int64_t *dnch, hipStream_t s);
 void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,

@@ -74,90 +74,121 @@ __global__ void k_row_splitlen(const ProdDev *__restrict__ prods,
     len[h] = (P.rptA[i + 1] - P.rptA[i]) * (int64_t)(P.nch + 1);
 }
 
-// Sub-range table of one group-7 row (fast path: sorted B, < 2^30 entries):
+// ntile[h] = tiles of kSabsJ A nonzeros of group-7 row h.
+__global__ void k_sabs_tiles(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
+                             int64_t nh, int64_t *__restrict__ ntile) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= nh) return;
+    const uint64_t e = items[h];
+    const ProdDev &P = prods[item_prod(e)];
+    const int64_t i = item_row(e);
+    ntile[h] = (P.rptA[i + 1] - P.rptA[i] + kSabsJ - 1) / kSabsJ;
+}
+
+// Sub-range table of the group-7 rows (fast path: sorted B, < 2^30 entries):
 // sabs[sbase[h] + c * alen + j] = absolute position in B of the first entry of
 // B row colA[a0 + j] with column >= c * W, for c = 0..nch.  Chunk c of the row
 // then reads, for every nonzero j, the range [sabs[c][j], sabs[c+1][j]) with
-// two coalesced loads.
-//
-// With mstart set, the row's work items are formed here as well.  The
-// intermediate products of every chunk are summed (a wave sum per chunk, one
-// LDS atomic per wave), then adjacent chunks are merged in column order while
-// their products together stay within `cap` and at most `merge` of them are
-// taken: mstart[cbase[h] + k] = first chunk of item k and nitem[h] = the
-// row's item count.  A merged item has at most cap outputs.  Rows with more
-// than kMaxMergeChunks chunks keep one item per chunk.
+// two coalesced loads.  One workgroup per tile of kSabsJ nonzeros of a row, so
+// a row with many nonzeros is spread over many workgroups.  The tile's bounds
+// are staged in LDS kSabsC at a time: the bounds of one B row are contiguous
+// in bsplit, so the gathers run with lanes over bounds and the stores with
+// lanes over nonzeros, both coalesced.  With ipc, the tile's products per
+// chunk are added to ipc[cbase[h] + c] (rows of at most kSabsC chunks).
 __global__ __launch_bounds__(256) void k_sabs(const ProdDev *__restrict__ prods,
-                                               const uint64_t *__restrict__ items, int64_t nh,
+                                               const uint64_t *__restrict__ items,
+                                               const int32_t *__restrict__ tile_row,
+                                               const int64_t *__restrict__ tbase,
                                                const int64_t *__restrict__ sbase,
-                                               uint32_t *__restrict__ sabs, int merge,
-                                               int64_t cap, const int64_t *__restrict__ cbase,
-                                               int32_t *__restrict__ mstart,
-                                               int64_t *__restrict__ nitem) {
-    __shared__ unsigned long long ipc[kMaxMergeChunks];
-    const int64_t h = blockIdx.x;
+                                               uint32_t *__restrict__ sabs,
+                                               const int64_t *__restrict__ cbase,
+                                               unsigned long long *__restrict__ ipc) {
+    __shared__ uint32_t tile[kSabsC + 1][kSabsJ + 1];  // [bound][nonzero], padded
+    __shared__ int32_t kk[kSabsJ];                     // B row of each nonzero of the tile
+    __shared__ uint32_t bb[kSabsJ];                    // its first position in B
+    const int64_t t = blockIdx.x;
+    const int64_t h = tile_row[t];
     const uint64_t e = items[h];
     const ProdDev &P = prods[item_prod(e)];
     const int64_t i = item_row(e);
     const int64_t a0 = P.rptA[i];
     const int64_t alen = P.rptA[i + 1] - a0;
+    const int64_t jt = (t - tbase[h]) * kSabsJ;
+    const int nj = (int)(alen - jt < kSabsJ ? alen - jt : kSabsJ);
     const int nch = P.nch;
     const int per = nch + 1;
-    const bool mg = mstart != nullptr && merge > 1 && nch <= kMaxMergeChunks;
-    const int lane = threadIdx.x & 63;
-    if (mg) {
-        for (int c = threadIdx.x; c < nch; c += 256) ipc[c] = 0ull;
-        __syncthreads();
-    }
+    const int tid = threadIdx.x;
     uint32_t *out = sabs + sbase[h];
-    for (int64_t jb = 0; jb < alen; jb += 256) {
-        const int64_t j = jb + threadIdx.x;
-        const bool valid = j < alen;
-        // wave-uniform: some lane of this wave holds a nonzero
-        const bool wave_live = jb + (threadIdx.x & ~63) < alen;
-        int64_t b0 = 0;
-        const int32_t *bs = nullptr;
-        if (valid) {
-            const int k = gld(P.colA + a0 + j);
-            b0 = gld(P.rptB + k);
-            bs = P.bsplit + (int64_t)k * per;
+    const bool acc = ipc != nullptr && nch <= kSabsC;
+    if (tid < nj) {
+        const int k = gld(P.colA + a0 + jt + tid);
+        kk[tid] = k;
+        bb[tid] = (uint32_t)gld(P.rptB + k);
+    }
+    for (int ct = 0; ct < per; ct += kSabsC) {
+        const int nc = per - ct < kSabsC + 1 ? per - ct : kSabsC + 1;  // bounds staged
+        const int ns = nc < kSabsC ? nc : kSabsC;                      // bounds stored
+        __syncthreads();
+        for (int f = tid; f < nj * nc; f += 256) {
+            const int jl = f / nc, cl = f - jl * nc;
+            tile[cl][jl] = bb[jl] + (uint32_t)gld(P.bsplit + (int64_t)kk[jl] * per + ct + cl);
         }
-        uint32_t prev = 0u;
-        for (int c = 0; c < per; ++c) {
-            uint32_t v = 0u;
-            if (valid) {
-                v = (uint32_t)(b0 + gld(bs + c));
-                out[(int64_t)c * alen + j] = v;
-            }
-            if (mg && c > 0 && wave_live) {
-                unsigned long long len = valid ? (unsigned long long)(v - prev) : 0ull;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) len += __shfl_xor(len, off, 64);
-                if (lane == 0 && len) atomicAdd(&ipc[c - 1], len);
-            }
-            prev = v;
+        __syncthreads();
+        for (int f = tid; f < ns * kSabsJ; f += 256) {
+            const int cl = f / kSabsJ, jl = f - cl * kSabsJ;
+            if (jl < nj) out[(int64_t)(ct + cl) * alen + jt + jl] = tile[cl][jl];
+        }
+        if (acc && tid < nch) {  // one staged tile holds every bound of the row
+            unsigned long long sum = 0ull;
+            for (int jl = 0; jl < nj; ++jl) sum += tile[tid + 1][jl] - tile[tid][jl];
+            if (sum) atomicAdd(ipc + cbase[h] + tid, sum);
         }
     }
-    if (mstart == nullptr) return;
+}
+
+// Work items of the group-7 rows when adjacent chunks are merged, one wave
+// per row: chunks are merged in column order while their intermediate
+// products (ipc) together stay within `cap` and at most `merge` of them are
+// taken; mstart[cbase[h] + k] = first chunk of item k and nitem[h] = the
+// row's item count.  A merged item therefore has at most cap outputs.  Rows
+// of more than kSabsC chunks keep one item per chunk.
+__global__ __launch_bounds__(256) void k_chunk_items(const ProdDev *__restrict__ prods,
+                                                      const uint64_t *__restrict__ items,
+                                                      int64_t nh, int merge, int64_t cap,
+                                                      const int64_t *__restrict__ cbase,
+                                                      const unsigned long long *__restrict__ ipc,
+                                                      int32_t *__restrict__ mstart,
+                                                      int64_t *__restrict__ nitem) {
+    static_assert(kSabsC <= 64, "one chunk per lane");
+    const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (h >= nh) return;  // wave-uniform
+    const int nch = prods[item_prod(items[h])].nch;
     int32_t *ms = mstart + cbase[h];
-    if (!mg) {
-        for (int c = threadIdx.x; c < nch; c += 256) ms[c] = c;
-        if (threadIdx.x == 0) nitem[h] = nch;
+    if (nch > kSabsC) {
+        for (int c = lane; c < nch; c += 64) ms[c] = c;
+        if (lane == 0) nitem[h] = nch;
         return;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int k = 0;
-        for (int c = 0; c < nch;) {
-            unsigned long long sum = ipc[c];
-            int e2 = c + 1;
-            while (e2 < nch && e2 - c < merge && sum + ipc[e2] <= (unsigned long long)cap)
-                sum += ipc[e2++];
-            ms[k++] = c;
-            c = e2;
+    // lane c holds chunk c's products, saturated at cap + 1 (32 bits)
+    const unsigned long long v = lane < nch ? ipc[cbase[h] + lane] : 0ull;
+    const uint32_t sat = (uint32_t)(cap < 0x7ffffffe ? cap + 1 : 0x7fffffff);
+    const uint32_t mine = v < sat ? (uint32_t)v : sat;
+    int k = 0;
+    for (int c = 0; c < nch;) {
+        uint64_t sum = __builtin_amdgcn_readlane(mine, c);
+        int e2 = c + 1;
+        while (e2 < nch && e2 - c < merge) {
+            const uint64_t x = __builtin_amdgcn_readlane(mine, e2);
+            if (sum + x > (uint64_t)cap) break;
+            sum += x;
+            ++e2;
         }
-        nitem[h] = k;
+        if (lane == 0) ms[k] = c;
+        ++k;
+        c = e2;
     }
+    if (lane == 0) nitem[h] = k;
 }
 
 // dnch[r] = items of numeric group-7 row r: those its symbolic row was given.
@@ -1102,12 +1133,27 @@ void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh
                        items, nh, len);
 }
 
-void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t nh, const int64_t *sbase,
-                 uint32_t *sabs, int merge, int64_t cap, const int64_t *cbase, int32_t *mstart,
-                 int64_t *nitem, hipStream_t s) {
+void launch_sabs_tiles(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *ntile,
+                       hipStream_t s) {
     if (nh <= 0) return;
-    hipLaunchKernelGGL(k_sabs, dim3((unsigned)nh), dim3(256), 0, s, prods, items, nh, sbase,
-                       sabs, merge, cap, cbase, mstart, nitem);
+    hipLaunchKernelGGL(k_sabs_tiles, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, prods,
+                       items, nh, ntile);
+}
+
+void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t ntiles,
+                 const int32_t *tile_row, const int64_t *tbase, const int64_t *sbase,
+                 uint32_t *sabs, const int64_t *cbase, unsigned long long *ipc, hipStream_t s) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_sabs, dim3((unsigned)ntiles), dim3(256), 0, s, prods, items, tile_row,
+                       tbase, sbase, sabs, cbase, ipc);
+}
+
+void launch_chunk_items(const ProdDev *prods, const uint64_t *items, int64_t nh, int merge,
+                        int64_t cap, const int64_t *cbase, const unsigned long long *ipc,
+                        int32_t *mstart, int64_t *nitem, hipStream_t s) {
+    if (nh <= 0) return;
+    hipLaunchKernelGGL(k_chunk_items, dim3((unsigned)((nh + 3) / 4)), dim3(256), 0, s, prods,
+                       items, nh, merge, cap, cbase, ipc, mstart, nitem);
 }
 
 void launch_num_nitems(const ProdDev *prods, const uint64_t *ditems, int64_t n,

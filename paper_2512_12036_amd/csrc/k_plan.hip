@@ -1,10 +1,12 @@
 // Row-size estimation, row grouping and scans.
 //
-//  * k_ipcount: intermediate products of every row (paper Algorithm 1).  All
-//    threads of a block walk the nonzeros of its 256 rows together, so a row
-//    of thousands of nonzeros does not serialise on one lane; per-lane counts
-//    are combined with a segmented wavefront scan and one LDS atomic per row
-//    segment.  The same pass builds the block's group histogram.
+//  * k_ipcount: intermediate products of every row (paper Algorithm 1).  The
+//    nonzeros of a block of 256 rows are cut into kIpSlices slices, one
+//    workgroup each, whose threads walk them together, so neither a row of
+//    thousands of nonzeros nor a block of hub rows serialises on a few
+//    lanes; per-lane counts are combined with a segmented wavefront scan, an
+//    LDS atomic per row segment and a global atomic per row.  k_ip_groups
+//    then builds the block's group histogram.
 //  * k_scatter: the row map of paper Section III-B.  Rows are not moved; the
 //    map lists rows group by group.  Positions come from an exclusive scan of
 //    the per-block histograms (group-major, block-minor) plus wavefront
@@ -169,7 +171,7 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
                                                 int64_t *blkcnt, ProdStats *st, int nch,
                                                 bool ip_stats, int64_t ncols) {
     __shared__ int hist[kGroups];
-    __shared__ unsigned long long red[kRowBlock / 64][4];
+    __shared__ unsigned long long red[kRowBlock / 64][5];
     if (threadIdx.x < kGroups) hist[threadIdx.x] = 0;
     __syncthreads();
     const int g = valid ? group_of(gkey, gb, ncols) : -1;
@@ -183,6 +185,8 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
     unsigned long long km = ks;
     unsigned long long hr = (g == kChunkGroup) ? 1ull : 0ull;
     unsigned long long ha = (g == kChunkGroup) ? (unsigned long long)alen : 0ull;
+    unsigned long long ht = (g == kChunkGroup) ? (unsigned long long)((alen + kSabsJ - 1) / kSabsJ)
+                                               : 0ull;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         ks += __shfl_down(ks, off, 64);
@@ -190,17 +194,25 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
         km = o > km ? o : km;
         hr += __shfl_down(hr, off, 64);
         ha += __shfl_down(ha, off, 64);
+        ht += __shfl_down(ht, off, 64);
     }
-    if (lane == 0) { red[w][0] = ks; red[w][1] = km; red[w][2] = hr; red[w][3] = ha; }
+    if (lane == 0) {
+        red[w][0] = ks;
+        red[w][1] = km;
+        red[w][2] = hr;
+        red[w][3] = ha;
+        red[w][4] = ht;
+    }
     __syncthreads();
     if (threadIdx.x < kGroups) blkcnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = hist[threadIdx.x];
     if (threadIdx.x == 0) {
-        unsigned long long s = 0, mx = 0, rows = 0, al = 0;
+        unsigned long long s = 0, mx = 0, rows = 0, al = 0, tl = 0;
         for (int i = 0; i < kRowBlock / 64; ++i) {
             s += red[i][0];
             mx = red[i][1] > mx ? red[i][1] : mx;
             rows += red[i][2];
             al += red[i][3];
+            tl += red[i][4];
         }
         if (ip_stats) {
             atomicAdd(&st->ip_sum, s);
@@ -208,6 +220,7 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
             if (rows) {
                 atomicAdd(&st->h_rows, rows);
                 atomicAdd(&st->h_alen, al);
+                atomicAdd(&st->h_tiles, tl);
                 atomicAdd(&st->h_split, al * (unsigned long long)(nch + 1));
                 atomicAdd(&st->h_items, rows * (unsigned long long)nch);
             }
@@ -222,11 +235,15 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
     }
 }
 
+// IP count, accumulation pass: workgroup (b, s) takes slice s of the A
+// nonzeros of row block b (kIpSlices slices), so a block holding hub rows of
+// many thousands of nonzeros is spread over kIpSlices workgroups.  Per-lane
+// B-row lengths are combined with a segmented wavefront scan and one LDS
+// atomic per row segment, then added to ip[row] (zeroed beforehand) with one
+// global atomic per row touched.
 __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict__ prods,
-                                                        const RowBlk *__restrict__ blks, int nblk,
-                                                        GroupBounds gb, int64_t *__restrict__ ip,
-                                                        int64_t *__restrict__ blkcnt,
-                                                        ProdStats *__restrict__ stats) {
+                                                        const RowBlk *__restrict__ blks,
+                                                        int64_t *__restrict__ ip) {
     __shared__ int64_t rp[kRowBlock + 1];
     __shared__ unsigned long long acc[kRowBlock];
     const RowBlk blk = blks[blockIdx.x];
@@ -235,7 +252,11 @@ __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict
     for (int t = threadIdx.x; t <= nr; t += kRowBlock) rp[t] = P.rptA[blk.i0 + t];
     acc[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t j0 = rp[0], j1 = rp[nr];
+    const int64_t b0 = rp[0], b1 = rp[nr];
+    const int64_t len_s = (b1 - b0 + kIpSlices - 1) / kIpSlices;
+    const int64_t j0 = b0 + len_s * blockIdx.y;
+    const int64_t j1 = j0 + len_s < b1 ? j0 + len_s : b1;
+    if (j0 >= j1) return;  // uniform
     const int lane = threadIdx.x & 63;
     constexpr int U = 4;
     for (int64_t jb = j0; jb < j1; jb += (int64_t)kRowBlock * U) {
@@ -269,10 +290,25 @@ __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict
         }
     }
     __syncthreads();
-    const bool valid = threadIdx.x < nr;
-    const int64_t key = valid ? (int64_t)acc[threadIdx.x] : 0;
-    const int64_t alen = valid ? rp[threadIdx.x + 1] - rp[threadIdx.x] : 0;
-    if (valid) ip[P.row_base + blk.i0 + threadIdx.x] = key;
+    if (threadIdx.x < nr && acc[threadIdx.x])
+        atomicAdd((unsigned long long *)&ip[P.row_base + blk.i0 + threadIdx.x],
+                  acc[threadIdx.x]);
+}
+
+// IP count, grouping pass: the block's symbolic group histogram and the
+// per-product statistics, from the finished ip[].
+__global__ __launch_bounds__(kRowBlock) void k_ip_groups(const ProdDev *__restrict__ prods,
+                                                          const RowBlk *__restrict__ blks,
+                                                          int nblk, GroupBounds gb,
+                                                          const int64_t *__restrict__ ip,
+                                                          int64_t *__restrict__ blkcnt,
+                                                          ProdStats *__restrict__ stats) {
+    const RowBlk blk = blks[blockIdx.x];
+    const ProdDev &P = prods[blk.p];
+    const bool valid = threadIdx.x < blk.nrows;
+    const int64_t row = blk.i0 + threadIdx.x;
+    const int64_t key = valid ? ip[P.row_base + row] : 0;
+    const int64_t alen = valid ? P.rptA[row + 1] - P.rptA[row] : 0;
     block_histogram(key, sym_key(key, P.n), alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch,
                     true, P.n);
 }
@@ -420,9 +456,12 @@ void launch_validate_cols(const CsrCheck &c, int *bad, hipStream_t s) {
 }
 
 void launch_ipcount(const ProdDev *prods, const RowBlk *blks, int nblk, GroupBounds gb,
-                    int64_t *ip, int64_t *blkcnt, ProdStats *stats, hipStream_t s) {
+                    int64_t *ip, int64_t *blkcnt, ProdStats *stats, int64_t nrows,
+                    hipStream_t s) {
     if (nblk == 0) return;
-    hipLaunchKernelGGL(k_ipcount, dim3(nblk), dim3(kRowBlock), 0, s, prods, blks, nblk, gb, ip,
+    launch_fill_i64(ip, nrows, 0, s);
+    hipLaunchKernelGGL(k_ipcount, dim3(nblk, kIpSlices), dim3(kRowBlock), 0, s, prods, blks, ip);
+    hipLaunchKernelGGL(k_ip_groups, dim3(nblk), dim3(kRowBlock), 0, s, prods, blks, nblk, gb, ip,
                        blkcnt, stats);
 }
 
