@@ -17,7 +17,8 @@ constexpr int kMaxItemCols = 65536;  // widest merged item (8 KiB LDS bitmap)
 constexpr int kSabsJ = 64;           // A nonzeros per workgroup of the sub-range tables
 constexpr int kSabsC = 64;           // chunk bounds per LDS tile of them; rows of more
                                      // chunks are not merged
-constexpr int kIpSlices = 16;        // workgroups per row block in the IP count
+constexpr int kIpSlices = 32;        // most workgroups per row block in the IP count
+constexpr int64_t kIpMinSlice = 4096; // fewest A nonzeros per IP-count workgroup
 constexpr int kRowBlock = 256;       // rows per block in the grouping kernels
 // Largest key each group can take (tables at most half full).
 constexpr int64_t kSymCap[kGroups] = {0, 32, 64, 128, 256, 4096, 16384, 0};

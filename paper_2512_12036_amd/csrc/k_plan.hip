@@ -1,7 +1,7 @@
 // Row-size estimation, row grouping and scans.
 //
 //  * k_ipcount: intermediate products of every row (paper Algorithm 1).  The
-//    nonzeros of a block of 256 rows are cut into kIpSlices slices, one
+//    nonzeros of a block of 256 rows are cut into up to kIpSlices slices, one
 //    workgroup each, whose threads walk them together, so neither a row of
 //    thousands of nonzeros nor a block of hub rows serialises on a few
 //    lanes; per-lane counts are combined with a segmented wavefront scan, an
@@ -236,8 +236,9 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
 }
 
 // IP count, accumulation pass: workgroup (b, s) takes slice s of the A
-// nonzeros of row block b (kIpSlices slices), so a block holding hub rows of
-// many thousands of nonzeros is spread over kIpSlices workgroups.  Per-lane
+// nonzeros of row block b (up to kIpSlices slices of at least kIpMinSlice
+// nonzeros), so a block holding hub rows of many thousands of nonzeros is
+// spread over many workgroups.  Per-lane
 // B-row lengths are combined with a segmented wavefront scan and one LDS
 // atomic per row segment, then added to ip[row] (zeroed beforehand) with one
 // global atomic per row touched.
@@ -249,14 +250,16 @@ __global__ __launch_bounds__(kRowBlock) void k_ipcount(const ProdDev *__restrict
     const RowBlk blk = blks[blockIdx.x];
     const ProdDev &P = prods[blk.p];
     const int nr = blk.nrows;
-    for (int t = threadIdx.x; t <= nr; t += kRowBlock) rp[t] = P.rptA[blk.i0 + t];
-    acc[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t b0 = rp[0], b1 = rp[nr];
-    const int64_t len_s = (b1 - b0 + kIpSlices - 1) / kIpSlices;
+    // slices of at least kIpMinSlice nonzeros: most blocks need one workgroup
+    const int64_t b0 = P.rptA[blk.i0], b1 = P.rptA[blk.i0 + nr];
+    int64_t len_s = (b1 - b0 + kIpSlices - 1) / kIpSlices;
+    if (len_s < kIpMinSlice) len_s = kIpMinSlice;
     const int64_t j0 = b0 + len_s * blockIdx.y;
     const int64_t j1 = j0 + len_s < b1 ? j0 + len_s : b1;
     if (j0 >= j1) return;  // uniform
+    for (int t = threadIdx.x; t <= nr; t += kRowBlock) rp[t] = P.rptA[blk.i0 + t];
+    acc[threadIdx.x] = 0;
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     constexpr int U = 4;
     for (int64_t jb = j0; jb < j1; jb += (int64_t)kRowBlock * U) {
