@@ -225,41 +225,60 @@ __device__ __forceinline__ void staged_products(const S *st_s, const E *st_e, co
     }
 }
 
-// Same contract as staged_products, but striped: a wave takes consecutive
-// rows of 64 products and lane l handles product l of each row, so one load
-// instruction of the wave reads consecutive B entries (a few cache lines
-// instead of one line per lane) and the lanes of one accumulation step
-// mostly hit distinct columns of the same B row.  The owner of the wave's
-// first product comes from one (uniform) binary search; each lane then walks
-// forward across the B-row slices its products reach, one LDS read per slice
-// boundary.  f receives VT products per lane at a time (arrays + valid flags).
+// Lane groups of striped_products (see there).
+#ifndef SPG_STRIPE_GROUPS
+#define SPG_STRIPE_GROUPS 8
+#endif
+constexpr int kStripeGroups = SPG_STRIPE_GROUPS;
+
+// Same contract as staged_products, but striped.  A wave takes a contiguous
+// range of the batch's products and splits it between G groups of 64 / G
+// lanes; each group takes a contiguous sub-range in steps of 64 / G
+// products, lane k of the group handling product k of each step.  So one
+// load instruction reads G runs of consecutive B entries (a few cache lines
+// instead of one per lane), and a lane's successive products are only 64 / G
+// apart: the owner of each product is found by walking forward from the
+// lane's previous owner (one LDS round trip per B-row slice boundary
+// crossed), and short slices make long walks when the steps are wide.  The
+// owner of each group's first product comes from one binary search per
+// staged batch.  f receives VT products per lane at a time (arrays + valid
+// flags).
 template <int WG, int VT, bool VALUES, typename E, typename S, typename F>
 __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, const float *st_a,
                                                  int nv, E total, const int32_t *colB,
                                                  const float *valB, F &&f,
                                                  int tid = threadIdx.x) {
     constexpr bool kOff32 = sizeof(S) == 4;
+    constexpr int G = kStripeGroups;
+    constexpr int GL = 64 / G;  // lanes per group
+    static_assert(G >= 1 && G <= 64 && 64 % G == 0, "lane groups");
     const int32_t *ucol = uniform_ptr(colB);
     const float *uval = VALUES ? uniform_ptr(valB) : valB;
     constexpr int NW = WG / 64;
     const int lane = tid & 63, w = tid >> 6;
-    // wave w takes a contiguous range of 64-product rows, so its lanes only
-    // ever walk forward and one binary search per staged batch suffices
+    const int g = lane / GL, k = lane % GL;
+    // wave w takes a contiguous range of 64-product rows, group g a
+    // contiguous part of it, so lanes only ever walk forward
     const E nrow = (total + 63) >> 6;
     const E r0 = nrow * w / NW, r1 = nrow * (w + 1) / NW;
     if (r0 >= r1) return;
-    int o = __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, r0 * 64));
+    const E p0 = r0 * 64, p1 = r1 * 64 < total ? r1 * 64 : total;
+    const E sub = ((p1 - p0 + G - 1) / G + GL - 1) / GL * GL;  // per group, whole steps
+    const E g0 = p0 + (E)g * sub;
+    const E g1 = g0 + sub < p1 ? g0 + sub : p1;
+    int o = G == 1 ? __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, p0))
+                   : lds_owner<E>(st_e, 0, nv, g0 < total ? g0 : total - 1);
     E e0 = st_e[o], e1 = st_e[o + 1];
     S base = st_s[o];
     float a = VALUES ? st_a[o] : 0.f;
-    for (E r = r0; r < r1; r += VT) {
+    for (E s = 0; s < sub; s += (E)VT * GL) {
         int cc[VT];
         float aa[VT], vv[VT];
         bool ok[VT];
 #pragma unroll
         for (int v = 0; v < VT; ++v) {
-            const E q = (r + v) * 64 + lane;
-            ok[v] = r + v < r1 && q < total;
+            const E q = g0 + s + (E)(v * GL + k);
+            ok[v] = q < g1;
             cc[v] = 0;
             aa[v] = 0.f;
             vv[v] = 0.f;
