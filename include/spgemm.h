@@ -108,8 +108,9 @@ typedef struct {
     int64_t sym_upper[SPGEMM_NGROUPS - 1];
     int64_t num_upper[SPGEMM_NGROUPS - 1];
     /* Maximum columns per chunk of group 7 (multiple of 64, 64 .. 16384).  The
-     * number of chunks per row is a multiple of 8 so that chunk c of every
-     * row runs on the same accelerator die (XCD c mod 8). */
+     * number of chunks per row is a multiple of 8.  Chunk items are launched
+     * in row order, so that the chunks of one row share its A nonzeros and
+     * sub-range tables in cache. */
     int32_t chunk_cols;
     /* 0: host-side checks only; 1: also check row_ptr / col_idx of A and B
      * on the device (one pass each) and fail with SPGEMM_EINDEX. */

@@ -213,9 +213,10 @@ __global__ void k_nch_of(const ProdDev *__restrict__ prods, const uint64_t *__re
 // and sparse column ranges (column densities are skewed) and items carry
 // similar work.  One workgroup per item amortises the row's A staging over
 // K chunks.
-// The item order inside a row is rotated by the row index: workgroup index
-// modulo 8 selects the accelerator die, and with skewed column densities a
-// fixed item-to-die mapping would pile the dense column ranges on one die.
+// The item order inside a row is rotated by the row index, so that with
+// skewed column densities the dense column ranges of successive rows do not
+// land on the same positions of the launch (workgroups are dealt out to the
+// eight dies in turn).
 __device__ __forceinline__ int item_q(int64_t it, int64_t base, int64_t row, int nitems_row) {
     return (int)((it - base + row) % nitems_row);
 }
