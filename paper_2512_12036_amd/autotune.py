@@ -1,4 +1,5 @@
-"""Autotuner for the row-group bounds and the chunk width on the current GPU.
+"""Autotuner for the row-group bounds, the chunk width, the rank cap and the
+chunk merging on the current GPU.
 
 Paper Table I fixes four groups with hand-picked bounds for the paper's GPU;
 here the bounds of the eight gfx950 groups (see include/spgemm.h) and the
@@ -27,10 +28,14 @@ def candidates(quick: bool = False):
     """Candidate option sets (keyword arguments of spgemm.make_options)."""
     small = [0, 32, 64, 128, 256]
     out = []
-    for cc, cap, sthr in itertools.product([4096, 8192, 16384], [0, 512, 1024, 2048], [64, 128]):
+    for cc, cap, sthr, merge in itertools.product([4096, 8192, 16384], [0, 512, 1024, 2048],
+                                                  [64, 128], [1, 2, 4]):
+        if cap == 0 and merge > 1:
+            continue  # merging needs the rank accumulator
         out.append(dict(chunk_cols=cc, sym_upper=small + [1024, 1024],
                         num_upper=small + [1024, 1024], chunks_per_item=1, chunk_wgs_per_cu=0,
-                        chunk_threads=0, sym_chunk_threads=sthr, num_rank_cap=cap))
+                        chunk_threads=0, sym_chunk_threads=sthr, num_rank_cap=cap,
+                        chunk_merge=merge))
     if quick:
         out = [c for c in out if c["chunk_cols"] == 8192 and c["sym_chunk_threads"] == 64]
     return out

@@ -466,10 +466,10 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
 constexpr int NVT = 8;        // products per lane per round in the numeric chunk kernels
 constexpr int kDenseVT = 16;  // same for dense chunks (more gathers in flight per wave)
 constexpr int kEmitU = 8;     // columns per thread per round of the dense emission
-#ifndef SPG_RANK_WAVES
-#define SPG_RANK_WAVES 1
+#ifndef SPG_RANK_ITEMS
+#define SPG_RANK_ITEMS 1
 #endif
-constexpr int kRankWaves = SPG_RANK_WAVES;  // independent chunks (waves) per workgroup
+constexpr int kRankItems = SPG_RANK_ITEMS;  // consecutive items per wave of the rank kernel
 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
@@ -675,7 +675,7 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
 }
 
 template <int WG, int WMAX>
-__global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict__ prods,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_sym_chunk_pipe(const ProdDev *__restrict__ prods,
                                                        const ChunkDesc *__restrict__ desc,
                                                        int64_t nitems,
                                                        const uint32_t *__restrict__ sabs,
@@ -754,8 +754,11 @@ __global__ __launch_bounds__(WG) void k_sym_chunk_pipe(const ProdDev *__restrict
     }
 }
 
+// The dense accumulator's LDS allows four 256-thread workgroups per compute
+// unit at 8,192 columns, so the kernel asks for registers for four waves per
+// SIMD: one register more would cost a quarter of the occupancy.
 template <int WG, int WMAX>
-__global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict__ prods,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_num_chunk_pipe(const ProdDev *__restrict__ prods,
                                                        const ChunkDesc *__restrict__ desc,
                                                        int64_t nitems,
                                                        const uint32_t *__restrict__ sabs,
@@ -764,7 +767,8 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
                                                        const uint32_t *__restrict__ sbits,
                                                        int wpc, int64_t min_expect, int resolved,
                                                        int *__restrict__ err) {
-    __shared__ float acc[WMAX + 64];  // + one dummy slot per lane for unused batch entries
+    // + one dummy slot per lane for unused batch entries
+    __shared__ __attribute__((aligned(16))) float acc[WMAX + 64];
     __shared__ uint2 sw[WMAX / 32];   // structure words and their first output slot
     __shared__ uint32_t st_s[WG];
     __shared__ int st_e[WG + 1];
@@ -800,8 +804,11 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
             return;
         }
         if (expect > min_expect) {  // smaller chunks belong to k_num_chunk_rank
-            if (!cleared) {
-                for (int q = threadIdx.x; q < WMAX + 64; q += WG) acc[q] = 0.f;
+            if (!cleared) {  // 16-byte stores
+                static_assert((WMAX + 64) % 4 == 0, "accumulator size");
+                float4 *acc4 = reinterpret_cast<float4 *>(acc);
+                for (int q = threadIdx.x; q < (WMAX + 64) / 4; q += WG)
+                    acc4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                 cleared = true;
             }
             const int64_t out0 = d.out0 + (in.pos - in.pos0);
@@ -858,7 +865,7 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
 #pragma unroll
                 for (int u = 0; u < kEmitU; ++u) {
                     const int col = c0 + u * WG;
-                    if (col < ncol) acc[col] = 0.f;
+                    if (more && col < ncol) acc[col] = 0.f;  // for the workgroup's next item
                     const uint32_t bit = 1u << (col & 31);
                     if (e[u].x & bit) {
                         const int r = (int)e[u].y + __popc(e[u].x & (bit - 1u));
@@ -885,9 +892,82 @@ __global__ __launch_bounds__(WG) void k_num_chunk_pipe(const ProdDev *__restrict
 // a compact array of CAP floats rather than one slot per column, a chunk
 // needs a few KB of LDS and many chunks are resident per compute unit.  The
 // values leave as one contiguous (coalesced) copy, already in column order;
-// the columns are written from the bitmap.
-template <int WMAX, int CAP, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
+// the columns are written from the bitmap.  A lane loads its structure
+// words into registers first, so the rank table is written in one LDS pass.
+// A wave may take IPW consecutive items (mostly chunks of one row), loading
+// the next item's inputs while it works on the current one; the registers
+// that costs lower the occupancy, and one item per wave measured fastest.
+
+// What a lane holds of one item before it is processed.
+template <int KMAX>
+struct RankIn {
+    ChunkDesc d;
+    int64_t expect;  // the item's output count (0: nothing to do here)
+    uint32_t x0, x1;
+    float a;
+    uint32_t wv[KMAX];  // structure words lane*K .. lane*K + K - 1
+};
+
+template <int WMAX, int CAP>
+__device__ __forceinline__ RankIn<WMAX / 2048> rank_load(const ProdDev *prods, uint64_t w,
+                                                         const uint32_t *sabs,
+                                                         const int64_t *chunk_cnt,
+                                                         const uint32_t *sbits, int wpc,
+                                                         int resolved) {
+    constexpr int KMAX = WMAX / 2048;
+    const int lane = threadIdx.x & 63;
+    RankIn<KMAX> in;
+    in.d = desc_unpack(w);
+    const ChunkDesc &d = in.d;
+    const int64_t slot = d.slot0 + d.q;
+    in.expect =
+        resolved ? (int64_t)d.pad : (int64_t)readlane64((uint64_t)gld(chunk_cnt + slot), 0);
+    in.x0 = in.x1 = 0u;
+    in.a = 0.f;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) in.wv[k] = 0u;
+    if (in.expect == 0 || in.expect > CAP) {
+        in.expect = 0;  // empty, or a dense chunk (k_num_chunk_pipe)
+        return in;
+    }
+    const ProdDev &P = prods[d.prod];
+    if (lane < d.alen) {
+        const uint32_t *sc = sabs + d.sb + (int64_t)d.q * d.alen;
+        in.x0 = gld(sc + lane);
+        in.x1 = gld(sc + (int64_t)d.span * d.alen + lane);
+        in.a = gld(P.valA + d.a0 + lane);
+    }
+    const int lo = d.q * P.W;
+    const int64_t end = (int64_t)lo + (int64_t)d.span * P.W;
+    const int hi = (int)(end < P.n ? end : P.n);
+    const int nwords = hi > lo ? (hi - lo + 31) >> 5 : 0;
+    const int K = (nwords + 63) >> 6;
+    const uint32_t *bits = sbits + slot * (int64_t)wpc;
+    if (K <= KMAX) {
+        if ((K & 3) == 0 && nwords == K * 64 && (wpc & 3) == 0) {  // 16-byte loads
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int k = 0; k < KMAX; k += 4)
+                if (k < K) {
+                    const u32x4 w4 = gld((const u32x4 *)(bits + lane * K + k));
+                    in.wv[k] = w4.x;
+                    in.wv[k + 1] = w4.y;
+                    in.wv[k + 2] = w4.z;
+                    in.wv[k + 3] = w4.w;
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int x = lane * K + k;
+                if (k < K && x < nwords) in.wv[k] = gld(bits + x);
+            }
+        }
+    }
+    return in;
+}
+
+template <int WMAX, int CAP, int IPW>
+__global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
                                                        const ChunkDesc *__restrict__ desc,
                                                        int64_t nitems,
                                                        const uint32_t *__restrict__ sabs,
@@ -897,127 +977,115 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
                                                        int wpc, int resolved,
                                                        int *__restrict__ err) {
     constexpr int NWD = WMAX / 32;  // structure words of the widest item
+    constexpr int KMAX = NWD / 64;  // of them per lane
     static_assert(NWD >= 64 && NWD % 64 == 0, "chunk width");
-    // each wave of the workgroup takes its own chunk, with its own LDS slices
-    __shared__ uint2 sw_all[WAVES][NWD];        // {word, outputs before the word}
-    __shared__ float cacc_all[WAVES][CAP + 64];  // + one dummy slot per lane for unused entries
-    __shared__ uint32_t st_s_all[WAVES][64];
-    __shared__ int st_e_all[WAVES][65];
-    __shared__ float st_a_all[WAVES][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t item = (int64_t)blockIdx.x * WAVES + wave;
-    if (item >= nitems) return;  // wave-uniform; the waves never meet at a barrier
-    uint2 *sw = sw_all[wave];
-    float *cacc = cacc_all[wave];
-    uint32_t *st_s = st_s_all[wave];
-    int *st_e = st_e_all[wave];
-    float *st_a = st_a_all[wave];
-    const ChunkDesc d = desc_unpack(desc_word(desc, item));
-    const int c = d.q;
-    const int64_t slot = d.slot0 + c;
-    const int64_t expect =
-        resolved ? (int64_t)d.pad : (int64_t)readlane64((uint64_t)gld(chunk_cnt + slot), 0);
-    if (expect == 0 || expect > CAP) return;  // empty, or a dense chunk (k_num_chunk_pipe)
-    const ProdDev &P = prods[d.prod];
-    ItemIn in;
-    in.x0 = in.x1 = 0u;
-    in.a = 0.f;
-    if (lane < d.alen) {
-        const uint32_t *sc = sabs + d.sb + (int64_t)c * d.alen;
-        in.x0 = gld(sc + lane);
-        in.x1 = gld(sc + (int64_t)d.span * d.alen + lane);
-        in.a = gld(P.valA + d.a0 + lane);
-    }
-    const int64_t out0 =
-        resolved ? d.out0 : d.out0 + (gld(chunk_pos + slot) - gld(chunk_pos + d.slot0));
-    const int lo = c * P.W;
-    const int64_t end = (int64_t)lo + (int64_t)d.span * P.W;
-    const int hi = (int)(end < P.n ? end : P.n);
-    const int nwords = (hi - lo + 31) >> 5;
-    if (hi - lo > WMAX) {  // the plan picks WMAX >= the widest item; never taken
-        if (lane == 0) atomicOr(err, kErrRow);
-        return;
-    }
-    // structure: lane l takes words l*K .. l*K + K - 1 (K = nwords / 64
-    // rounded up); sw[x] = {word x, outputs before word x}
-    const uint32_t *bits = sbits + slot * (int64_t)wpc;
-    const int K = (nwords + 63) >> 6;
-    int cnt = 0;
-    if ((K & 3) == 0 && nwords == K * 64 && (wpc & 3) == 0) {  // 16-byte loads
-        for (int k = 0; k < K; k += 4) {
-            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-            const u32x4 w4 = gld((const u32x4 *)(bits + lane * K + k));
-            uint2 *o = sw + lane * K + k;
-            o[0].x = w4.x;
-            o[1].x = w4.y;
-            o[2].x = w4.z;
-            o[3].x = w4.w;
-            cnt += __popc(w4.x) + __popc(w4.y) + __popc(w4.z) + __popc(w4.w);
-        }
-    } else {
-        for (int k = 0; k < K; ++k) {
-            const int x = lane * K + k;
-            const uint32_t w = x < nwords ? gld(bits + x) : 0u;
-            sw[x].x = w;
-            cnt += __popc(w);
-        }
-    }
-    int total;
-    int pre = wg_excl_scan<64, int>(cnt, nullptr, total);
-    for (int k = 0; k < K; ++k) {
-        uint2 &e = sw[lane * K + k];
-        e.y = (uint32_t)pre;
-        pre += __popc(e.x);
-    }
-    for (int r = lane; r < expect; r += 64) cacc[r] = 0.f;
-    cacc[CAP + lane] = 0.f;
-    if (lane == 0 && total != expect) atomicOr(err, kErrChunk);
-    wave_lds_sync();
-    const int dummy = CAP + lane;
+    __shared__ uint2 sw[NWD];         // {word, outputs before the word}
+    __shared__ float cacc[CAP + 64];  // + one dummy slot per lane for unused entries
+    __shared__ uint32_t st_s[64];
+    __shared__ int st_e[65];
+    __shared__ float st_a[64];
+    const int lane = threadIdx.x & 63;
+    const int64_t first = (int64_t)blockIdx.x * IPW;
+    if (first >= nitems) return;
+    const int64_t last = first + IPW < nitems ? first + IPW : nitems;
+    RankIn<KMAX> cur = rank_load<WMAX, CAP>(prods, desc_word(desc, first), sabs, chunk_cnt,
+                                            sbits, wpc, resolved);
+    uint64_t wnext = first + 1 < last ? desc_word(desc, first + 1) : 0ull;
     bool stray = false;
-    pipe_products<64, NVT, true, true>(
-        P, d, in, sabs, st_s, st_e, st_a, nullptr,
-        [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
-            int idx[NVT];
-            float add[NVT];
-#pragma unroll
-            for (int v = 0; v < NVT; ++v) {
-                const int rel = cc[v] - lo;
-                const uint2 e = sw[(ok[v] ? rel : 0) >> 5];
-                const uint32_t bit = 1u << (rel & 31);
-                const bool in_structure = (e.x & bit) != 0u;
-                stray |= ok[v] && !in_structure;
-                const bool take = ok[v] && in_structure;
-                idx[v] = take ? (int)e.y + __popc(e.x & (bit - 1u)) : dummy;
-                add[v] = take ? aa[v] * vv[v] : 0.f;
-            }
-            lds_fadd_many<NVT>(cacc, idx, add);
-        },
-        lane);
-    if (stray) atomicOr(err, kErrChunk);  // a product outside the symbolic structure
-    wave_lds_sync();
-    const int ex = (int)expect;
-    float *valC = P.valC + out0;
-    for (int r = lane; r < ex; r += 64) gst(valC + r, cacc[r]);
-    // the columns: every lane expands its words' set bits into the (now
-    // free) accumulator at their ranks, then one coalesced copy
-    wave_lds_sync();
-    for (int k = 0; k < K; ++k) {
-        const int x = lane * K + k;
-        const uint2 e = sw[x];
-        uint32_t w = e.x;
-        int r = (int)e.y;
-        const int base = lo + (x << 5);
-        while (w) {
-            const int b = __builtin_ctz(w);
-            w &= w - 1u;
-            if (r < ex) cacc[r] = __int_as_float(base + b);
-            ++r;
+    for (int64_t item = first; item < last; ++item) {
+        const bool more = IPW > 1 && item + 1 < last;
+        RankIn<KMAX> nxt;
+        if (IPW > 1 && more) {  // the next item's inputs, loaded while this one is processed
+            nxt = rank_load<WMAX, CAP>(prods, wnext, sabs, chunk_cnt, sbits, wpc, resolved);
+            wnext = item + 2 < last ? desc_word(desc, item + 2) : 0ull;
         }
+        const ChunkDesc &d = cur.d;
+        const int64_t expect = cur.expect;
+        if (expect > 0) {
+            const ProdDev &P = prods[d.prod];
+            const int c = d.q;
+            const int64_t slot = d.slot0 + c;
+            const int64_t out0 =
+                resolved ? d.out0 : d.out0 + (gld(chunk_pos + slot) - gld(chunk_pos + d.slot0));
+            const int lo = c * P.W;
+            const int64_t end = (int64_t)lo + (int64_t)d.span * P.W;
+            const int hi = (int)(end < P.n ? end : P.n);
+            const int nwords = (hi - lo + 31) >> 5;
+            if (hi - lo > WMAX) {  // the plan picks WMAX >= the widest item; never taken
+                if (lane == 0) atomicOr(err, kErrRow);
+                return;
+            }
+            // sw[x] = {word x, outputs before word x}; lane l holds words
+            // l*K .. l*K + K - 1
+            const int K = (nwords + 63) >> 6;
+            int cnt = 0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) cnt += __popc(cur.wv[k]);
+            int total;
+            int pre = wg_excl_scan<64, int>(cnt, nullptr, total);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < K) {
+                    sw[lane * K + k] = make_uint2(cur.wv[k], (uint32_t)pre);
+                    pre += __popc(cur.wv[k]);
+                }
+            for (int r = lane; r < expect; r += 64) cacc[r] = 0.f;
+            cacc[CAP + lane] = 0.f;
+            if (lane == 0 && total != expect) atomicOr(err, kErrChunk);
+            wave_lds_sync();
+            const int dummy = CAP + lane;
+            ItemIn in;
+            in.x0 = cur.x0;
+            in.x1 = cur.x1;
+            in.a = cur.a;
+            pipe_products<64, NVT, true, true>(
+                P, d, in, sabs, st_s, st_e, st_a, nullptr,
+                [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
+                    int idx[NVT];
+                    float add[NVT];
+#pragma unroll
+                    for (int v = 0; v < NVT; ++v) {
+                        const int rel = cc[v] - lo;
+                        const uint2 e = sw[(ok[v] ? rel : 0) >> 5];
+                        const uint32_t bit = 1u << (rel & 31);
+                        const bool in_structure = (e.x & bit) != 0u;
+                        stray |= ok[v] && !in_structure;
+                        const bool take = ok[v] && in_structure;
+                        idx[v] = take ? (int)e.y + __popc(e.x & (bit - 1u)) : dummy;
+                        add[v] = take ? aa[v] * vv[v] : 0.f;
+                    }
+                    lds_fadd_many<NVT>(cacc, idx, add);
+                },
+                lane);
+            wave_lds_sync();
+            const int ex = (int)expect;
+            float *valC = P.valC + out0;
+            for (int r = lane; r < ex; r += 64) gst(valC + r, cacc[r]);
+            // the columns: every lane expands its words' set bits into the
+            // (now free) accumulator at their ranks, then one coalesced copy
+            wave_lds_sync();
+            for (int k = 0; k < K; ++k) {
+                const int x = lane * K + k;
+                const uint2 e = sw[x];
+                uint32_t w = e.x;
+                int r = (int)e.y;
+                const int base = lo + (x << 5);
+                while (w) {
+                    const int b = __builtin_ctz(w);
+                    w &= w - 1u;
+                    if (r < ex) cacc[r] = __int_as_float(base + b);
+                    ++r;
+                }
+            }
+            wave_lds_sync();
+            int32_t *colC = P.colC + out0;
+            for (int r = lane; r < ex; r += 64) gst(colC + r, __float_as_int(cacc[r]));
+            wave_lds_sync();  // the accumulator and structure are reused by the next item
+        }
+        if (IPW == 1 || !more) break;
+        cur = nxt;
     }
-    wave_lds_sync();
-    int32_t *colC = P.colC + out0;
-    for (int r = lane; r < ex; r += 64) gst(colC + r, __float_as_int(cacc[r]));
+    if (stray) atomicOr(err, kErrChunk);  // a product outside the symbolic structure
 }
 
 // Workgroups of a pipelined launch: wgs_per_cu per compute unit (a multiple
@@ -1298,17 +1366,17 @@ static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const u
                             const uint32_t *sbits, int wpc, int rank_cap, bool resolved, int *err,
                             hipStream_t s) {
     const int res = resolved ? 1 : 0;
-    constexpr int WV = kRankWaves;
-    const dim3 grid((unsigned)((nitems + WV - 1) / WV));
+    constexpr int IPW = kRankItems;
+    const dim3 grid((unsigned)((nitems + IPW - 1) / IPW));
     if (rank_cap <= 512)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512, WV>), grid, dim3(64 * WV), 0, s, prods,
-                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512, IPW>), grid, dim3(64), 0, s, prods, desc,
+                           nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else if (rank_cap <= 1024)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024, WV>), grid, dim3(64 * WV), 0, s, prods,
-                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024, IPW>), grid, dim3(64), 0, s, prods, desc,
+                           nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048, WV>), grid, dim3(64 * WV), 0, s, prods,
-                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048, IPW>), grid, dim3(64), 0, s, prods, desc,
+                           nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
 }
 
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
