@@ -79,7 +79,10 @@ struct spgemm_plan {
     int64_t *dflag = nullptr, *dfpos = nullptr;
     int64_t n_dense = -1;  // -1: not split
     int64_t n_items = 0;   // numeric items (exact)
-    int64_t n_merged = 0;  // of which merged (the last ones of the split list)
+    // the split list: dense | large single | small single | large merged |
+    // small merged (small: at most half the rank cap outputs)
+    int64_t n_s1 = 0, n_s0 = 0, n_m1 = 0, n_m0 = 0;
+    int64_t *dflag2 = nullptr, *dfpos2 = nullptr;
     int wmax = 0;       // widest chunk over the products
     bool fast = true;   // every B sorted with < 2^30 entries (32-bit chunk indexing)
 
@@ -595,7 +598,7 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     if (p->nd != p->num_start[kGroups] - p->num_start[kGroups - 1]) return SPGEMM_EINTERNAL;
     if (p->d_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
     p->n_items = p->d_items / p->opt.chunks_per_item;
-    p->n_merged = 0;
+    p->n_s1 = p->n_s0 = p->n_m1 = p->n_m0 = 0;
     if (p->nd > 0) {
         const uint64_t *ditems = p->map_num + p->num_start[kGroups - 1];
         // with merging an upper bound; the exact count is dbase[nd]
@@ -618,28 +621,35 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
         ST_TRY(launch_check());
         p->n_dense = -1;
         if (num_chunk_rank_used(p->fast, p->opt.chunks_per_item, p->opt.num_rank_cap)) {
-            // dense chunks first, then single and merged rank-accumulated
-            // items, so that each kernel is launched over its own items only
+            // dense chunks first, then the rank-accumulated items by kind and
+            // size, so that each launch covers its own items only
             ST_TRY(dalloc(p, &p->ndesc_split, nitems));
             ST_TRY(dalloc(p, &p->dflag, nitems));
             ST_TRY(dalloc(p, &p->dfpos, nitems + 1));
+            ST_TRY(dalloc(p, &p->dflag2, nitems));
+            ST_TRY(dalloc(p, &p->dfpos2, nitems + 1));
             launch_desc_flag(p->ndesc, nitems, p->chunk_cnt, p->opt.num_rank_cap, nlim, p->dflag,
-                             st);
+                             p->dflag2, st);
             ST_TRY(launch_check());
             ST_TRY(scan(p, p->dflag, p->dfpos, nitems));
-            launch_desc_split(p->ndesc, nitems, p->dflag, p->dfpos, p->chunk_cnt, p->chunk_pos,
-                              nlim, p->ndesc_split, st);
+            ST_TRY(scan(p, p->dflag2, p->dfpos2, nitems));
+            launch_desc_split(p->ndesc, nitems, p->dflag, p->dfpos, p->dflag2, p->dfpos2,
+                              p->chunk_cnt, p->chunk_pos, nlim, p->ndesc_split, st);
             ST_TRY(launch_check());
             HIP_TRY(hipMemcpyAsync(p->hread, p->dfpos + nitems, sizeof(int64_t),
                                    hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipMemcpyAsync(p->hread + 1, p->dbase + p->nd, sizeof(int64_t),
+            HIP_TRY(hipMemcpyAsync(p->hread + 1, p->dfpos2 + nitems, sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(p->hread + 2, p->dbase + p->nd, sizeof(int64_t),
                                    hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             p->n_dense = p->hread[0] & 0xffffffffll;
-            p->n_merged = p->hread[0] >> 32;
-            p->n_items = p->hread[1];
-            if (p->n_items < 0 || p->n_items > nitems || p->n_dense + p->n_merged > p->n_items)
-                return SPGEMM_EINTERNAL;
+            p->n_s0 = p->hread[0] >> 32;
+            p->n_m1 = p->hread[1] & 0xffffffffll;
+            p->n_m0 = p->hread[1] >> 32;
+            p->n_items = p->hread[2];
+            p->n_s1 = p->n_items - p->n_dense - p->n_s0 - p->n_m1 - p->n_m0;
+            if (p->n_items < 0 || p->n_items > nitems || p->n_s1 < 0) return SPGEMM_EINTERNAL;
         }
     }
     p->state = 2;
@@ -678,18 +688,30 @@ spgemm_status numeric_impl(spgemm_plan *p) {
                              rank ? p->opt.num_rank_cap : 0, split, p->flags, st);
         }
         if (rank) {
-            // single chunks, then merged items (their own launch: wider structure)
+            // large and small single chunks, then large and small merged items
+            // (merged items have a wider structure; small items a half-size
+            // accumulator)
             TimeScope ts(p, "num.g7r");
-            const ChunkDesc *rdesc = split ? p->ndesc_split + p->n_dense : p->ndesc;
-            const int64_t nm = split ? p->n_merged : 0;
-            const int64_t nr = (split ? p->n_items - p->n_dense : p->d_items) - nm;
-            launch_num_chunk_rank(p->wmax, p->dprods, rdesc, p->sabs, nr, p->chunk_cnt,
-                                  p->chunk_pos, p->sbits, p->wpc, p->opt.num_rank_cap, split,
-                                  p->flags, st);
-            if (nm > 0)
-                launch_num_chunk_rank(p->wmax_item, p->dprods, rdesc + nr, p->sabs, nm,
-                                      p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc,
-                                      p->opt.num_rank_cap, split, p->flags, st);
+            const int cap = p->opt.num_rank_cap;
+            if (!split) {
+                launch_num_chunk_rank(p->wmax, p->dprods, p->ndesc, p->sabs, p->d_items,
+                                      p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc, cap, false,
+                                      p->flags, st);
+            } else {
+                const ChunkDesc *r = p->ndesc_split + p->n_dense;
+                const struct { int64_t n; int w, cap; } parts[4] = {
+                    {p->n_s1, p->wmax, cap},
+                    {p->n_s0, p->wmax, cap / 2},
+                    {p->n_m1, p->wmax_item, cap},
+                    {p->n_m0, p->wmax_item, cap / 2}};
+                for (const auto &q : parts) {
+                    if (q.n > 0)
+                        launch_num_chunk_rank(q.w, p->dprods, r, p->sabs, q.n, p->chunk_cnt,
+                                              p->chunk_pos, p->sbits, p->wpc, q.cap, true,
+                                              p->flags, st);
+                    r += q.n;
+                }
+            }
         }
     }
     return launch_check();

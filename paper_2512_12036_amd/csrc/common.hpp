@@ -182,14 +182,17 @@ void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
                       const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,
                       int threads, int rank_cap, bool resolved, int *err, hipStream_t s);
-// Numeric chunk items split by output count and span: more than cap outputs
-// first, then single chunks, then merged items.  flag/fpos entries pack the
-// dense count (low 32 bits) and the merged count (high 32 bits).
+// Numeric chunk items split by output count and span into five lists: more
+// than cap outputs, single chunks above and at most cap / 2, merged items
+// above and at most cap / 2.  fa/fb (and their scans) pack two counters each:
+// fa = dense (low 32 bits) | small single (high), fb = large merged | small
+// merged.
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
-                      int64_t cap, const int64_t *nlim, int64_t *flag, hipStream_t s);
-void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
-                       const int64_t *fpos, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                       const int64_t *nlim, ChunkDesc *out, hipStream_t s);
+                      int64_t cap, const int64_t *nlim, int64_t *fa, int64_t *fb, hipStream_t s);
+void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *fa,
+                       const int64_t *fapos, const int64_t *fb, const int64_t *fbpos,
+                       const int64_t *chunk_cnt, const int64_t *chunk_pos, const int64_t *nlim,
+                       ChunkDesc *out, hipStream_t s);
 // Chunks with at most rank_cap outputs (fast path, one chunk per item only).
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap);
 void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,

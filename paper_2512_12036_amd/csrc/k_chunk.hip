@@ -1105,31 +1105,41 @@ static unsigned pipe_grid(int wgs_per_cu, int64_t nitems) {
     return (unsigned)g;
 }
 
-// Splits the numeric chunk items (one chunk per item) into three parts,
+// Splits the numeric chunk items (one chunk per item) into five parts,
 // keeping the order within each: items with more than `cap` outputs (dense),
-// then single chunks with at most cap outputs, then merged items (which
-// never have more than cap).  The flag packs two counters, dense in the low
-// 32 bits and merged in the high 32 bits, so one exclusive scan of the flags
-// gives each item its position.  The launches cover an upper bound of the
-// item count; nlim (if set) points at the exact count.
+// single chunks with more than cap / 2 outputs, single chunks with at most
+// cap / 2, merged items with more than cap / 2, merged items with at most
+// cap / 2 (a merged item never has more than cap).  The halves get their own
+// launches with a half-size accumulator, so more of them fit in a compute
+// unit's LDS.  Two flag words per item each pack two counters (low and high
+// 32 bits): fa = dense | small single, fb = large merged | small merged; an
+// exclusive scan of each gives every item its position.  The launches cover
+// an upper bound of the item count; nlim (if set) points at the exact count.
 __global__ void k_desc_flag(const ChunkDesc *__restrict__ desc, int64_t nitems,
                             const int64_t *__restrict__ chunk_cnt, int64_t cap,
-                            const int64_t *__restrict__ nlim, int64_t *__restrict__ flag) {
+                            const int64_t *__restrict__ nlim, int64_t *__restrict__ fa,
+                            int64_t *__restrict__ fb) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
-    if (nlim && it >= *nlim) {
-        flag[it] = 0;
-        return;
+    int64_t a = 0, b = 0;
+    if (!(nlim && it >= *nlim)) {
+        const ChunkDesc d = desc[it];
+        const int64_t cnt = chunk_cnt[d.slot0 + d.q];
+        const bool small = cnt <= cap / 2;
+        if (cnt > cap) a = 1;
+        else if (d.span > 1) b = small ? (int64_t(1) << 32) : 1;
+        else if (small) a = int64_t(1) << 32;
     }
-    const ChunkDesc d = desc[it];
-    flag[it] = chunk_cnt[d.slot0 + d.q] > cap ? 1 : (d.span > 1 ? (int64_t(1) << 32) : 0);
+    fa[it] = a;
+    fb[it] = b;
 }
 
 // The split descriptors are resolved: out0 is the item's own first output
 // slot in C_p and pad its output count, so the numeric kernels need no
 // further look-ups of the chunk counts and offsets.
 __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
-                             const int64_t *__restrict__ flag, const int64_t *__restrict__ fpos,
+                             const int64_t *__restrict__ fa, const int64_t *__restrict__ fapos,
+                             const int64_t *__restrict__ fb, const int64_t *__restrict__ fbpos,
                              const int64_t *__restrict__ chunk_cnt,
                              const int64_t *__restrict__ chunk_pos,
                              const int64_t *__restrict__ nlim, ChunkDesc *__restrict__ out) {
@@ -1137,13 +1147,18 @@ __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
     if (it >= nitems) return;
     const int64_t n = nlim ? *nlim : nitems;
     if (it >= n) return;
-    const int64_t tot = fpos[nitems];
-    const int64_t ndense = tot & 0xffffffffll, nmerged = tot >> 32;
-    const int64_t f = fpos[it];
-    const int64_t fd = f & 0xffffffffll, fm = f >> 32;
-    const int64_t fl = flag[it];
-    const int64_t pos = (fl & 0xffffffffll) ? fd : (fl >> 32) ? n - nmerged + fm
-                                                              : ndense + (it - fd - fm);
+    constexpr int64_t LO = 0xffffffffll;
+    const int64_t ta = fapos[nitems], tb = fbpos[nitems];
+    const int64_t n_dense = ta & LO, n_s0 = ta >> 32, n_m1 = tb & LO, n_m0 = tb >> 32;
+    const int64_t n_s1 = n - n_dense - n_s0 - n_m1 - n_m0;
+    const int64_t pa = fapos[it], pb = fbpos[it];
+    const int64_t a = fa[it], b = fb[it];
+    int64_t pos;
+    if (a & LO) pos = pa & LO;                                          // dense
+    else if (a >> 32) pos = n_dense + n_s1 + (pa >> 32);                // small single
+    else if (b & LO) pos = n_dense + n_s1 + n_s0 + (pb & LO);           // large merged
+    else if (b >> 32) pos = n_dense + n_s1 + n_s0 + n_m1 + (pb >> 32);  // small merged
+    else pos = n_dense + (it - (pa & LO) - (pa >> 32) - (pb & LO) - (pb >> 32));  // large single
     ChunkDesc d = desc[it];
     const int64_t slot = d.slot0 + d.q;
     d.out0 += chunk_pos[slot] - chunk_pos[d.slot0];
@@ -1152,18 +1167,19 @@ __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
 }
 
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
-                      int64_t cap, const int64_t *nlim, int64_t *flag, hipStream_t s) {
+                      int64_t cap, const int64_t *nlim, int64_t *fa, int64_t *fb, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_desc_flag, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, desc,
-                       nitems, chunk_cnt, cap, nlim, flag);
+                       nitems, chunk_cnt, cap, nlim, fa, fb);
 }
 
-void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *flag,
-                       const int64_t *fpos, const int64_t *chunk_cnt, const int64_t *chunk_pos,
-                       const int64_t *nlim, ChunkDesc *out, hipStream_t s) {
+void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *fa,
+                       const int64_t *fapos, const int64_t *fb, const int64_t *fbpos,
+                       const int64_t *chunk_cnt, const int64_t *chunk_pos, const int64_t *nlim,
+                       ChunkDesc *out, hipStream_t s) {
     if (nitems <= 0) return;
     hipLaunchKernelGGL(k_desc_split, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s,
-                       desc, nitems, flag, fpos, chunk_cnt, chunk_pos, nlim, out);
+                       desc, nitems, fa, fapos, fb, fbpos, chunk_cnt, chunk_pos, nlim, out);
 }
 
 void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int W, int nch,
@@ -1368,7 +1384,10 @@ static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const u
     const int res = resolved ? 1 : 0;
     constexpr int IPW = kRankItems;
     const dim3 grid((unsigned)((nitems + IPW - 1) / IPW));
-    if (rank_cap <= 512)
+    if (rank_cap <= 256)
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 256, IPW>), grid, dim3(64), 0, s, prods, desc,
+                           nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+    else if (rank_cap <= 512)
         hipLaunchKernelGGL((k_num_chunk_rank<RW, 512, IPW>), grid, dim3(64), 0, s, prods, desc,
                            nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else if (rank_cap <= 1024)
