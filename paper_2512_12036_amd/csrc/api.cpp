@@ -734,7 +734,7 @@ void spgemm_default_options(spgemm_options *opt) {
     opt->chunk_cols = 8192;
     opt->validate = 0;
     opt->chunks_per_item = 1;
-    opt->num_rank_cap = 1024;
+    opt->num_rank_cap = 2048;
 }
 
 spgemm_status spgemm_plan_create(spgemm_plan **out, const spgemm_csr *A, const spgemm_csr *B,
