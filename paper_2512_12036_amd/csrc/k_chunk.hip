@@ -470,6 +470,10 @@ constexpr int kEmitU = 8;     // columns per thread per round of the dense emiss
 #define SPG_RANK_ITEMS 1
 #endif
 constexpr int kRankItems = SPG_RANK_ITEMS;  // consecutive items per wave of the rank kernel
+#ifndef SPG_RANK_WAVES
+#define SPG_RANK_WAVES 1
+#endif
+constexpr int kRankWaves = SPG_RANK_WAVES;  // independent waves (items) per workgroup
 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
@@ -966,8 +970,8 @@ __device__ __forceinline__ RankIn<WMAX / 2048> rank_load(const ProdDev *prods, u
     return in;
 }
 
-template <int WMAX, int CAP, int IPW>
-__global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
+template <int WMAX, int CAP, int IPW, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
                                                        const ChunkDesc *__restrict__ desc,
                                                        int64_t nitems,
                                                        const uint32_t *__restrict__ sabs,
@@ -979,14 +983,21 @@ __global__ __launch_bounds__(64) void k_num_chunk_rank(const ProdDev *__restrict
     constexpr int NWD = WMAX / 32;  // structure words of the widest item
     constexpr int KMAX = NWD / 64;  // of them per lane
     static_assert(NWD >= 64 && NWD % 64 == 0, "chunk width");
-    __shared__ uint2 sw[NWD];         // {word, outputs before the word}
-    __shared__ float cacc[CAP + 64];  // + one dummy slot per lane for unused entries
-    __shared__ uint32_t st_s[64];
-    __shared__ int st_e[65];
-    __shared__ float st_a[64];
-    const int lane = threadIdx.x & 63;
-    const int64_t first = (int64_t)blockIdx.x * IPW;
-    if (first >= nitems) return;
+    // each wave of the workgroup takes its own items, with its own LDS
+    // slices; the waves never meet at a barrier
+    __shared__ uint2 sw_all[WAVES][NWD];         // {word, outputs before the word}
+    __shared__ float cacc_all[WAVES][CAP + 64];  // + one dummy slot per lane
+    __shared__ uint32_t st_s_all[WAVES][64];
+    __shared__ int st_e_all[WAVES][65];
+    __shared__ float st_a_all[WAVES][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint2 *sw = sw_all[wave];
+    float *cacc = cacc_all[wave];
+    uint32_t *st_s = st_s_all[wave];
+    int *st_e = st_e_all[wave];
+    float *st_a = st_a_all[wave];
+    const int64_t first = ((int64_t)blockIdx.x * WAVES + wave) * IPW;
+    if (first >= nitems) return;  // wave-uniform
     const int64_t last = first + IPW < nitems ? first + IPW : nitems;
     RankIn<KMAX> cur = rank_load<WMAX, CAP>(prods, desc_word(desc, first), sabs, chunk_cnt,
                                             sbits, wpc, resolved);
@@ -1382,20 +1393,21 @@ static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const u
                             const uint32_t *sbits, int wpc, int rank_cap, bool resolved, int *err,
                             hipStream_t s) {
     const int res = resolved ? 1 : 0;
-    constexpr int IPW = kRankItems;
-    const dim3 grid((unsigned)((nitems + IPW - 1) / IPW));
+    constexpr int IPW = kRankItems, WV = kRankWaves;
+    const int64_t per_wg = (int64_t)IPW * WV;
+    const dim3 grid((unsigned)((nitems + per_wg - 1) / per_wg)), block(64 * WV);
     if (rank_cap <= 256)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 256, IPW>), grid, dim3(64), 0, s, prods, desc,
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 256, IPW, WV>), grid, block, 0, s, prods, desc,
                            nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else if (rank_cap <= 512)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512, IPW>), grid, dim3(64), 0, s, prods, desc,
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 512, IPW, WV>), grid, block, 0, s, prods, desc,
                            nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else if (rank_cap <= 1024)
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024, IPW>), grid, dim3(64), 0, s, prods, desc,
-                           nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 1024, IPW, WV>), grid, block, 0, s, prods,
+                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
     else
-        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048, IPW>), grid, dim3(64), 0, s, prods, desc,
-                           nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+        hipLaunchKernelGGL((k_num_chunk_rank<RW, 2048, IPW, WV>), grid, block, 0, s, prods,
+                           desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
 }
 
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
