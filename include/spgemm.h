@@ -57,6 +57,9 @@ typedef enum {
     SPGEMM_EINTERNAL = 8   /* a kernel raised its error flag (probe limit,
                               symbolic / numeric count mismatch)               */
 } spgemm_status;
+/* With the environment variable SPGEMM_DEBUG set, a call that returns
+ * SPGEMM_EHIP first prints the failing HIP call and its error name to
+ * stderr. */
 
 /* spgemm_csr.flags: every row stores strictly ascending columns. */
 #define SPGEMM_ROWS_SORTED 1u
@@ -145,7 +148,15 @@ typedef struct {
      * spans at most 65536 columns, and rows of more than 64 chunks are not
      * merged. */
     int32_t chunk_merge;
-    int32_t reserved[1];
+    /* 1: the first spgemm_numeric (or spgemm_numeric_batch) call of the plan
+     * captures the phase's kernel launches into a HIP graph that the plan
+     * keeps, and every call, that one included, runs the phase as one launch
+     * of that graph on the plan's stream.  A value-only re-run then costs
+     * one descriptor upload and one graph launch, whatever the number of
+     * row groups.  The graph holds no memory set or copy node; the value and
+     * output pointers of each call reach the kernels through the uploaded
+     * descriptors.  Ignored (launches stay eager) when profile = 1.  0 = off. */
+    int32_t graph;
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;

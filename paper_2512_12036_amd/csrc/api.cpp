@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -100,16 +102,27 @@ struct spgemm_plan {
     std::vector<Timed> timed;
 
     int state = 0;  // 1 planned, 2 symbolic done
+    hipGraphExec_t num_graph = nullptr;  // the numeric launches, captured (opt.graph)
     std::vector<void *> allocs;
     size_t ws_bytes = 0;
 };
 
 namespace {
 
+// With SPGEMM_DEBUG set in the environment, every HIP failure that turns
+// into SPGEMM_EHIP is reported on stderr with the call and its error name.
+void report_hip(const char *what, hipError_t e, int line) {
+    static const bool on = std::getenv("SPGEMM_DEBUG") != nullptr;
+    if (on) std::fprintf(stderr, "spgemm: %s -> %s (api.cpp:%d)\n", what, hipGetErrorName(e), line);
+}
+
 #define HIP_TRY(expr)                                     \
     do {                                                  \
         hipError_t e__ = (expr);                          \
-        if (e__ != hipSuccess) return SPGEMM_EHIP;        \
+        if (e__ != hipSuccess) {                          \
+            report_hip(#expr, e__, __LINE__);             \
+            return SPGEMM_EHIP;                           \
+        }                                                 \
     } while (0)
 
 #define ST_TRY(expr)                                      \
@@ -118,9 +131,11 @@ namespace {
         if (s__ != SPGEMM_OK) return s__;                 \
     } while (0)
 
-spgemm_status launch_check() {
+spgemm_status launch_check(int line = __builtin_LINE()) {
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? SPGEMM_OK : SPGEMM_EHIP;
+    if (e == hipSuccess) return SPGEMM_OK;
+    report_hip("kernel launch", e, line);
+    return SPGEMM_EHIP;
 }
 
 // Event pair around a launch group when profiling is on.
@@ -226,6 +241,7 @@ spgemm_status check_options(const spgemm_options &o) {
     if (o.chunk_merge != 0 && o.chunk_merge != 1 && o.chunk_merge != 2 && o.chunk_merge != 4 &&
         o.chunk_merge != 8)
         return SPGEMM_EINVAL;
+    if (o.graph < 0 || o.graph > 1) return SPGEMM_EINVAL;
     return SPGEMM_OK;
 }
 
@@ -656,10 +672,11 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     return SPGEMM_OK;
 }
 
-spgemm_status numeric_impl(spgemm_plan *p) {
-    if (p->state != 2) return SPGEMM_ESTATE;
-    hipStream_t st = p->stream;
-    ST_TRY(upload_descriptors(p));
+// Enqueues every kernel of the numeric phase on `st`.  Each kernel reads the
+// value and output pointers from the device descriptors; every other argument
+// is fixed once the symbolic phase is done, so the same launches can be
+// captured once and replayed.
+spgemm_status numeric_launch(spgemm_plan *p, hipStream_t st) {
     static const char *const num_names[kGroups] = {"num.g0", "num.g1", "num.g2", "num.g3",
                                                    "num.g4", "num.g5", "num.g6", "num.g7"};
     for (int g = 1; g <= 4; ++g) {
@@ -715,6 +732,40 @@ spgemm_status numeric_impl(spgemm_plan *p) {
         }
     }
     return launch_check();
+}
+
+// Captures numeric_launch into p->num_graph, on a private stream (the
+// plan's stream may be the null stream, which cannot be captured).
+spgemm_status capture_numeric(spgemm_plan *p) {
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    spgemm_status s = SPGEMM_OK;
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) {
+        s = numeric_launch(p, cs);
+        e = hipStreamEndCapture(cs, &g);  // always ends the capture
+    }
+    if (s == SPGEMM_OK && e == hipSuccess)
+        e = hipGraphInstantiate(&p->num_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (s != SPGEMM_OK) return s;
+    if (e != hipSuccess) {
+        p->num_graph = nullptr;
+        (void)hipGetLastError();
+        return SPGEMM_EHIP;
+    }
+    return SPGEMM_OK;
+}
+
+spgemm_status numeric_impl(spgemm_plan *p) {
+    if (p->state != 2) return SPGEMM_ESTATE;
+    ST_TRY(upload_descriptors(p));
+    if (!p->opt.graph || p->opt.profile) return numeric_launch(p, p->stream);
+    if (!p->num_graph) ST_TRY(capture_numeric(p));
+    HIP_TRY(hipGraphLaunch(p->num_graph, p->stream));
+    return SPGEMM_OK;
 }
 
 }  // namespace
@@ -856,6 +907,7 @@ spgemm_status spgemm_export(const spgemm_plan *p, int32_t what, void *dst, int64
 void spgemm_free(spgemm_plan *p) {
     if (!p) return;
     (void)hipStreamSynchronize(p->stream);
+    if (p->num_graph) (void)hipGraphExecDestroy(p->num_graph);
     for (void *ptr : p->allocs) {
         if (p->ffn) p->ffn(p->actx, ptr, (void *)p->stream);
         else (void)hipFree(ptr);

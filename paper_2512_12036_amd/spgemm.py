@@ -34,7 +34,7 @@ class Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("chunks_per_item", ctypes.c_int32),
                 ("chunk_wgs_per_cu", ctypes.c_int32), ("chunk_threads", ctypes.c_int32),
                 ("sym_chunk_threads", ctypes.c_int32), ("num_rank_cap", ctypes.c_int32),
-                ("chunk_merge", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("chunk_merge", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -75,6 +75,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    # torch first: its HIP libraries ask for the runtime by its unversioned
+    # name, so a runtime that this library pulled in earlier (by its
+    # versioned name) would not be shared, and the second runtime of the
+    # process finds no device.  Loaded after torch, the library binds to the
+    # runtime torch already holds.
+    _torch()
     lib = ctypes.CDLL(path)
     pp = ctypes.POINTER(_VP)
     lib.spgemm_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -133,7 +139,7 @@ def default_options() -> Options:
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
                  profile=None, chunks_per_item=None, chunk_wgs_per_cu=None,
                  chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None,
-                 chunk_merge=None) -> Options:
+                 chunk_merge=None, graph=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -159,6 +165,8 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.num_rank_cap = int(num_rank_cap)
     if chunk_merge is not None:
         o.chunk_merge = int(chunk_merge)
+    if graph is not None:
+        o.graph = int(graph)
     return o
 
 

@@ -76,7 +76,8 @@ def _create(a, b, o):
                                          ("chunks_per_item", 3), ("chunk_wgs_per_cu", -1),
                                          ("chunk_wgs_per_cu", 65), ("chunk_threads", 96),
                                          ("sym_chunk_threads", 32), ("num_rank_cap", 300),
-                                         ("chunk_merge", 3), ("chunk_merge", 16)])
+                                         ("chunk_merge", 3), ("chunk_merge", 16),
+                                         ("graph", 2), ("graph", -1)])
 def test_bad_options_rejected(field, value):
     o = spgemm.default_options()
     setattr(o, field, value)
