@@ -31,9 +31,13 @@ __device__ __forceinline__ const T *uniform_ptr(const T *p) {
 // Element idx of a uniform base, addressed with a 32-bit byte offset
 // (requires idx * sizeof(T) < 2^32).
 template <typename T>
-__device__ __forceinline__ T gld_off(const T *base, uint32_t idx) {
-    const uint32_t byte = idx * (uint32_t)sizeof(T);
+__device__ __forceinline__ T gld_boff(const T *base, uint32_t byte) {
     return *(const __attribute__((address_space(1))) T *)((const char *)base + byte);
+}
+
+template <typename T>
+__device__ __forceinline__ T gld_off(const T *base, uint32_t idx) {
+    return gld_boff(base, idx * (uint32_t)sizeof(T));
 }
 
 // Largest o in [lo, hi) with e[o] <= q (e non-decreasing, e[lo] <= q).
@@ -242,8 +246,12 @@ constexpr int kStripeGroups = SPG_STRIPE_GROUPS;
 // crossed), and short slices make long walks when the steps are wide.  The
 // owner of each group's first product comes from one binary search per
 // staged batch.  f receives VT products per lane at a time (arrays + valid
-// flags).
-template <int WG, int VT, bool VALUES, typename E, typename S, typename F>
+// flags).  CLAMP: a lane past its group's end reads the group's last product
+// again (a real one, at or after the lane's previous product), so the loads
+// need no branch, and f gets that product with its flag false; this pays
+// where most lanes are busy and costs redundant loads where items are
+// short.  Without CLAMP, an entry whose flag is false holds zeros.
+template <int WG, int VT, bool VALUES, typename E, typename S, bool CLAMP = true, typename F>
 __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, const float *st_a,
                                                  int nv, E total, const int32_t *colB,
                                                  const float *valB, F &&f,
@@ -266,11 +274,47 @@ __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, c
     const E sub = ((p1 - p0 + G - 1) / G + GL - 1) / GL * GL;  // per group, whole steps
     const E g0 = p0 + (E)g * sub;
     const E g1 = g0 + sub < p1 ? g0 + sub : p1;
+    // a group past the end of the wave's range has nothing to do (f holds no
+    // wave-wide operation, so its lanes may leave)
+    if (CLAMP && G > 1 && g0 >= g1) return;
     int o = G == 1 ? __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, p0))
                    : lds_owner<E>(st_e, 0, nv, g0 < total ? g0 : total - 1);
     E e0 = st_e[o], e1 = st_e[o + 1];
     S base = st_s[o];
     float a = VALUES ? st_a[o] : 0.f;
+    if constexpr (CLAMP && kOff32) {
+        // Byte units (4 q, 4 e1, 4 (base - e0)), so that a product's address
+        // is one add; B offsets are below 2^32 bytes here, and products of a
+        // batch far fewer.
+        uint32_t e1b = (uint32_t)e1 * 4u;
+        uint32_t bob = ((uint32_t)base - (uint32_t)e0) * 4u;
+        const uint32_t lastb = (uint32_t)(g1 - 1) * 4u;
+        for (E s = 0; s < sub; s += (E)VT * GL) {
+            int cc[VT];
+            float aa[VT], vv[VT];
+            bool ok[VT];
+            const uint32_t qs = (uint32_t)(g0 + s + k) * 4u;
+#pragma unroll
+            for (int v = 0; v < VT; ++v) {
+                const uint32_t qb = qs + (uint32_t)(v * GL * 4);
+                ok[v] = qb <= lastb;
+                const uint32_t qcb = qb < lastb ? qb : lastb;
+                while (qcb >= e1b) {
+                    ++o;
+                    bob = ((uint32_t)st_s[o] - (uint32_t)e1) * 4u;  // e1 is o's first product
+                    e1 = st_e[o + 1];
+                    e1b = (uint32_t)e1 * 4u;
+                    if (VALUES) a = st_a[o];
+                }
+                const uint32_t tb = bob + qcb;
+                cc[v] = gld_boff(ucol, tb);
+                vv[v] = VALUES ? gld_boff(uval, tb) : 0.f;
+                aa[v] = a;
+            }
+            f(cc, aa, vv, ok);
+        }
+        return;
+    }
     for (E s = 0; s < sub; s += (E)VT * GL) {
         int cc[VT];
         float aa[VT], vv[VT];
@@ -279,26 +323,46 @@ __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, c
         for (int v = 0; v < VT; ++v) {
             const E q = g0 + s + (E)(v * GL + k);
             ok[v] = q < g1;
-            cc[v] = 0;
-            aa[v] = 0.f;
-            vv[v] = 0.f;
-            if (ok[v]) {
-                while (q >= e1) {
+            if (CLAMP) {
+                const E qc = ok[v] ? q : g1 - 1;
+                while (qc >= e1) {
                     ++o;
                     e0 = e1;
                     e1 = st_e[o + 1];
                     base = st_s[o];
                     if (VALUES) a = st_a[o];
                 }
-                const S t = base + (S)(q - e0);
+                const S t = base + (S)(qc - e0);
                 if (kOff32) {
                     cc[v] = gld_off(ucol, (uint32_t)t);
-                    if (VALUES) vv[v] = gld_off(uval, (uint32_t)t);
+                    vv[v] = VALUES ? gld_off(uval, (uint32_t)t) : 0.f;
                 } else {
                     cc[v] = gld(colB + t);
-                    if (VALUES) vv[v] = gld(valB + t);
+                    vv[v] = VALUES ? gld(valB + t) : 0.f;
                 }
                 aa[v] = a;
+            } else {
+                cc[v] = 0;
+                aa[v] = 0.f;
+                vv[v] = 0.f;
+                if (ok[v]) {
+                    while (q >= e1) {
+                        ++o;
+                        e0 = e1;
+                        e1 = st_e[o + 1];
+                        base = st_s[o];
+                        if (VALUES) a = st_a[o];
+                    }
+                    const S t = base + (S)(q - e0);
+                    if (kOff32) {
+                        cc[v] = gld_off(ucol, (uint32_t)t);
+                        if (VALUES) vv[v] = gld_off(uval, (uint32_t)t);
+                    } else {
+                        cc[v] = gld(colB + t);
+                        if (VALUES) vv[v] = gld(valB + t);
+                    }
+                    aa[v] = a;
+                }
             }
         }
         f(cc, aa, vv, ok);

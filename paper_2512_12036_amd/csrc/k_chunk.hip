@@ -641,7 +641,7 @@ __device__ __forceinline__ ItemIn item_load(const ProdDev *prods, const ChunkDes
 // (the first round from the prefetched `in`) and hands every product to f.
 // WAVE: a single wave working on its own (tid = lane), ordering its LDS
 // traffic by itself instead of with workgroup barriers.
-template <int WG, int VT, bool VALUES, bool WAVE = false, typename F>
+template <int WG, int VT, bool VALUES, bool WAVE = false, bool CLAMP = true, typename F>
 __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc &d,
                                               const ItemIn &in, const uint32_t *sabs,
                                               uint32_t *st_s, int *st_e, float *st_a, int *wsum,
@@ -672,8 +672,8 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
         if (WAVE) wave_lds_sync(); else lds_sync();
         const int nv = alen - jb < WG ? alen - jb : WG;
         if (total > 0)
-            striped_products<WG, VT, VALUES, int, uint32_t>(st_s, st_e, st_a, nv, total, P.colB,
-                                                            P.valB, f, tid);
+            striped_products<WG, VT, VALUES, int, uint32_t, CLAMP>(st_s, st_e, st_a, nv, total,
+                                                                   P.colB, P.valB, f, tid);
         if (WAVE) wave_lds_sync(); else lds_sync();
     }
 }
@@ -1049,7 +1049,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             in.x0 = cur.x0;
             in.x1 = cur.x1;
             in.a = cur.a;
-            pipe_products<64, NVT, true, true>(
+            pipe_products<64, NVT, true, true, false>(
                 P, d, in, sabs, st_s, st_e, st_a, nullptr,
                 [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
                     int idx[NVT];
