@@ -103,3 +103,11 @@ def test_library_loaded_before_torch():
                        timeout=100)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "nnz" in r.stdout
+
+
+def test_graph_unsorted_b():
+    # rows of B stored out of order: the chunk kernels without sub-range
+    # tables, captured the same way
+    a = gen.rmat(12, 16, seed=73)
+    b = gen.shuffle_rows(a, 9)
+    _replays([a], [b], forced_options(7, chunk_cols=1024), "rmat12 unsorted B")
