@@ -1,6 +1,8 @@
 // Device-side helpers shared by the hash and chunk kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace spg {
@@ -66,16 +68,48 @@ __device__ __forceinline__ void lds_fadd(float *p, float v) {
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active).
+// 32-bit integers go through DPP: row shifts of 1, 2, 4 and 8 lanes give
+// each 16-lane row its own prefix, then the broadcasts of lane 15 (into rows
+// 1 and 3) and of lane 31 (into rows 2 and 3) add the earlier rows' totals.
+// That is six ALU steps with no LDS traffic, where a shuffle (ds_bpermute)
+// costs an LDS round trip per step.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    if constexpr (sizeof(T) == 4 && std::is_integral<T>::value) {
+        int v = (int)x;
+        v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+        v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+        v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+        v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+        v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+        v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+        return (T)v;
+    } else {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            T o = __shfl_up(x, off, 64);
+            if (lane >= off) x += o;
+        }
+        return x;
+    }
+}
+
+// Lane 63's value, in every lane (the wave total after wave_incl_scan).
+template <typename T>
+__device__ __forceinline__ T wave_last(T x) {
+    if constexpr (sizeof(T) == 4 && std::is_integral<T>::value)
+        return (T)__builtin_amdgcn_readlane((int)x, 63);
+    else
+        return __shfl(x, 63, 64);
+}
+
 template <int NT, typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T *wsum, T &total) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    T incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        T o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
+    const T incl = wave_incl_scan(v);
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
     T before = 0, tot = 0;
@@ -90,11 +124,23 @@ __device__ __forceinline__ T block_excl_scan(T v, T *wsum, T &total) {
     return before + incl - v;
 }
 
+// Sum over the 64 lanes of a wave, valid in lane 0 (in every lane for
+// 32-bit integers).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    if constexpr (sizeof(T) == 4 && std::is_integral<T>::value) {
+        return wave_last(wave_incl_scan(v));
+    } else {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        return v;
+    }
+}
+
 template <int NT, typename T>
 __device__ __forceinline__ T block_sum(T v, T *wsum) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    v = wave_sum(v);
     if (lane == 0) wsum[w] = v;
     __syncthreads();
     T tot = 0;
@@ -125,14 +171,9 @@ template <int NT, typename T>
 __device__ __forceinline__ T wg_excl_scan(T v, T *wsum, T &total) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    T incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        T o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
+    const T incl = wave_incl_scan(v);
     if (NW == 1) {
-        total = __shfl(incl, 63, 64);
+        total = wave_last(incl);
         return incl - v;
     }
     if (lane == 63) wsum[w] = incl;
@@ -153,9 +194,11 @@ template <int NT, typename T>
 __device__ __forceinline__ T wg_sum(T v, T *wsum) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (NW == 1) return __shfl(v, 0, 64);
+    v = wave_sum(v);
+    if constexpr (NW == 1) {
+        if constexpr (sizeof(T) == 4 && std::is_integral<T>::value) return v;
+        else return __shfl(v, 0, 64);
+    }
     if (lane == 0) wsum[w] = v;
     lds_sync();
     T tot = 0;

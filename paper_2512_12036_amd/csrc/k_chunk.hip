@@ -744,7 +744,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
                 bm[x] = 0u;
             }
         }
-        const int64_t tot = wg_sum<WG, int64_t>(cnt, wsum);
+        // an item's count is at most its width (< 2^31)
+        const int64_t tot = wg_sum<WG, int>((int)cnt, (int *)wsum);
         if (threadIdx.x == 0) {
             chunk_cnt[d.slot0 + c] = tot;
             if (tot) atomicAdd((unsigned long long *)&row_nnz[d.out0], (unsigned long long)tot);
