@@ -288,17 +288,18 @@ constexpr int kStripeGroups = SPG_STRIPE_GROUPS;
 // lane's previous owner (one LDS round trip per B-row slice boundary
 // crossed), and short slices make long walks when the steps are wide.  The
 // owner of each group's first product comes from one binary search per
-// staged batch.  f receives VT products per lane at a time (arrays + valid
-// flags).  CLAMP: a lane past its group's end reads the group's last product
-// again (a real one, at or after the lane's previous product), so the loads
-// need no branch, and f gets that product with its flag false; this pays
-// where most lanes are busy and costs redundant loads where items are
-// short.  Without CLAMP, an entry whose flag is false holds zeros.
+// staged batch (in a single-wave workgroup, a ballot over my_e, each lane's
+// own st_e entry).  f receives VT products per lane at a time (arrays +
+// valid flags).  CLAMP: a lane past its group's end reads the group's last
+// product again (a real one, at or after the lane's previous product), so
+// the loads need no branch, and f gets that product with its flag false;
+// this pays where most lanes are busy and costs redundant loads where items
+// are short.  Without CLAMP, an entry whose flag is false holds zeros.
 template <int WG, int VT, bool VALUES, typename E, typename S, bool CLAMP = true, typename F>
 __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, const float *st_a,
                                                  int nv, E total, const int32_t *colB,
                                                  const float *valB, F &&f,
-                                                 int tid = threadIdx.x) {
+                                                 int tid = threadIdx.x, E my_e = 0) {
     constexpr bool kOff32 = sizeof(S) == 4;
     constexpr int G = kStripeGroups;
     constexpr int GL = 64 / G;  // lanes per group
@@ -317,10 +318,25 @@ __device__ __forceinline__ void striped_products(const S *st_s, const E *st_e, c
     const E sub = ((p1 - p0 + G - 1) / G + GL - 1) / GL * GL;  // per group, whole steps
     const E g0 = p0 + (E)g * sub;
     const E g1 = g0 + sub < p1 ? g0 + sub : p1;
+    int o = 0;
+    if constexpr (NW == 1 && G > 1) {
+        // A single-wave workgroup: lane j holds st_e[j] in my_e (not
+        // decreasing over the lanes, lanes past nv at total), so the owner of
+        // each group's first product is a ballot count, without a search
+        // through LDS; taken before any lane leaves, so that every lane votes.
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            E qg = p0 + (E)gg * sub;
+            if (qg > total - 1) qg = total - 1;
+            const int og = __popcll(__ballot(my_e <= qg)) - 1;
+            if (g == gg) o = og;
+        }
+    }
     // a group past the end of the wave's range has nothing to do (f holds no
     // wave-wide operation, so its lanes may leave)
     if (CLAMP && G > 1 && g0 >= g1) return;
-    int o = G == 1 ? __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, p0))
+    if constexpr (!(NW == 1 && G > 1))
+        o = G == 1 ? __builtin_amdgcn_readfirstlane(lds_owner<E>(st_e, 0, nv, p0))
                    : lds_owner<E>(st_e, 0, nv, g0 < total ? g0 : total - 1);
     E e0 = st_e[o], e1 = st_e[o + 1];
     S base = st_s[o];

@@ -673,7 +673,7 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
         const int nv = alen - jb < WG ? alen - jb : WG;
         if (total > 0)
             striped_products<WG, VT, VALUES, int, uint32_t, CLAMP>(st_s, st_e, st_a, nv, total,
-                                                                   P.colB, P.valB, f, tid);
+                                                                   P.colB, P.valB, f, tid, excl);
         if (WAVE) wave_lds_sync(); else lds_sync();
     }
 }
