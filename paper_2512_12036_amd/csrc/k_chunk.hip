@@ -1035,6 +1035,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             for (int k = 0; k < KMAX; ++k) cnt += __popc(cur.wv[k]);
             int total;
             int pre = wg_excl_scan<64, int>(cnt, nullptr, total);
+            const int pre0 = pre;  // the rank of the lane's first output
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
                 if (k < K) {
@@ -1072,26 +1073,40 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             wave_lds_sync();
             const int ex = (int)expect;
             float *valC = P.valC + out0;
-            for (int r = lane; r < ex; r += 64) gst(valC + r, cacc[r]);
-            // the columns: every lane expands its words' set bits into the
-            // (now free) accumulator at their ranks, then one coalesced copy
-            wave_lds_sync();
-            for (int k = 0; k < K; ++k) {
-                const int x = lane * K + k;
-                const uint2 e = sw[x];
-                uint32_t w = e.x;
-                int r = (int)e.y;
-                const int base = lo + (x << 5);
-                while (w) {
-                    const int b = __builtin_ctz(w);
-                    w &= w - 1u;
-                    if (r < ex) cacc[r] = __int_as_float(base + b);
-                    ++r;
+            int32_t *colC = P.colC + out0;
+            // The columns: every lane expands the set bits of its structure
+            // words (still in registers) at their ranks, then coalesced
+            // copies.  They go into the rank table, which is no longer read,
+            // when it has room for the item's outputs (values and columns then
+            // leave together); else into the accumulator once the values have
+            // left.
+            constexpr bool kColsInTable = 2 * NWD >= CAP;
+            int *ccol = kColsInTable ? reinterpret_cast<int *>(sw) : reinterpret_cast<int *>(cacc);
+            if (!kColsInTable) {
+                for (int r = lane; r < ex; r += 64) gst(valC + r, cacc[r]);
+                wave_lds_sync();
+            }
+            {
+                int r = pre0;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    if (k < K) {
+                        uint32_t w = cur.wv[k];
+                        const int base = lo + ((lane * K + k) << 5);
+                        while (w) {
+                            const int b = __builtin_ctz(w);
+                            w &= w - 1u;
+                            if (r < ex) ccol[r] = base + b;
+                            ++r;
+                        }
+                    }
                 }
             }
             wave_lds_sync();
-            int32_t *colC = P.colC + out0;
-            for (int r = lane; r < ex; r += 64) gst(colC + r, __float_as_int(cacc[r]));
+            for (int r = lane; r < ex; r += 64) {
+                if (kColsInTable) gst(valC + r, cacc[r]);
+                gst(colC + r, ccol[r]);
+            }
             wave_lds_sync();  // the accumulator and structure are reused by the next item
         }
         if (IPW == 1 || !more) break;
