@@ -650,19 +650,9 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
     const int alen = d.alen;
     const uint32_t *sc = sabs + d.sb + (int64_t)d.q * alen;
     const int64_t send = (int64_t)d.span * alen;  // the item's end bound
+    uint32_t x0 = in.x0, x1 = in.x1;
+    float a = in.a;
     for (int jb = 0; jb < alen; jb += WG) {
-        const int j = jb + tid;
-        uint32_t x0 = in.x0, x1 = in.x1;
-        float a = in.a;
-        if (jb > 0) {
-            x0 = x1 = 0u;
-            a = 0.f;
-            if (j < alen) {
-                x0 = gld(sc + j);
-                x1 = gld(sc + send + j);
-                if (VALUES) a = gld(P.valA + d.a0 + j);
-            }
-        }
         int total;
         const int excl = wg_excl_scan<WG, int>((int)(x1 - x0), wsum, total);
         st_s[tid] = x0;
@@ -671,10 +661,22 @@ __device__ __forceinline__ void pipe_products(const ProdDev &P, const ChunkDesc 
         if (tid == 0) st_e[WG] = total;
         if (WAVE) wave_lds_sync(); else lds_sync();
         const int nv = alen - jb < WG ? alen - jb : WG;
+        // the next batch's bounds, loaded while this batch's products run
+        const int jn = jb + WG + tid;
+        uint32_t nx0 = 0u, nx1 = 0u;
+        float na = 0.f;
+        if (jn < alen) {
+            nx0 = gld(sc + jn);
+            nx1 = gld(sc + send + jn);
+            if (VALUES) na = gld(P.valA + d.a0 + jn);
+        }
         if (total > 0)
             striped_products<WG, VT, VALUES, int, uint32_t, CLAMP>(st_s, st_e, st_a, nv, total,
                                                                    P.colB, P.valB, f, tid, excl);
         if (WAVE) wave_lds_sync(); else lds_sync();
+        x0 = nx0;
+        x1 = nx1;
+        a = na;
     }
 }
 
