@@ -103,6 +103,7 @@ struct spgemm_plan {
 
     int state = 0;  // 1 planned, 2 symbolic done
     hipGraphExec_t num_graph = nullptr;  // the numeric launches, captured (opt.graph)
+    bool num_graph_empty = false;        // captured, with nothing to launch
     std::vector<void *> allocs;
     size_t ws_bytes = 0;
 };
@@ -746,12 +747,19 @@ spgemm_status capture_numeric(spgemm_plan *p) {
         s = numeric_launch(p, cs);
         e = hipStreamEndCapture(cs, &g);  // always ends the capture
     }
-    if (s == SPGEMM_OK && e == hipSuccess)
-        e = hipGraphInstantiate(&p->num_graph, g, nullptr, nullptr, 0);
+    size_t nodes = 0;
+    if (s == SPGEMM_OK && e == hipSuccess) e = hipGraphGetNodes(g, nullptr, &nodes);
+    if (s == SPGEMM_OK && e == hipSuccess) {
+        if (nodes == 0)
+            p->num_graph_empty = true;  // an empty product: nothing to replay
+        else
+            e = hipGraphInstantiate(&p->num_graph, g, nullptr, nullptr, 0);
+    }
     if (g) (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cs);
     if (s != SPGEMM_OK) return s;
     if (e != hipSuccess) {
+        report_hip("numeric graph capture", e, __LINE__);
         p->num_graph = nullptr;
         (void)hipGetLastError();
         return SPGEMM_EHIP;
@@ -763,8 +771,8 @@ spgemm_status numeric_impl(spgemm_plan *p) {
     if (p->state != 2) return SPGEMM_ESTATE;
     ST_TRY(upload_descriptors(p));
     if (!p->opt.graph || p->opt.profile) return numeric_launch(p, p->stream);
-    if (!p->num_graph) ST_TRY(capture_numeric(p));
-    HIP_TRY(hipGraphLaunch(p->num_graph, p->stream));
+    if (!p->num_graph && !p->num_graph_empty) ST_TRY(capture_numeric(p));
+    if (p->num_graph) HIP_TRY(hipGraphLaunch(p->num_graph, p->stream));
     return SPGEMM_OK;
 }
 

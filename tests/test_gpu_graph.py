@@ -111,3 +111,14 @@ def test_graph_unsorted_b():
     a = gen.rmat(12, 16, seed=73)
     b = gen.shuffle_rows(a, 9)
     _replays([a], [b], forced_options(7, chunk_cols=1024), "rmat12 unsorted B")
+
+
+def test_graph_degenerate_products():
+    # empty shapes and an all-zero A capture a graph with nothing to launch;
+    # every call must still succeed and give the (empty) product
+    for (m, k, n) in [(0, 5, 7), (5, 0, 7), (5, 7, 0), (1, 1, 1)]:
+        a = gen.random_csr(m, k, 0.5, 1)
+        b = gen.random_csr(k, n, 0.5, 2)
+        _replays([a], [b], spgemm.make_options(), f"degenerate {(m, k, n)}", reps=2)
+    z = gen.random_csr(100, 80, 0.0, 1)
+    _replays([z], [gen.random_csr(80, 90, 0.3, 2)], spgemm.make_options(), "zero A", reps=2)
