@@ -30,13 +30,15 @@ __device__ __forceinline__ const T *uniform_ptr(const T *p) {
     return (const T *)(((uint64_t)hi << 32) | lo);
 }
 
-// Element idx of a uniform base, addressed with a 32-bit byte offset
-// (requires idx * sizeof(T) < 2^32).
+// The value at a 32-bit byte offset from a uniform base (one global load
+// with a scalar base and a vector offset).
 template <typename T>
 __device__ __forceinline__ T gld_boff(const T *base, uint32_t byte) {
     return *(const __attribute__((address_space(1))) T *)((const char *)base + byte);
 }
 
+// Element idx of a uniform base, addressed the same way (requires
+// idx * sizeof(T) < 2^32).
 template <typename T>
 __device__ __forceinline__ T gld_off(const T *base, uint32_t idx) {
     return gld_boff(base, idx * (uint32_t)sizeof(T));
