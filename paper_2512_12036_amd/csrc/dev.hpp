@@ -98,6 +98,45 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
     }
 }
 
+// Inclusive prefix sum over aligned segments of G lanes (G = 8, 16, 32 or
+// 64; every lane of the segment active, other segments may be idle).  The
+// DPP steps only ever read lanes of the same segment: shifts inside a
+// 16-lane row, masked at segment starts when G < 16, then for G >= 32 the
+// broadcast of lane 15 into the next row and for G = 64 that of lane 31.
+template <int G>
+__device__ __forceinline__ int seg_incl_scan(int v) {
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "segment width");
+    const int l = (int)threadIdx.x & (G - 1);
+    int t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (G >= 16 || l >= 1) ? t : 0;
+    t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (G >= 16 || l >= 2) ? t : 0;
+    t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (G >= 16 || l >= 4) ? t : 0;
+    if constexpr (G >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    if constexpr (G >= 32) v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    if constexpr (G >= 64) v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+// The value of the last lane of each lane's G-lane segment (its total after
+// seg_incl_scan), by readlanes: those of other segments are read but unused.
+template <int G>
+__device__ __forceinline__ int seg_last(int v) {
+    if constexpr (G == 64) {
+        return __builtin_amdgcn_readlane(v, 63);
+    } else {
+        const int seg = ((int)threadIdx.x & 63) / G;
+        int r = 0;
+#pragma unroll
+        for (int s = 0; s < 64 / G; ++s) {
+            const int x = __builtin_amdgcn_readlane(v, s * G + G - 1);
+            if (seg == s) r = x;
+        }
+        return r;
+    }
+}
+
 // Lane 63's value, in every lane (the wave total after wave_incl_scan).
 template <typename T>
 __device__ __forceinline__ T wave_last(T x) {

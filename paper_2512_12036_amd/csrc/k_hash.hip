@@ -190,13 +190,8 @@ __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int 
             len = (int)(gld(P.rptB + k + 1) - s);
             if (VALUES) a = gld(P.valA + j);
         }
-        int incl = len;
-#pragma unroll
-        for (int off = 1; off < G; off <<= 1) {
-            int o = __shfl_up(incl, off, G);
-            if (lane >= off) incl += o;
-        }
-        const int total = __shfl(incl, G - 1, G);
+        const int incl = seg_incl_scan<G>(len);
+        const int total = seg_last<G>(incl);
         gs_s[lane] = s;
         gs_e[lane] = incl - len;
         if (VALUES) gs_a[lane] = a;
@@ -262,8 +257,7 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
                                                   : lds_insert_many<4>(tab, T - 1, LOG2T, cc,
                                                                        ok, err);
                                 });
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, G);
+    cnt = seg_last<G>(seg_incl_scan<G>(cnt));
     if (lane == 0) row_nnz[P.row_base + i] = cnt;
 }
 
@@ -317,13 +311,8 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
         vv[r] = tv[q];
         mine += kk[r] != kEmptyKey;
     }
-    int incl = mine;
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        int o = __shfl_up(incl, off, G);
-        if (lane >= off) incl += o;
-    }
-    const int n = __shfl(incl, G - 1, G);
+    const int incl = seg_incl_scan<G>(mine);
+    const int n = seg_last<G>(incl);
     int pos = incl - mine;
     __syncthreads();
     if (active && !direct) {
