@@ -838,7 +838,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // then thread t takes columns t, t + WG, ...: the output slot of a
             // set column is its word's slot plus the set bits below it, so
             // consecutive set columns go to consecutive slots (coalesced
-            // writes, already in column order), and every slot of the
+            // writes, already in column order), and every set slot of the
             // accumulator is cleared for the next chunk.  kEmitU columns per
             // thread are read from LDS together, so that one LDS round trip
             // serves all of them.
@@ -872,9 +872,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                 for (int u = 0; u < kEmitU; ++u) {
                     const int col = c0 + u * WG;
-                    if (more && col < ncol) acc[col] = 0.f;  // for the workgroup's next item
                     const uint32_t bit = 1u << (col & 31);
                     if (e[u].x & bit) {
+                        // for the workgroup's next item; the products only
+                        // ever touch the chunk's structure, so the other
+                        // slots are still zero
+                        if (more) acc[col] = 0.f;
                         const int r = (int)e[u].y + __popc(e[u].x & (bit - 1u));
                         if (r < ex) {
                             gst(colC + r, lo + col);
@@ -1053,7 +1056,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             in.x0 = cur.x0;
             in.x1 = cur.x1;
             in.a = cur.a;
-            pipe_products<64, NVT, true, true, false>(
+            // items of more than 1,024 outputs are long enough for branch-free
+            // (clamped) loads to pay; shorter ones keep masked loads
+            pipe_products<64, NVT, true, true, (CAP >= 2048)>(
                 P, d, in, sabs, st_s, st_e, st_a, nullptr,
                 [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
                     int idx[NVT];
