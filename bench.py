@@ -2,10 +2,14 @@
 
 A step is one pass of the whole path on one product: plan (intermediate
 products per row + row grouping), symbolic phase (+ row-pointer scan),
-allocation of C, numeric phase (+ gather and sort), plan release.  The
-workload is C = A*A with A an R-MAT graph of scale 18, edge factor 16,
-(a, b, c, d) = (0.57, 0.19, 0.19, 0.05), duplicates merged, FP32 values in
-(0, 1]; the inputs are resident in HBM before timing starts.
+allocation of C, numeric phase (+ gather and sort), kernel flag check, plan
+release.  The headline workload is C = A*A with A an R-MAT graph of scale 18,
+edge factor 16, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), duplicates merged,
+FP32 values in (0, 1]; the inputs are resident in HBM before timing starts.
+The other workloads are reported under "configs" (Erdos-Renyi 2k
+self-product, graph contraction, Markov clustering) and "served" (4,096
+GNN aggregation requests under continuous batching against plain
+per-request plans).
 
 Prints one JSON line.  Throughput is 2 * sum(intermediate products) / time
 (paper Section VI).  The roofline entry is for the dominant kernel, timed with
@@ -80,47 +84,191 @@ def rmat18():
     return gen.rmat(18, 16, seed=2)
 
 
-def group_units(plan, a, what):
-    """Per-group (rows, sum ip, sum nnz, sum alen) for the plan's row map."""
-    import torch
+def group_units(plan, rpt_a):
+    """Per-group (rows, sum ip, sum nnz, sum alen) of the symbolic (1) and
+    numeric (2) row maps of a single-product plan after its symbolic phase,
+    and the totals.  rpt_a: A's row pointers (device tensor)."""
     ip, _ = plan.export(0)
-    m, gs = plan.export(what)
-    rows = (m & 0xffffffff).long()
-    rpt = torch.from_numpy(a.rpt).to(ip.device)
-    alen = (rpt[1:] - rpt[:-1])
-    nnz = (plan.rpts[0][1:] - plan.rpts[0][:-1]) if plan.rpts else torch.zeros_like(ip)
-    out = {}
-    for g in range(8):
-        sel = rows[gs[g]:gs[g + 1]]
-        out[g] = dict(rows=int(sel.numel()), ip=int(ip[sel].sum()), nnz=int(nnz[sel].sum()),
-                      alen=int(alen[sel].sum()))
-    tot = dict(rows=a.nrows, ip=int(ip.sum()), nnz=int(nnz.sum()), alen=int(alen.sum()))
-    return out, tot
+    alen = (rpt_a[1:] - rpt_a[:-1])
+    nnz = plan.rpts[0][1:] - plan.rpts[0][:-1]
+    res = []
+    for what in (1, 2):
+        m, gs = plan.export(what)
+        rows = (m & 0xffffffff).long()
+        out = {}
+        for g in range(8):
+            sel = rows[gs[g]:gs[g + 1]]
+            out[g] = dict(rows=int(sel.numel()), ip=int(ip[sel].sum()), nnz=int(nnz[sel].sum()),
+                          alen=int(alen[sel].sum()))
+        res.append(out)
+    tot = dict(rows=int(alen.numel()), ip=int(ip.sum()), nnz=int(nnz.sum()),
+               alen=int(alen.sum()))
+    return res[0], res[1], tot
 
 
-def cpu_baseline(a, target_s: float = 10.0):
-    """The CPU oracle on the same product, timed on this host's cores over
-    row slices (rows i with i mod 8 = k, for k = 0, 1, 2, ... cycling) until
-    about target_s seconds of work are done."""
+def model_bytes(model, u):
+    return (model["ip"] * u["ip"] + model["nnz"] * u["nnz"] + model["alen"] * u["alen"]
+            + model["row"] * u["rows"])
+
+
+def launch_groups(timings, steps):
+    """Average duration per step of every launch group (HIP events on the
+    plan's stream), and the same with the dense and rank launches of the
+    numeric chunk group (num.g7, num.g7r: disjoint chunks) taken as one."""
+    agg = {}
+    for tl in timings:
+        for name, t in tl:
+            agg.setdefault(name, []).append(t)
+    avg = {k: float(np.sum(v)) / steps for k, v in agg.items()}
+    per_launch = {}
+    for k, v in avg.items():
+        key = "num.g7" if k.startswith("num.g7") else k
+        per_launch[key] = per_launch.get(key, 0.0) + v
+    return avg, per_launch
+
+
+def alg_bytes_of(name, units):
+    """Algorithmic bytes of launch group `name` ("sym.g5", "num.g7",
+    "plan.ipcount", ...) from the per-group units of its plan."""
+    sym_u, num_u, tot = units
+    phase, grp = name.split(".")
+    if phase == "num" and grp.startswith("g"):
+        return model_bytes(NUM_BYTES, num_u[int(grp[1])])
+    if phase == "sym" and grp.startswith("g"):
+        return model_bytes(SYM_BYTES, sym_u[int(grp[1])])
+    return model_bytes(PLAN_BYTES, tot)
+
+
+def roofline_entry(name, ms, nbytes, traffic=None, kernel=None):
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel or name, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "alg_bytes_per_launch": int(nbytes),
+            "avg_launch_ms": round(ms, 4)}
+
+
+def plan_units(da, db):
+    """Group units of C = A * B under the default options."""
+    from paper_2512_12036_amd import spgemm
+    plan = spgemm.Plan(da, db, spgemm.make_options())
+    plan.symbolic()
+    u = group_units(plan, da.rpt)
+    plan.free()
+    return u
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(fn, reps: int = 3) -> list[float]:
+    """Wall seconds of `reps` runs of fn() (the oracle on a fixed sample)."""
+    out = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        out.append(time.perf_counter() - t0)
+    return out
+
+
+def cpu_baseline_of(a, b, rows, flops: float, sample: str, rows_1core=None,
+                    flops_1core: float = 0.0):
+    """The oracle timed on this host: the median of 3 runs on all threads over
+    `rows` of A*B (flops = 2 x their intermediate products), and one run on a
+    single thread over rows_1core."""
+    import oracle
+    nthreads = oracle.max_threads()
+    t_all = time_oracle(lambda: oracle.product(a, b, rows))
+    med = float(np.median(t_all))
+    out = {"value": round(flops / med / 1e9, 3), "unit": "GFLOP/s", "cores": nthreads,
+           "kind": "oracle", "sample": f"{sample}; median of {len(t_all)} runs "
+                                       f"({', '.join(f'{t:.2f}' for t in t_all)} s)",
+           "cpu_model": cpu_model()}
+    if rows_1core is not None:
+        oracle.set_threads(1)
+        try:
+            t1 = time_oracle(lambda: oracle.product(a, b, rows_1core), reps=1)[0]
+        finally:
+            oracle.set_threads(nthreads)
+        out["one_core"] = {"value": round(flops_1core / t1 / 1e9, 3), "unit": "GFLOP/s",
+                           "seconds": round(t1, 2)}
+    return out
+
+
+def cpu_baseline(a):
+    """The CPU oracle on the R-MAT 18 self-product over row slices (rows i
+    with i mod 8 = k): three slices (3/8 of the product, about 3 s on 16
+    threads) for the median of 3, one slice on one thread."""
     import oracle
     ip = oracle.ip(a, a)
-    stride = 8
-    done_ip, t_total, slices = 0, 0.0, 0
-    while t_total < target_s and slices < 64:
-        rows = np.arange(slices % stride, a.nrows, stride, dtype=np.int64)
-        t0 = time.perf_counter()
-        oracle.product(a, a, rows)
-        t_total += time.perf_counter() - t0
-        done_ip += int(ip[rows].sum())
-        slices += 1
-    return {"value": round(2.0 * done_ip / t_total / 1e9, 3), "unit": "GFLOP/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{slices} row slices of A (rows i with i mod 8 = k, k cycling; "
-                      f"{done_ip} intermediate products = {slices / stride:.2f} x the whole "
-                      f"product), FP64 Gustavson, {t_total:.1f} s"}
+    rows = np.concatenate([np.arange(k, a.nrows, 8, dtype=np.int64) for k in range(3)])
+    rows1 = np.arange(3, a.nrows, 64, dtype=np.int64)
+    return cpu_baseline_of(a, a, rows, 2.0 * float(ip[rows].sum()),
+                           f"rows i with i mod 8 in {{0, 1, 2}} ({int(ip[rows].sum())} "
+                           f"intermediate products = 3/8 of the product), FP64 Gustavson",
+                           rows1, 2.0 * float(ip[rows1].sum()))
 
 
-def run_plain(args):
+def measure_product(da, db, steps: int, warmup: int, label: str):
+    """Times `steps` whole passes (plan, symbolic, allocation of C, numeric,
+    flag check, release) of C = A * B after `warmup` untimed ones, with the
+    launch groups timed by HIP events on the plan's stream."""
+    import torch
+    from paper_2512_12036_amd import spgemm
+    opt = spgemm.make_options(profile=1)
+    stream = torch.cuda.current_stream(da.rpt.device)
+
+    def step():
+        plan = spgemm.Plan(da, db, opt, stream)
+        plan.symbolic()
+        cols, vals = plan.allocate_outputs()
+        plan.numeric(cols, vals)
+        return plan, cols, vals
+
+    for w in range(warmup):
+        plan, cols, vals = step()
+        torch.cuda.synchronize()
+        plan.sync()
+        plan.free()
+        del cols, vals
+    log(f"[bench] {label}: {warmup} warmup steps done")
+    info = None
+    timings = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        plan, cols, vals = step()
+        torch.cuda.synchronize()
+        plan.sync()                     # kernel error flags of this step
+        timings.append(plan.timings())
+        if k == 0:
+            info = plan.info()
+        plan.free()
+        del cols, vals
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"[bench] {label}: {steps} timed steps done")
+    ms = (t1 - t0) * 1e3 / steps
+    avg, per_launch = launch_groups(timings, steps)
+    return dict(ms=ms, info=info, avg=avg, per_launch=per_launch, opt=opt)
+
+
+def dominant_roofline(per_launch, avg, units, chunk_cols=None):
+    dom = max(per_launch, key=lambda k: per_launch[k])
+    traffic = measured_traffic(dom, chunk_cols) if chunk_cols is not None else None
+    kernel = dom + (" (k_num_chunk_pipe + k_num_chunk_rank)"
+                    if dom == "num.g7" and "num.g7r" in avg else "")
+    return roofline_entry(dom, per_launch[dom], alg_bytes_of(dom, units), traffic, kernel)
+
+
+def run_rmat18(args):
     import torch
     from paper_2512_12036_amd import spgemm
     torch.cuda.init()
@@ -129,8 +277,6 @@ def run_plain(args):
     a = rmat18()
     da = spgemm.to_device(a, dev)
     torch.cuda.synchronize()
-    opt = spgemm.make_options(profile=1)
-    stream = torch.cuda.current_stream(dev)
     if args.calib_copy_mib:
         # a plain copy of known size: the scale for the HBM byte counters
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -141,78 +287,16 @@ def run_plain(args):
         torch.cuda.synchronize()
         del src, dst
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
-
-    def step():
-        plan = spgemm.Plan(da, da, opt, stream)
-        plan.symbolic()
-        cols, vals = plan.allocate_outputs()
-        plan.numeric(cols, vals)
-        return plan, cols, vals
-
-    for w in range(args.warmup):
-        plan, cols, vals = step()
-        torch.cuda.synchronize()
-        plan.free()
-        del cols, vals
-        log(f"[bench] warmup {w + 1}/{args.warmup} done")
-    info = None
-    timings = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        plan, cols, vals = step()
-        torch.cuda.synchronize()
-        timings.append(plan.timings())
-        if k == 0:
-            info = plan.info()
-        plan.free()
-        del cols, vals
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"[bench] {args.steps} timed steps done")
-    ms = (t1 - t0) * 1e3 / args.steps
+    r = measure_product(da, da, args.steps, args.warmup, "R-MAT 18")
+    info, avg, per_launch = r["info"], r["avg"], r["per_launch"]
+    ms = r["ms"]
     flops = info.flops
     gflops = flops / (ms * 1e-3) / 1e9
-
-    # per-launch-group average durations (HIP events on the plan's stream)
-    agg = {}
-    for tl in timings:
-        for name, t in tl:
-            agg.setdefault(name, []).append(t)
-    avg = {k: float(np.mean(v)) * (len(v) / args.steps) for k, v in agg.items()}
-    # The chunked rows of the numeric phase (group 7) run as two kernels over
-    # disjoint chunks: dense accumulator (num.g7) and rank-indexed compact
-    # accumulator (num.g7r).  The roofline treats them as one launch group.
-    per_launch = {}
-    for k, v in avg.items():
-        key = "num.g7" if k.startswith("num.g7") else k
-        per_launch[key] = per_launch.get(key, 0.0) + v
-    dom = max(per_launch, key=lambda k: per_launch[k])
-
-    # algorithmic bytes of the dominant launch group
-    plan = spgemm.Plan(da, da, spgemm.make_options())
-    plan.symbolic()
-    sym_u, _ = group_units(plan, a, 1)
-    num_u, tot = group_units(plan, a, 2)
-    plan.free()
-    phase, grp = dom.split(".")
-    if phase == "num":
-        u = num_u[int(grp[1])]
-        model = NUM_BYTES
-    elif phase == "sym" and grp.startswith("g"):
-        u = sym_u[int(grp[1])]
-        model = SYM_BYTES
-    else:
-        u = tot
-        model = PLAN_BYTES
-    nbytes = model["ip"] * u["ip"] + model["nnz"] * u["nnz"] + model["alen"] * u["alen"] + \
-        model["row"] * u["rows"]
-    achieved = nbytes / (per_launch[dom] * 1e-3) / 1e9
-    num_total_bytes = sum(NUM_BYTES["ip"] * v["ip"] + NUM_BYTES["nnz"] * v["nnz"] +
-                          NUM_BYTES["alen"] * v["alen"] + NUM_BYTES["row"] * v["rows"]
-                          for g, v in num_u.items() if g > 0)
+    units = plan_units(da, da)
+    roof = dominant_roofline(per_launch, avg, units, r["opt"].chunk_cols)
+    num_u = units[1]
+    num_total_bytes = sum(model_bytes(NUM_BYTES, v) for g, v in num_u.items() if g > 0)
     num_ms = sum(t for k, t in avg.items() if k.startswith("num."))
-
     out = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -222,15 +306,7 @@ def run_plain(args):
                                "(a,b,c,d) = (.57,.19,.19,.05), duplicates merged, FP32 in (0,1]",
                    "nnz_a": a.nnz, "intermediate_products": info.ip_total,
                    "nnz_c": info.nnz_c, "flops": flops},
-        "roofline": {"bound": "hbm",
-                     "kernel": dom + (" (k_num_chunk_pipe + k_num_chunk_rank)"
-                                      if dom == "num.g7" and "num.g7r" in avg else ""),
-                     "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom, opt.chunk_cols),
-                     "alg_bytes_per_launch": int(nbytes),
-                     "avg_launch_ms": round(per_launch[dom], 4)},
+        "roofline": roof,
         "numeric_phase": {"ms": round(num_ms, 3), "alg_bytes": int(num_total_bytes),
                           "alg_GBps": round(num_total_bytes / (num_ms * 1e-3) / 1e9, 1)
                           if num_ms > 0 else None},
@@ -239,59 +315,296 @@ def run_plain(args):
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a row sample ...")
         out["cpu_baseline"] = cpu_baseline(a)
+    del da
+    torch.cuda.empty_cache()
     return out
 
 
-def run_served(n_req: int):
+def run_er2k(args):
+    """Erdos-Renyi 2,000 x 2,000 with 16,000 nonzeros, C = A*A: the latency
+    floor of one whole pass."""
+    import torch
+    from paper_2512_12036_amd import gen, spgemm
+    a = gen.er(2000, 16000, seed=1)
+    da = spgemm.to_device(a)
+    steps = max(20, 4 * args.steps)
+    r = measure_product(da, da, steps, max(5, args.warmup), "ER 2k")
+    units = plan_units(da, da)
+    out = {"workload": "C = A*A, A 2,000 x 2,000 Erdos-Renyi G(n, M), M = 16,000, FP32 U[-1, 1]",
+           "steps": steps, "ms_per_step": round(r["ms"], 4),
+           "gflops": round(r["info"].flops / (r["ms"] * 1e-3) / 1e9, 3),
+           "intermediate_products": r["info"].ip_total, "nnz_c": r["info"].nnz_c,
+           "roofline": dominant_roofline(r["per_launch"], r["avg"], units),
+           "phases_ms": {k: round(v, 4) for k, v in sorted(r["avg"].items())}}
+    if not args.no_cpu:
+        rows = np.arange(a.nrows, dtype=np.int64)
+        out["cpu_baseline"] = cpu_baseline_of(a, a, rows, float(r["info"].flops),
+                                              "the whole product", rows, float(r["info"].flops))
+    return out
+
+
+def run_contraction(args):
+    """Graph contraction C = S^T (A S), A R-MAT scale 20 edge factor 8, S the
+    n x n/16 selector of uniform labels.  A step: S and S^T built on the
+    device from the labels, then the two products, both kept on the GPU."""
+    import torch
+    from paper_2512_12036_amd import apps, gen, spgemm
+    log("[bench] generating R-MAT scale 20 (contraction) ...")
+    a = gen.rmat(20, 8, seed=23)
+    k = a.nrows // 16
+    labels_h = gen.contraction_labels(a.nrows, k, seed=24)
+    da = spgemm.to_device(a)
+    labels = torch.from_numpy(labels_h).cuda()
+    opt = spgemm.make_options(profile=1)
+
+    def product(x, y):
+        plan = spgemm.Plan(x, y, opt)
+        plan.symbolic()
+        cols, vals = plan.allocate_outputs()
+        plan.numeric(cols, vals)
+        torch.cuda.synchronize()
+        plan.sync()
+        c = plan.results(cols, vals)[0]
+        t = plan.timings()
+        plan.free()
+        return c, t
+
+    def step():
+        s = apps.selector(labels, k)
+        st = spgemm.selector_transpose(labels, k)
+        p, tp = product(da, s)
+        c, tc = product(st, p)
+        return p, c, tp, tc, s, st
+
+    for _ in range(max(2, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    steps = max(5, args.steps)
+    tps, tcs = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p, c, tp, tc, s, st = step()
+        tps.append(tp)
+        tcs.append(tc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    log(f"[bench] contraction: {steps} timed steps done")
+    up = plan_units(da, s)
+    uc = plan_units(st, p)
+    avg_p, pl_p = launch_groups(tps, steps)
+    avg_c, pl_c = launch_groups(tcs, steps)
+    ip_p, ip_c = up[2]["ip"], uc[2]["ip"]
+    flops = 2 * (ip_p + ip_c)
+    rp = dominant_roofline(pl_p, avg_p, up)
+    rc = dominant_roofline(pl_c, avg_c, uc)
+    roof = rp if rp["avg_launch_ms"] >= rc["avg_launch_ms"] else rc
+    roof["kernel"] = ("A*S " if roof is rp else "S^T*P ") + roof["kernel"]
+    out = {"workload": "C = S^T (A S), A R-MAT scale 20 (1,048,576 vertices), edge factor 8, "
+                       "FP32 in (0,1]; S n x n/16, one 1.0 per row at a uniform cluster id",
+           "steps": steps, "ms_per_step": round(ms, 3),
+           "ms_products": {"A*S": round(sum(pl_p.values()), 3),
+                           "S^T*P": round(sum(pl_c.values()), 3)},
+           "gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+           "intermediate_products": [ip_p, ip_c], "nnz": [p.nnz, c.nnz],
+           "roofline": roof}
+    if not args.no_cpu:
+        import oracle
+        sh = gen.selector(labels_h, k)
+        sth = gen.Csr(k, a.nrows, *oracle.transpose(a.nrows, k, sh.rpt, sh.col, sh.val))
+        ph = oracle.product(a, sh)
+        ph = gen.Csr(a.nrows, k, ph.rpt, ph.col, ph.val.astype(np.float32))
+
+        def both(sel_a, sel_c):
+            oracle.product(a, sh, sel_a)
+            oracle.product(sth, ph, sel_c)
+        import functools
+        rows_a = np.arange(a.nrows, dtype=np.int64)
+        rows_c = np.arange(k, dtype=np.int64)
+        t_all = time_oracle(functools.partial(both, rows_a, rows_c))
+        nthreads = oracle.max_threads()
+        oracle.set_threads(1)
+        try:
+            t1 = time_oracle(functools.partial(both, rows_a, rows_c), reps=1)[0]
+        finally:
+            oracle.set_threads(nthreads)
+        med = float(np.median(t_all))
+        out["cpu_baseline"] = {
+            "value": round(flops / med / 1e9, 3), "unit": "GFLOP/s", "cores": nthreads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "both products, all rows (the oracle's own P feeds S^T P); median of 3 "
+                      f"runs ({', '.join(f'{t:.2f}' for t in t_all)} s)",
+            "one_core": {"value": round(flops / t1 / 1e9, 3), "unit": "GFLOP/s",
+                         "seconds": round(t1, 2)}}
+    del da, p, c, s, st
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_mcl(args):
+    """Markov clustering: 100,000-node planted partition (1,000 communities),
+    5 iterations of expansion T*T, inflation x^2, row normalisation, prune at
+    1e-4, renormalisation, on the row-stochastic transpose T = M^T.  A step is
+    the whole 5-iteration loop; throughput counts the expansions' products."""
+    import torch
+    from paper_2512_12036_amd import gen, spgemm
+    log("[bench] generating the planted-partition graph (MCL) ...")
+    t0h = gen.planted_partition(1000, 100, seed=5)
+    t0 = spgemm.to_device(t0h)
+    opt = spgemm.make_options(profile=1)
+
+    def loop(record):
+        t = t0
+        it_ms, tl, ips, units = [], [], [], []
+        for it in range(5):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            plan = spgemm.Plan(t, t, opt)
+            plan.symbolic()
+            cols, vals = plan.allocate_outputs()
+            plan.numeric(cols, vals)
+            torch.cuda.synchronize()
+            plan.sync()
+            e = plan.results(cols, vals)[0]
+            tl.append(plan.timings())
+            ips.append(plan.info().ip_total)
+            plan.free()
+            del cols, vals
+            if record:
+                units.append(plan_units(t, t))
+            nt = spgemm.mcl_prune(e, 2.0, 1e-4)
+            ev1.record()
+            del e
+            t = nt
+            torch.cuda.synchronize()
+            it_ms.append(ev0.elapsed_time(ev1))
+        return it_ms, tl, ips, units, t
+
+    loop(False)
+    torch.cuda.empty_cache()
+    log("[bench] mcl: warmup loop done")
+    steps = 2
+    all_ms, all_tl = [], []
+    torch.cuda.synchronize()
+    tt = time.perf_counter()
+    for _ in range(steps):
+        it_ms, tl, ips, _, tfin = loop(False)
+        all_ms.append(it_ms)
+        all_tl.append(tl)
+        torch.cuda.empty_cache()
+    ms = (time.perf_counter() - tt) * 1e3 / steps
+    log(f"[bench] mcl: {steps} timed loops done")
+    _, _, _, units, _ = loop(True)
+    torch.cuda.empty_cache()
+    flops = 2 * sum(ips)
+    # dominant launch group over the iterations
+    best = None
+    for it in range(5):
+        avg, pl = launch_groups([all_tl[s][it] for s in range(steps)], steps)
+        r = dominant_roofline(pl, avg, units[it])
+        if best is None or r["avg_launch_ms"] > best["avg_launch_ms"]:
+            best = r
+            best["kernel"] = f"iteration {it + 1} " + r["kernel"]
+    out = {"workload": "MCL on a 100,000-node planted partition (1,000 communities of 100, "
+                       "~25 intra + ~5 inter edges per node, + self loops), column-stochastic "
+                       "FP32; 5 iterations of expansion, inflation power 2, prune at 1e-4, "
+                       "renormalisation",
+           "steps": steps, "ms_per_step": round(ms, 2),
+           "ms_per_iteration": [round(float(np.mean([m[i] for m in all_ms])), 3)
+                                for i in range(5)],
+           "gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+           "intermediate_products": ips, "nnz_final": tfin.nnz, "roofline": best}
+    if not args.no_cpu:
+        import oracle
+        ip1 = oracle.ip(t0h, t0h)
+        rows = np.arange(t0h.nrows, dtype=np.int64)
+        rows1 = np.arange(0, t0h.nrows, 4, dtype=np.int64)
+        out["cpu_baseline"] = cpu_baseline_of(
+            t0h, t0h, rows, 2.0 * float(ip1.sum()),
+            f"iteration 1's expansion, all rows ({int(ip1.sum())} intermediate products)",
+            rows1, 2.0 * float(ip1[rows1].sum()))
+    del t0, tfin
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_served(n_req: int, configs):
     """Served GNN aggregation trace: n_req requests C = A_hat X (seeds 0 ..
-    n_req - 1) generated in device memory, served with continuous batching
-    under a 200 GB HBM budget and, for comparison, one request after another
-    on single-product plans.  The backlogged trace (all requests waiting at
-    t = 0) gives the throughputs and the speedup; a second pass with Poisson
-    arrivals at 0.7 x the served capacity gives the latency percentiles."""
+    n_req - 1).  The graphs A_hat are generated in device memory first (the
+    resident graph store, untimed); each request's features X are built on
+    the device when it is admitted and released when it completes, inside the
+    HBM budget of 200 GB.  Served with continuous batching and, for
+    comparison, one request after another on single-product plans (which
+    build X the same way).  For each server configuration (max requests and
+    products per batch, streams) the backlogged trace (all requests waiting
+    at t = 0) gives the throughput and the speedup, and a second pass with
+    Poisson arrivals at 0.7 x that configuration's capacity the latency
+    percentiles."""
     import torch
     from paper_2512_12036_amd import serve
-    log(f"[bench] generating {n_req} served requests on the GPU ...")
-    reqs = serve.gnn_requests(range(n_req), "cuda")
+    log(f"[bench] generating {n_req} served requests (graphs on the GPU) ...")
+    reqs = serve.gnn_requests(range(n_req), "cuda", features_on_admission=True,
+                              log=log if n_req > 512 else None)
     torch.cuda.synchronize()
     ip_total = sum(r.ip for r in reqs)
-    srv = serve.Server(budget_bytes=200 << 30, max_batch=64, max_batch_ip=8 << 30, n_streams=4)
+    budget = 200 * 10 ** 9
     warm = reqs[:min(16, n_req)]
-    srv.run(warm)
     serve.run_plain(warm)
-    log("[bench] served run (backlogged) ...")
-    s_stats, _ = srv.run(reqs)
     log("[bench] plain run ...")
     p_stats, _ = serve.run_plain(reqs)
-    rate = 0.7 * n_req / s_stats["makespan_s"]
-    arr = serve.poisson_arrivals(n_req, rate, seed=11)
-    for r, t in zip(reqs, arr):
-        r.arrival = float(t)
-    log(f"[bench] served run (Poisson arrivals, {rate:.0f}/s) ...")
-    l_stats, _ = srv.run(reqs)
-    return {"requests": n_req, "intermediate_products": ip_total,
-            "workload": "C = A_hat X, A_hat sym-normalised G(n, n d / 2) + I, n log-uniform "
-                        "[1e3, 2e5], d U[5, 50]; X n x F, F U{64..512}, round(rho F) kept "
-                        "dense columns, rho U[0.1, 0.5]; FP32",
-            "hbm_budget_gb": 200, "batches": s_stats["batches"],
-            "served_gflops": round(s_stats["gflops"], 2),
-            "plain_gflops": round(p_stats["gflops"], 2),
+    out = {"requests": n_req, "intermediate_products": ip_total,
+           "workload": "C = A_hat X, A_hat sym-normalised G(n, n d / 2) + I, n log-uniform "
+                       "[1e3, 2e5], d U[5, 50]; X n x F, F U{64..512}, round(rho F) kept "
+                       "dense columns, rho U[0.1, 0.5]; FP32; graphs resident, X built on "
+                       "admission and released on completion",
+           "hbm_budget_gb": budget / 1e9,
+           "plain_gflops": round(p_stats["gflops"], 2),
+           "plain_makespan_s": round(p_stats["makespan_s"], 4),
+           "plain_backlogged_p50_ms": round(p_stats["p50_ms"], 3), "servers": []}
+    for max_batch, max_batch_ip, n_streams in configs:
+        srv = serve.Server(budget_bytes=budget, max_batch=max_batch, max_batch_ip=max_batch_ip,
+                           n_streams=n_streams)
+        srv.run(warm)
+        for r in reqs:
+            r.arrival = 0.0
+        log(f"[bench] served run (backlogged, batches of <= {max_batch}) ...")
+        s_stats, _ = srv.run(reqs)
+        torch.cuda.empty_cache()
+        rate = 0.7 * n_req / s_stats["makespan_s"]
+        arr = serve.poisson_arrivals(n_req, rate, seed=11)
+        for r, t in zip(reqs, arr):
+            r.arrival = float(t)
+        log(f"[bench] served run (Poisson arrivals, {rate:.0f}/s) ...")
+        l_stats, _ = srv.run(reqs)
+        torch.cuda.empty_cache()
+        out["servers"].append({
+            "max_batch": max_batch, "max_batch_ip": max_batch_ip, "streams": n_streams,
+            "batches": s_stats["batches"], "served_gflops": round(s_stats["gflops"], 2),
             "speedup_vs_plain": round(p_stats["makespan_s"] / s_stats["makespan_s"], 3),
             "served_makespan_s": round(s_stats["makespan_s"], 4),
-            "plain_makespan_s": round(p_stats["makespan_s"], 4),
+            "peak_admitted_gb": round(s_stats["peak_admitted_bytes"] / 1e9, 2),
+            "budget_waits": s_stats["budget_waits"], "budget_cuts": s_stats["budget_cuts"],
             "arrival_rate_per_s": round(rate, 1),
             "p50_ms": round(l_stats["p50_ms"], 3), "p99_ms": round(l_stats["p99_ms"], 3),
-            "plain_backlogged_p50_ms": round(p_stats["p50_ms"], 3)}
+            "poisson_peak_admitted_gb": round(l_stats["peak_admitted_bytes"] / 1e9, 2)})
+    best = max(out["servers"], key=lambda x: x["served_gflops"])
+    out.update({k: best[k] for k in ("served_gflops", "speedup_vs_plain", "p50_ms", "p99_ms")})
+    del reqs
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-requests", type=int, default=1024,
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the served GNN trace (0: skip it)")
+
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the ER, contraction and MCL workloads")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -299,9 +612,14 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the row-block "
               f"sharding over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
-    out = run_plain(args)
+    out = run_rmat18(args)
+    if not args.no_configs:
+        out["configs"] = {"er2k": run_er2k(args), "contraction": run_contraction(args),
+                          "mcl": run_mcl(args)}
     if args.serve_requests > 0:
-        out["served"] = run_served(args.serve_requests)
+        # small batches (latency, throughput) and large ones (the HBM budget
+        # binds: batches are closed by it)
+        out["served"] = run_served(args.serve_requests, [(64, 8 << 30, 4), (1024, 128 << 30, 4)])
     print(json.dumps(out), flush=True)
 
 

@@ -115,8 +115,11 @@ typedef struct {
      * in row order, so that the chunks of one row share its A nonzeros and
      * sub-range tables in cache. */
     int32_t chunk_cols;
-    /* 0: host-side checks only; 1: also check row_ptr / col_idx of A and B
-     * on the device (one pass each) and fail with SPGEMM_EINDEX. */
+    /* Validation level of A and B: 0 none (host-side argument checks only);
+     * 1 cheap: row pointers checked on the device (row_ptr[0] = 0,
+     * non-decreasing, row_ptr[nrows] = nnz; one pass over nrows + 1 values);
+     * 2 full: also every column index in [0, ncols) (one pass over nnz
+     * values).  A malformed input fails with SPGEMM_EINDEX. */
     int32_t validate;
     /* 1: record a HIP event pair around every kernel launch group on the
      * plan's stream (read back with spgemm_timing). */
@@ -157,6 +160,11 @@ typedef struct {
      * output pointers of each call reach the kernels through the uploaded
      * descriptors.  Ignored (launches stay eager) when profile = 1.  0 = off. */
     int32_t graph;
+    /* Most column-chunk work items (group 7) a plan may create in either
+     * phase; 0 = 2^31 - 1, what the 32-bit item indexing holds.  A plan that
+     * needs more fails with SPGEMM_EOVERFLOW: spgemm_plan_create for the
+     * symbolic items, spgemm_symbolic for the numeric ones. */
+    int64_t item_limit;
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;
@@ -230,6 +238,18 @@ spgemm_status spgemm_numeric_batch(spgemm_plan *p, const float *const *a_values,
                                    int32_t *const *c_col_idx,
                                    float *const *c_values);
 
+/* Row-size estimation alone (paper Algorithm 1), for admission control
+ * before a plan exists: writes three int64 to out (device memory, caller
+ * owned): out[0] = sum over rows of the intermediate products, out[1] = sum
+ * over rows of min(intermediate products, B.ncols), an upper bound of
+ * nnz(C), out[2] = the largest row's intermediate products.  Reads
+ * A.row_ptr, A.col_idx and B.row_ptr only (no values, no B columns).
+ * Enqueued on `stream`; never synchronises and allocates nothing.  Errors:
+ * EINVAL (NULL pointers, negative sizes), EDIM (A.ncols != B.nrows or a size
+ * >= 2^31), EHIP (launch failed). */
+spgemm_status spgemm_estimate(const spgemm_csr *A, const spgemm_csr *B, int64_t *out,
+                              void *stream);
+
 /* Waits for the plan's stream and reports a kernel-raised error flag
  * (EINTERNAL) or a failed launch (EHIP). */
 spgemm_status spgemm_sync(spgemm_plan *p);
@@ -276,22 +296,54 @@ spgemm_status spgemm_selector_transpose(const int32_t *labels, int64_t n, int64_
  * row-stochastic transpose of the column-stochastic matrix (the paper's
  * column operations become row operations): every entry x becomes x^power,
  * each row is divided by its sum, entries below theta are dropped (strictly:
- * y >= theta is kept) and each row is divided by the sum of what it keeps;
- * kept entries stay in their input order.  Two calls share `workspace`
- * (spgemm_mcl_prune_workspace(m) bytes of device memory):
+ * y >= theta is kept), with k > 0 only the k largest of the rest are kept
+ * (ordered by the input values, which must be nonnegative; equal values in
+ * storage order, so the lower columns of a column-sorted row first), and
+ * each row is divided by the sum of what it keeps; kept entries stay in
+ * their input order.  Two calls share `workspace`
+ * (spgemm_mcl_prune_workspace(m) bytes of device memory) and the same
+ * power, theta and k:
  *   _count writes the m + 1 output row pointers (device) and returns the
  *          output length in *out_nnz (host; synchronises the stream);
  *   _write fills out_col / out_val (device, out_nnz entries each).
  * Arithmetic in FP32.  A row whose entries are all zero keeps nothing.
- * EINVAL for NULL pointers, negative m, theta < 0 or power <= 0. */
+ * EINVAL for NULL pointers, negative m or k, theta < 0 or power <= 0. */
 size_t spgemm_mcl_prune_workspace(int64_t m);
 spgemm_status spgemm_mcl_prune_count(int64_t m, const int64_t *row_ptr, const float *values,
-                                     float power, float theta, int64_t *out_row_ptr,
+                                     float power, float theta, int32_t k, int64_t *out_row_ptr,
                                      void *workspace, int64_t *out_nnz, void *stream);
 spgemm_status spgemm_mcl_prune_write(int64_t m, const int64_t *row_ptr, const int32_t *col_idx,
-                                     const float *values, float power, float theta,
+                                     const float *values, float power, float theta, int32_t k,
                                      const int64_t *out_row_ptr, void *workspace,
                                      int32_t *out_col, float *out_val, void *stream);
+
+/* The convergence test of Markov clustering (paper Algorithm 6 iterates
+ * while successive matrices change): writes to *out (device, one double)
+ * the largest |a_ij - b_ij| over the union of the patterns of two m-row CSR
+ * matrices A and B with column-sorted rows (an entry stored on one side
+ * only counts against 0), computed in FP64 from the FP32 values, so exactly.
+ * Enqueued on `stream`, no synchronisation.  EINVAL for NULL pointers or
+ * negative sizes. */
+spgemm_status spgemm_mcl_change(int64_t m, const int64_t *rpt_a, const int32_t *col_a,
+                                const float *val_a, const int64_t *rpt_b, const int32_t *col_b,
+                                const float *val_b, int64_t nnz_a, int64_t nnz_b, double *out,
+                                void *stream);
+
+/* The cluster interpretation of Markov clustering (paper Algorithm 6, last
+ * step): connected components of the undirected graph with an edge {i, j}
+ * for every stored entry (i, j) of the n x n pattern (row_ptr n + 1 int64,
+ * col_idx nnz int32; values are not read).  labels (device, n int32) gets,
+ * for every vertex, the smallest vertex of its component.  Rounds of
+ * hooking and pointer jumping on the device; the host reads a flag after
+ * each round (synchronises the stream) and returns the number of rounds in
+ * *rounds (host, may be NULL).  workspace: spgemm_components_workspace()
+ * bytes of device memory.  EINVAL for NULL pointers or negative sizes, EDIM
+ * for n >= 2^31, EINTERNAL if the rounds do not settle (a malformed
+ * pattern). */
+size_t spgemm_components_workspace(void);
+spgemm_status spgemm_components(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                                int64_t nnz, int32_t *labels, void *workspace, void *stream,
+                                int32_t *rounds);
 
 /* Releases a plan and its workspace.  NULL-safe.  Waits for the stream. */
 void spgemm_free(spgemm_plan *p);

@@ -14,6 +14,9 @@ path (``paper_2512_12036_amd``) never does, and shares no code with it.
   Algorithm 6): Hadamard power, column normalisation and pruning, written on
   the transposed (row-stochastic) matrix so that column operations are row
   operations.
+* ``mcl_prune_topk``, ``mcl_change`` and ``components`` are the top-k
+  pruning, the convergence measure and the cluster interpretation of
+  Algorithm 6.
 * ``transpose`` builds S^T for graph contraction (paper Algorithm 7).
 
 Every function here is pinned by ``tests/test_oracle*.py`` against closed
@@ -213,6 +216,86 @@ def mcl_inflate_normalize_prune(rpt, col, val, power: float, theta: float):
     return nrpt, ncol, nval, before
 
 
+def mcl_prune_topk(rpt, col, val, power: float, theta: float, k: int):
+    """The pruning step of Algorithm 6 with its top-k part, on row-stochastic
+    storage, in FP64: x -> x**power, divide each row by its sum, drop entries
+    below theta (strictly), keep only the k largest of what is left (k = 0:
+    no limit; among equal values the lower columns first), divide each row
+    by the sum of what it keeps.  Returns (rpt, col, val, before) like
+    mcl_inflate_normalize_prune."""
+    rpt = np.asarray(rpt, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    col = np.asarray(col)
+    m = rpt.shape[0] - 1
+    new_cols, new_vals, counts = [], [], np.zeros(m, dtype=np.int64)
+    before = np.zeros_like(val)
+    for i in range(m):
+        s, e = rpt[i], rpt[i + 1]
+        x = val[s:e] ** power
+        tot = x.sum()
+        y = x / tot if tot > 0 else x
+        before[s:e] = y
+        keep = np.nonzero(y >= theta)[0]
+        if k > 0 and keep.shape[0] > k:
+            # largest first; equal values in ascending column order
+            order = sorted(keep, key=lambda j: (-y[j], col[s + j]))
+            keep = np.sort(np.asarray(order[:k], dtype=np.int64))
+        z = y[keep]
+        tz = z.sum()
+        z = z / tz if tz > 0 else z
+        new_cols.append(col[s:e][keep])
+        new_vals.append(z)
+        counts[i] = z.shape[0]
+    nrpt = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(counts, out=nrpt[1:])
+    ncol = np.concatenate(new_cols).astype(np.int32) if m else np.zeros(0, np.int32)
+    nval = np.concatenate(new_vals) if m else np.zeros(0)
+    return nrpt, ncol, nval, before
+
+
+def mcl_change(rpt_a, col_a, val_a, rpt_b, col_b, val_b) -> float:
+    """The change between successive iterates of Algorithm 6: the largest
+    |a_ij - b_ij| over the union of the two patterns (an entry missing from
+    one side counts as 0)."""
+    m = len(rpt_a) - 1
+    worst = 0.0
+    for i in range(m):
+        da = dict(zip(col_a[rpt_a[i]:rpt_a[i + 1]], val_a[rpt_a[i]:rpt_a[i + 1]]))
+        db = dict(zip(col_b[rpt_b[i]:rpt_b[i + 1]], val_b[rpt_b[i]:rpt_b[i + 1]]))
+        for c in set(da) | set(db):
+            worst = max(worst, abs(float(da.get(c, 0.0)) - float(db.get(c, 0.0))))
+    return worst
+
+
+def components(n: int, rpt, col) -> np.ndarray:
+    """Cluster interpretation of Algorithm 6's final matrix: the connected
+    components of the undirected graph with an edge {i, j} for every stored
+    entry (i, j) of the n x n matrix, by breadth-first search.  Each vertex
+    is labelled with the smallest vertex of its component (int32)."""
+    rpt = np.asarray(rpt, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    adj = [[] for _ in range(n)]
+    for i in range(n):
+        for j in col[rpt[i]:rpt[i + 1]]:
+            adj[i].append(int(j))
+            adj[int(j)].append(i)
+    label = np.full(n, -1, dtype=np.int64)
+    for v in range(n):              # ascending: v is its component's smallest
+        if label[v] >= 0:
+            continue
+        label[v] = v
+        frontier = [v]
+        while frontier:
+            nxt = []
+            for u in frontier:
+                for w in adj[u]:
+                    if label[w] < 0:
+                        label[w] = v
+                        nxt.append(w)
+            frontier = nxt
+    return label.astype(np.int32)
+
+
 def transpose(nrows: int, ncols: int, rpt, col, val):
     """CSR transpose with ascending columns in every output row."""
     rpt = np.asarray(rpt, dtype=np.int64)
@@ -258,7 +341,9 @@ def compare(ref: Product, rpt, col, val, rows: np.ndarray | None = None,
             np.zeros(0, dtype=np.int64)
         g_col = col[idx]
         g_val = val[idx].astype(np.float64)
-    if not np.array_equal(g_col.astype(np.int64), ref.col.astype(np.int64)):
+    same = (np.array_equal(g_col, ref.col) if g_col.dtype == ref.col.dtype else
+            np.array_equal(g_col.astype(np.int64), ref.col.astype(np.int64)))
+    if not same:
         pos = int(np.nonzero(g_col.astype(np.int64) != ref.col)[0][0])
         return f"col_idx differs at entry {pos}"
     if exact_values:

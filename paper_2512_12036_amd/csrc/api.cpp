@@ -228,7 +228,8 @@ spgemm_status check_options(const spgemm_options &o) {
     if (o.sym_upper[kGroups - 2] > o.num_upper[kGroups - 2]) return SPGEMM_EINVAL;
     if (o.chunk_cols < 64 || o.chunk_cols > kMaxChunkCols || (o.chunk_cols % 64) != 0)
         return SPGEMM_EINVAL;
-    if (o.validate < 0 || o.validate > 1) return SPGEMM_EINVAL;
+    if (o.validate < 0 || o.validate > 2) return SPGEMM_EINVAL;
+    if (o.item_limit < 0) return SPGEMM_EINVAL;
     if (o.profile < 0 || o.profile > 1) return SPGEMM_EINVAL;
     if (o.chunks_per_item != 1 && o.chunks_per_item != 2 && o.chunks_per_item != 4 &&
         o.chunks_per_item != 8)
@@ -255,6 +256,11 @@ spgemm_status check_csr(const spgemm_csr &m, bool need_values) {
     return SPGEMM_OK;
 }
 
+int64_t item_limit(const spgemm_options &o) {
+    const int64_t cap = (int64_t(1) << 31) - 1;
+    return (o.item_limit > 0 && o.item_limit < cap) ? o.item_limit : cap;
+}
+
 GroupBounds bounds_of(const int64_t *up) {
     GroupBounds gb{};
     for (int g = 0; g < kGroups - 1; ++g) gb.up[g] = up[g];
@@ -279,6 +285,12 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
     p->hstats.resize(nprod);
     p->nnz_c.assign(nprod, -1);
     int64_t row_base = 0;
+    {
+        size_t nb = 0;
+        for (int q = 0; q < nprod; ++q)
+            if (A[q].nrows > 0) nb += (size_t)((A[q].nrows + kRowBlock - 1) / kRowBlock);
+        p->hblks.reserve(nb);
+    }
     for (int q = 0; q < nprod; ++q) {
         const spgemm_csr &a = A[q], &b = B[q];
         ST_TRY(check_csr(a, false));
@@ -359,6 +371,9 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         ST_TRY(launch_check());
         ST_TRY(read_flags(p, f, 3));
         if (f[1] || f[2]) return SPGEMM_EINDEX;
+    }
+    if (p->opt.validate >= 2) {
+        int f[3];
         for (int q = 0; q < nprod; ++q) {
             CsrCheck ca{A[q].row_ptr, A[q].col_idx, A[q].nrows, A[q].nnz, A[q].ncols};
             CsrCheck cb{B[q].row_ptr, B[q].col_idx, B[q].nrows, B[q].nnz, B[q].ncols};
@@ -415,7 +430,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
     }
     if (p->nh != p->sym_start[kGroups] - p->sym_start[kGroups - 1]) return SPGEMM_EINTERNAL;
-    if (p->h_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
+    if (p->h_items > item_limit(p->opt)) return SPGEMM_EOVERFLOW;
 
     // chunk-group preparation: chunk bases, item -> row map, chunk bounds of
     // every B row, item descriptors
@@ -613,7 +628,7 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
         p->d_items += (int64_t)ps[q].d_items;
     }
     if (p->nd != p->num_start[kGroups] - p->num_start[kGroups - 1]) return SPGEMM_EINTERNAL;
-    if (p->d_items >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
+    if (p->d_items > item_limit(p->opt)) return SPGEMM_EOVERFLOW;
     p->n_items = p->d_items / p->opt.chunks_per_item;
     p->n_s1 = p->n_s0 = p->n_m1 = p->n_m0 = 0;
     if (p->nd > 0) {
@@ -869,6 +884,19 @@ spgemm_status spgemm_numeric_batch(spgemm_plan *p, const float *const *a_values,
     return numeric_impl(p);
 }
 
+spgemm_status spgemm_estimate(const spgemm_csr *A, const spgemm_csr *B, int64_t *out,
+                              void *stream) {
+    if (!A || !B || !out) return SPGEMM_EINVAL;
+    if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0 || B->nrows < 0 || B->ncols < 0)
+        return SPGEMM_EINVAL;
+    if (A->nrows >= (int64_t(1) << 31) || B->ncols >= (int64_t(1) << 31)) return SPGEMM_EDIM;
+    if (A->ncols != B->nrows) return SPGEMM_EDIM;
+    if (!A->row_ptr || !B->row_ptr || (A->nnz > 0 && !A->col_idx)) return SPGEMM_EINVAL;
+    launch_ip_estimate(A->row_ptr, A->col_idx, B->row_ptr, A->nrows, B->ncols, out,
+                       (hipStream_t)stream);
+    return launch_check();
+}
+
 spgemm_status spgemm_sync(spgemm_plan *p) {
     if (!p) return SPGEMM_EINVAL;
     HIP_TRY(hipGetLastError());
@@ -969,24 +997,44 @@ spgemm_status spgemm_selector_transpose(const int32_t *labels, int64_t n, int64_
     return h ? SPGEMM_EINDEX : SPGEMM_OK;
 }
 
+// MCL prune workspace: rowsum (2 m floats), sel (2 m int32), keep (m + 1
+// int64), scan tiles.
 size_t spgemm_mcl_prune_workspace(int64_t m) {
     if (m < 0) return 0;
-    return align256(sizeof(float) * 2 * (size_t)m) + align256(sizeof(int64_t) * (size_t)(m + 1)) +
-           align256(scan_temp_bytes(m));
+    return align256(sizeof(float) * 2 * (size_t)m) + align256(sizeof(int32_t) * 2 * (size_t)m) +
+           align256(sizeof(int64_t) * (size_t)(m + 1)) + align256(scan_temp_bytes(m));
 }
 
+namespace {
+struct MclWs {
+    float *rowsum;
+    int32_t *sel;
+    int64_t *keep;
+    void *tmp;
+};
+MclWs mcl_ws(void *workspace, int64_t m) {
+    char *w = (char *)workspace;
+    MclWs r;
+    r.rowsum = (float *)w;
+    w += align256(sizeof(float) * 2 * (size_t)m);
+    r.sel = (int32_t *)w;
+    w += align256(sizeof(int32_t) * 2 * (size_t)m);
+    r.keep = (int64_t *)w;
+    w += align256(sizeof(int64_t) * (size_t)(m + 1));
+    r.tmp = w;
+    return r;
+}
+}  // namespace
+
 spgemm_status spgemm_mcl_prune_count(int64_t m, const int64_t *row_ptr, const float *values,
-                                     float power, float theta, int64_t *out_row_ptr,
+                                     float power, float theta, int32_t k, int64_t *out_row_ptr,
                                      void *workspace, int64_t *out_nnz, void *stream) {
     if (m < 0 || !row_ptr || !out_row_ptr || !workspace || !out_nnz) return SPGEMM_EINVAL;
-    if (!(power > 0.f) || !(theta >= 0.f)) return SPGEMM_EINVAL;
+    if (!(power > 0.f) || !(theta >= 0.f) || k < 0) return SPGEMM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    char *w = (char *)workspace;
-    float *rowsum = (float *)w;
-    int64_t *keep = (int64_t *)(w + align256(sizeof(float) * 2 * (size_t)m));
-    void *tmp = (char *)keep + align256(sizeof(int64_t) * (size_t)(m + 1));
-    launch_mcl_count(m, row_ptr, values, power, theta, rowsum, keep, st);
-    launch_scan_i64(keep, out_row_ptr, m, tmp, st);
+    const MclWs w = mcl_ws(workspace, m);
+    launch_mcl_count(m, row_ptr, values, power, theta, k, w.rowsum, w.keep, w.sel, st);
+    launch_scan_i64(w.keep, out_row_ptr, m, w.tmp, st);
     ST_TRY(launch_check());
     int64_t nnz = 0;
     HIP_TRY(hipMemcpyAsync(&nnz, out_row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -996,14 +1044,54 @@ spgemm_status spgemm_mcl_prune_count(int64_t m, const int64_t *row_ptr, const fl
 }
 
 spgemm_status spgemm_mcl_prune_write(int64_t m, const int64_t *row_ptr, const int32_t *col_idx,
-                                     const float *values, float power, float theta,
+                                     const float *values, float power, float theta, int32_t k,
                                      const int64_t *out_row_ptr, void *workspace,
                                      int32_t *out_col, float *out_val, void *stream) {
     if (m < 0 || !row_ptr || !out_row_ptr || !workspace) return SPGEMM_EINVAL;
-    if (!(power > 0.f) || !(theta >= 0.f)) return SPGEMM_EINVAL;
-    launch_mcl_write(m, row_ptr, col_idx, values, power, theta, (const float *)workspace,
-                     out_row_ptr, out_col, out_val, (hipStream_t)stream);
+    if (!(power > 0.f) || !(theta >= 0.f) || k < 0) return SPGEMM_EINVAL;
+    const MclWs w = mcl_ws(workspace, m);
+    launch_mcl_write(m, row_ptr, col_idx, values, power, theta, w.rowsum, w.sel, out_row_ptr,
+                     out_col, out_val, (hipStream_t)stream);
     return launch_check();
+}
+
+spgemm_status spgemm_mcl_change(int64_t m, const int64_t *rpt_a, const int32_t *col_a,
+                                const float *val_a, const int64_t *rpt_b, const int32_t *col_b,
+                                const float *val_b, int64_t nnz_a, int64_t nnz_b, double *out,
+                                void *stream) {
+    if (m < 0 || nnz_a < 0 || nnz_b < 0 || !rpt_a || !rpt_b || !out) return SPGEMM_EINVAL;
+    if ((nnz_a > 0 && (!col_a || !val_a)) || (nnz_b > 0 && (!col_b || !val_b)))
+        return SPGEMM_EINVAL;
+    launch_mcl_change(m, rpt_a, col_a, val_a, nnz_a, rpt_b, col_b, val_b, nnz_b, out,
+                      (hipStream_t)stream);
+    return launch_check();
+}
+
+size_t spgemm_components_workspace(void) { return 256; }
+
+spgemm_status spgemm_components(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                                int64_t nnz, int32_t *labels, void *workspace, void *stream,
+                                int32_t *rounds) {
+    if (n < 0 || nnz < 0 || !row_ptr || !labels || !workspace) return SPGEMM_EINVAL;
+    if (nnz > 0 && !col_idx) return SPGEMM_EINVAL;
+    if (n >= (int64_t(1) << 31)) return SPGEMM_EDIM;
+    hipStream_t st = (hipStream_t)stream;
+    int *changed = (int *)workspace;
+    launch_cc_init(n, labels, st);
+    // every round lowers at least one parent, and parents are vertex
+    // indices: the loop ends; the bound only guards against a broken input
+    const int max_rounds = 64 + 2 * 31;
+    int r = 0;
+    for (; r < max_rounds; ++r) {
+        launch_cc_round(n, row_ptr, col_idx, nnz, labels, changed, st);
+        ST_TRY(launch_check());
+        int h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, changed, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (!h) break;
+    }
+    if (rounds) *rounds = r + 1;
+    return r < max_rounds ? SPGEMM_OK : SPGEMM_EINTERNAL;
 }
 
 const char *spgemm_status_string(spgemm_status s) {

@@ -20,6 +20,9 @@ LIB = os.path.join(PKG, "libspgemm.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["k_plan.hip", "k_hash.hip", "k_chunk.hip", "k_apps.hip", "api.cpp"]
+# the device input generator of the served workload: a library of its own
+GEN_SOURCES = ["k_gen.hip"]
+GEN_LIB = os.path.join(PKG, "libspgemm_gen.so")
 ARCH = os.environ.get("SPGEMM_ARCH", "gfx950")
 
 
@@ -49,18 +52,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + GEN_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], GEN_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {GEN_LIB}")
     return LIB
 
 

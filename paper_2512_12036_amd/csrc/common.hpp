@@ -200,6 +200,10 @@ void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc
                            const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
                            bool resolved, int *err, hipStream_t s);
 
+// Algorithm 1 alone, aggregated into out[3] (device): sum of intermediate
+// products, sum of min(ip, ncols), largest row.
+void launch_ip_estimate(const int64_t *rptA, const int32_t *colA, const int64_t *rptB, int64_t m,
+                        int64_t ncols, int64_t *out, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,
                        int64_t *dst, hipStream_t s);
@@ -209,9 +213,17 @@ void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m,
 void launch_selector_t(const int32_t *labels, int64_t n, int64_t k, int64_t *rpt, int32_t *col,
                        float *val, int64_t *work, void *scan_tmp, int *err, hipStream_t s);
 void launch_mcl_count(int64_t m, const int64_t *rpt, const float *val, float power, float theta,
-                      float *rowsum, int64_t *keep, hipStream_t s);
+                      int k, float *rowsum, int64_t *keep, int32_t *sel, hipStream_t s);
 void launch_mcl_write(int64_t m, const int64_t *rpt, const int32_t *col, const float *val,
-                      float power, float theta, const float *rowsum, const int64_t *out_rpt,
-                      int32_t *out_col, float *out_val, hipStream_t s);
+                      float power, float theta, const float *rowsum, const int32_t *sel,
+                      const int64_t *out_rpt, int32_t *out_col, float *out_val, hipStream_t s);
+void launch_mcl_change(int64_t m, const int64_t *rpt_a, const int32_t *col_a, const float *val_a,
+                       int64_t nnz_a, const int64_t *rpt_b, const int32_t *col_b,
+                       const float *val_b, int64_t nnz_b, double *out, hipStream_t s);
+// Connected components (labels = smallest vertex of the component): init,
+// then rounds of hook + compress until a round hooks nothing (*changed = 0).
+void launch_cc_init(int64_t n, int32_t *lab, hipStream_t s);
+void launch_cc_round(int64_t n, const int64_t *rpt, const int32_t *col, int64_t nnz, int32_t *lab,
+                     int *changed, hipStream_t s);
 
 }  // namespace spg

@@ -493,6 +493,51 @@ void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
 }
 
+// Row-size estimation alone (Algorithm 1), aggregated: 16 lanes per row sum
+// the lengths of the B rows the row's A nonzeros name; out[0] += sum of the
+// rows' intermediate products, out[1] += sum of min(ip, ncols) (a bound of
+// nnz(C)), out[2] = max(out[2], ip).  One global atomic per value and block.
+__global__ __launch_bounds__(256) void k_ip_estimate(const int64_t *__restrict__ rptA,
+                                                     const int32_t *__restrict__ colA,
+                                                     const int64_t *__restrict__ rptB, int64_t m,
+                                                     int64_t ncols,
+                                                     unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long acc[3];
+    if (threadIdx.x < 3) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const int seg = threadIdx.x & 15;
+    const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    int64_t ip = 0;
+    if (i < m) {
+        const int64_t a0 = rptA[i], a1 = rptA[i + 1];
+        for (int64_t j = a0 + seg; j < a1; j += 16) {
+            const int c = colA[j];
+            ip += rptB[c + 1] - rptB[c];
+        }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) ip += __shfl_xor(ip, off, 16);
+    if (seg == 0 && i < m && ip > 0) {
+        atomicAdd(&acc[0], (unsigned long long)ip);
+        atomicAdd(&acc[1], (unsigned long long)(ip < ncols ? ip : ncols));
+        atomicMax(&acc[2], (unsigned long long)ip);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && acc[0] > 0) {
+        atomicAdd(&out[0], acc[0]);
+        atomicAdd(&out[1], acc[1]);
+        atomicMax(&out[2], acc[2]);
+    }
+}
+
+void launch_ip_estimate(const int64_t *rptA, const int32_t *colA, const int64_t *rptB, int64_t m,
+                        int64_t ncols, int64_t *out, hipStream_t s) {
+    launch_fill_i64(out, 3, 0, s);
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_ip_estimate, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s, rptA,
+                       colA, rptB, m, ncols, (unsigned long long *)out);
+}
+
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m, int64_t *dst,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_rows_local, dim3((unsigned)((m + 256) / 256)), dim3(256), 0, s, rptv,

@@ -368,19 +368,14 @@ class TorchCsr:
                    self.val.cpu().numpy())
 
 
-def gnn_request_t(seed: int, device="cpu", n: int | None = None, d: float | None = None,
-                  f: int | None = None, rho: float | None = None):
-    """The served aggregation request C = A_hat X for `seed`, built on
-    `device`: A_hat = D^-1/2 (A + I) D^-1/2 of an undirected graph with
-    round(n d / 2) distinct random edges (the first distinct ones of a hashed
-    stream of vertex pairs), X with round(rho f) kept columns (dense, values in
-    (0, 1]) and all other columns zero.  Returns (A_hat, X, (n, d, f, rho))."""
+def gnn_graph_t(seed: int, device="cpu", n: int | None = None, d: float | None = None):
+    """A_hat = D^-1/2 (A + I) D^-1/2 of the served request `seed`, built on
+    `device`: an undirected graph with round(n d / 2) distinct random edges
+    (the first distinct ones of a hashed stream of vertex pairs)."""
     import torch
-    pn, pd, pf, prho = gnn_request_params(seed)
+    pn, pd, _, _ = gnn_request_params(seed)
     n = pn if n is None else n
     d = pd if d is None else d
-    f = pf if f is None else f
-    rho = prho if rho is None else rho
     m_edges = min(int(round(n * d / 2.0)), n * (n - 1) // 2)
     cand = int(m_edges * 1.15) + 64
     hu = _stream(seed, 1, cand, device)
@@ -407,12 +402,125 @@ def gnn_request_t(seed: int, device="cpu", n: int | None = None, d: float | None
     rpt[1:] = torch.cumsum(cnt, 0)
     deg = cnt.to(torch.float64)
     val = (1.0 / torch.sqrt(deg[rows] * deg[cols])).to(torch.float32)
-    a_hat = TorchCsr(n, n, rpt, cols.to(torch.int32), val)
-    nk = max(1, int(round(rho * f)))
+    return TorchCsr(n, n, rpt, cols.to(torch.int32), val)
+
+
+def gnn_features_shape(seed: int, n: int | None = None, f: int | None = None,
+                       rho: float | None = None):
+    """(rows, columns, kept columns) of the served request's X."""
+    pn, _, pf, prho = gnn_request_params(seed)
+    n = pn if n is None else n
+    f = pf if f is None else f
+    rho = prho if rho is None else rho
+    return n, f, max(1, int(round(rho * f)))
+
+
+def gnn_features_t(seed: int, device="cpu", n: int | None = None, f: int | None = None,
+                   rho: float | None = None, structure_only: bool = False):
+    """X of the served request `seed` on `device`: n x f with round(rho f)
+    kept columns, dense with values in (0, 1], every other column zero.  With
+    structure_only, only the row pointers are built (col / val empty)."""
+    import torch
+    n, f, nk = gnn_features_shape(seed, n, f, rho)
+    xrpt = torch.arange(n + 1, dtype=torch.int64, device=device) * nk
+    if structure_only:
+        empty_c = torch.zeros(0, dtype=torch.int32, device=device)
+        return TorchCsr(n, f, xrpt, empty_c, torch.zeros(0, dtype=torch.float32, device=device))
     rank = torch.argsort(_stream(seed, 3, f, device))
     kept = torch.sort(rank[:nk])[0].to(torch.int32)
-    xrpt = torch.arange(n + 1, dtype=torch.int64, device=device) * nk
     xcol = kept.repeat(n)
     xval = _unit_open_low_t(_stream(seed, 4, n * nk, device))
-    x = TorchCsr(n, f, xrpt, xcol, xval)
+    return TorchCsr(n, f, xrpt, xcol, xval)
+
+
+def gnn_request_t(seed: int, device="cpu", n: int | None = None, d: float | None = None,
+                  f: int | None = None, rho: float | None = None):
+    """The served aggregation request C = A_hat X for `seed`, built on
+    `device` (gnn_graph_t and gnn_features_t).  Returns (A_hat, X, (n, d, f,
+    rho))."""
+    pn, pd, pf, prho = gnn_request_params(seed)
+    n = pn if n is None else n
+    d = pd if d is None else d
+    f = pf if f is None else f
+    rho = prho if rho is None else rho
+    a_hat = gnn_graph_t(seed, device, n, d)
+    x = gnn_features_t(seed, device, n, f, rho)
     return a_hat, x, (n, d, f, rho)
+
+
+# ---------------------------------------------------------------------------
+# The same streams with numpy (host metadata), and the served request's
+# features built in one device kernel (libspgemm_gen.so, a generator library
+# of its own); both bit-identical to gnn_features_t.
+
+_M64 = (1 << 64) - 1
+
+
+def _hash64_np(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser on a uint64 array (wrapping arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(_SM_GAMMA & _M64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_SM_M1 & _M64)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_SM_M2 & _M64)
+        return z ^ (z >> np.uint64(31))
+
+
+def _stream_offset(seed: int, tag: int) -> int:
+    return ((((seed & 0xFFFFFFFF) << 24) + (tag << 2) + 1) * 0x100000001) % (1 << 64)
+
+
+def _stream_np(seed: int, tag: int, n: int) -> np.ndarray:
+    """_stream on the host: int64 values with the same bits."""
+    idx = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        x = idx * np.uint64(4) + np.uint64(_stream_offset(seed, tag))
+    return _hash64_np(x).view(np.int64)
+
+
+def gnn_kept_columns(seed: int, f: int, nk: int) -> np.ndarray:
+    """The kept columns of the request's X (sorted int32), as gnn_features_t
+    chooses them: the nk columns of smallest stream value."""
+    rank = np.argsort(_stream_np(seed, 3, f), kind="stable")
+    return np.sort(rank[:nk]).astype(np.int32)
+
+
+_genlib = None
+
+
+def _gen_lib():
+    global _genlib
+    if _genlib is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspgemm_gen.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (the HIP runtime torch holds is the one shared)
+        lib = ctypes.CDLL(path)
+        vp = ctypes.c_void_p
+        lib.gen_gnn_features.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_uint64,
+                                         vp, vp, vp, vp]
+        lib.gen_gnn_features.restype = ctypes.c_int
+        _genlib = lib
+    return _genlib
+
+
+def gnn_features_device(seed: int, kept, n: int, f: int, stream=None) -> TorchCsr:
+    """X of the served request `seed` built by one device kernel on the
+    current (or given) stream; kept: device int32 tensor of its kept columns
+    (gnn_kept_columns).  Equal bit for bit to gnn_features_t."""
+    import ctypes
+    import torch
+    dev = kept.device
+    nk = int(kept.numel())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rpt = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(n * nk, dtype=torch.int32, device=dev)
+    val = torch.empty(n * nk, dtype=torch.float32, device=dev)
+    vp = ctypes.c_void_p
+    rc = _gen_lib().gen_gnn_features(n, nk, vp(kept.data_ptr()), _stream_offset(seed, 4),
+                                     vp(rpt.data_ptr()), vp(col.data_ptr()) if n else None,
+                                     vp(val.data_ptr()) if n else None, vp(st.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"gen_gnn_features failed ({rc})")
+    return TorchCsr(n, f, rpt, col, val)

@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("chunks_per_item", ctypes.c_int32),
                 ("chunk_wgs_per_cu", ctypes.c_int32), ("chunk_threads", ctypes.c_int32),
                 ("sym_chunk_threads", ctypes.c_int32), ("num_rank_cap", ctypes.c_int32),
-                ("chunk_merge", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("chunk_merge", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("item_limit", _I64)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +57,9 @@ EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_
             "spgemm_numeric_batch", "spgemm_sync", "spgemm_get_info", "spgemm_export",
             "spgemm_timing_count", "spgemm_timing", "spgemm_free", "spgemm_status_string",
             "spgemm_selector_transpose_workspace", "spgemm_selector_transpose",
-            "spgemm_mcl_prune_workspace", "spgemm_mcl_prune_count", "spgemm_mcl_prune_write"]
+            "spgemm_mcl_prune_workspace", "spgemm_mcl_prune_count", "spgemm_mcl_prune_write",
+            "spgemm_estimate",
+            "spgemm_mcl_change", "spgemm_components_workspace", "spgemm_components"]
 
 
 class SpgemmError(RuntimeError):
@@ -96,6 +99,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spgemm_numeric_batch.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                          ctypes.POINTER(_VP), ctypes.POINTER(_VP)]
     lib.spgemm_sync.argtypes = [_VP]
+    lib.spgemm_estimate.argtypes = [ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _VP, _VP]
     lib.spgemm_get_info.argtypes = [_VP, ctypes.POINTER(Info)]
     lib.spgemm_export.argtypes = [_VP, ctypes.c_int32, _VP, ctypes.POINTER(_I64)]
     lib.spgemm_timing_count.argtypes = [_VP]
@@ -112,14 +116,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spgemm_selector_transpose.argtypes = [_VP, _I64, _I64, _VP, _VP, _VP, _VP, _VP]
     lib.spgemm_mcl_prune_workspace.argtypes = [_I64]
     lib.spgemm_mcl_prune_workspace.restype = ctypes.c_size_t
-    lib.spgemm_mcl_prune_count.argtypes = [_I64, _VP, _VP, ctypes.c_float, ctypes.c_float, _VP,
-                                           _VP, ctypes.POINTER(_I64), _VP]
+    lib.spgemm_mcl_prune_count.argtypes = [_I64, _VP, _VP, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_int32, _VP, _VP, ctypes.POINTER(_I64), _VP]
     lib.spgemm_mcl_prune_write.argtypes = [_I64, _VP, _VP, _VP, ctypes.c_float, ctypes.c_float,
-                                           _VP, _VP, _VP, _VP, _VP]
+                                           ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]
+    lib.spgemm_mcl_change.argtypes = [_I64, _VP, _VP, _VP, _VP, _VP, _VP, _I64, _I64, _VP, _VP]
+    lib.spgemm_components_workspace.argtypes = []
+    lib.spgemm_components_workspace.restype = ctypes.c_size_t
+    lib.spgemm_components.argtypes = [_I64, _VP, _VP, _I64, _VP, _VP, _VP,
+                                      ctypes.POINTER(ctypes.c_int32)]
     for name in ("spgemm_plan_create", "spgemm_plan_create_batch", "spgemm_symbolic",
                  "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
                  "spgemm_sync", "spgemm_get_info", "spgemm_export", "spgemm_selector_transpose",
-                 "spgemm_mcl_prune_count", "spgemm_mcl_prune_write"):
+                 "spgemm_mcl_prune_count", "spgemm_mcl_prune_write", "spgemm_estimate",
+                 "spgemm_mcl_change", "spgemm_components"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -139,7 +149,7 @@ def default_options() -> Options:
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
                  profile=None, chunks_per_item=None, chunk_wgs_per_cu=None,
                  chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None,
-                 chunk_merge=None, graph=None) -> Options:
+                 chunk_merge=None, graph=None, item_limit=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -167,6 +177,8 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.chunk_merge = int(chunk_merge)
     if graph is not None:
         o.graph = int(graph)
+    if item_limit is not None:
+        o.item_limit = int(item_limit)
     return o
 
 
@@ -404,6 +416,19 @@ def matmul_batch(As, Bs, options: Options | None = None, stream=None):
         plan.free()
 
 
+def estimate_async(A: DeviceCsr, B: DeviceCsr, out, stream=None):
+    """Enqueues Algorithm 1 alone for C = A * B: out (device int64[3]) gets
+    [sum of intermediate products, sum over rows of min(ip, B.ncols), largest
+    row].  Needs only A's structure and B's row pointers (B.col may be
+    empty); no synchronisation."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    da = A.desc(False)
+    db = CsrDesc(B.nrows, B.ncols, B.nnz, B.rpt.data_ptr(), None, None, 0)
+    _check(load().spgemm_estimate(ctypes.byref(da), ctypes.byref(db), _VP(out.data_ptr()),
+                                  _VP(st.cuda_stream)), "spgemm_estimate")
+
+
 def _ptr(t):
     return _VP(t.data_ptr()) if t is not None and t.numel() else None
 
@@ -428,9 +453,11 @@ def selector_transpose(labels, k: int, stream=None) -> DeviceCsr:
     return DeviceCsr(k, n, rpt, col[:n], val[:n], False)
 
 
-def mcl_prune(E: DeviceCsr, power: float = 2.0, theta: float = 1e-4, stream=None) -> DeviceCsr:
+def mcl_prune(E: DeviceCsr, power: float = 2.0, theta: float = 1e-4, k: int = 0,
+              stream=None) -> DeviceCsr:
     """Markov-clustering step after an expansion, on row-stochastic storage:
-    x -> x^power, row-normalise, drop entries below theta, row-normalise."""
+    x -> x^power, row-normalise, drop entries below theta, keep the k largest
+    (k = 0: all), row-normalise."""
     torch = _torch()
     lib = load()
     dev = E.rpt.device
@@ -441,15 +468,50 @@ def mcl_prune(E: DeviceCsr, power: float = 2.0, theta: float = 1e-4, stream=None
     rpt = torch.empty(m + 1, dtype=torch.int64, device=dev)
     nnz = _I64()
     _check(lib.spgemm_mcl_prune_count(m, _VP(E.rpt.data_ptr()), _ptr(E.val), float(power),
-                                      float(theta), _VP(rpt.data_ptr()), _VP(ws.data_ptr()),
-                                      ctypes.byref(nnz), _VP(st.cuda_stream)),
-           "spgemm_mcl_prune_count")
-    k = int(nnz.value)
-    col = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
-    val = torch.empty(max(k, 1), dtype=torch.float32, device=dev)
+                                      float(theta), int(k), _VP(rpt.data_ptr()),
+                                      _VP(ws.data_ptr()), ctypes.byref(nnz),
+                                      _VP(st.cuda_stream)), "spgemm_mcl_prune_count")
+    n = int(nnz.value)
+    col = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
     _check(lib.spgemm_mcl_prune_write(m, _VP(E.rpt.data_ptr()), _ptr(E.col), _ptr(E.val),
-                                      float(power), float(theta), _VP(rpt.data_ptr()),
+                                      float(power), float(theta), int(k), _VP(rpt.data_ptr()),
                                       _VP(ws.data_ptr()), _VP(col.data_ptr()),
                                       _VP(val.data_ptr()), _VP(st.cuda_stream)),
            "spgemm_mcl_prune_write")
-    return DeviceCsr(m, E.ncols, rpt, col[:k], val[:k], E.sorted_rows)
+    return DeviceCsr(m, E.ncols, rpt, col[:n], val[:n], E.sorted_rows)
+
+
+def mcl_change_async(A: DeviceCsr, B: DeviceCsr, out, stream=None):
+    """Enqueues the largest |a_ij - b_ij| over both patterns into out (device
+    float64 tensor of one element)."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(load().spgemm_mcl_change(A.nrows, _VP(A.rpt.data_ptr()), _ptr(A.col), _ptr(A.val),
+                                    _VP(B.rpt.data_ptr()), _ptr(B.col), _ptr(B.val), A.nnz,
+                                    B.nnz, _VP(out.data_ptr()), _VP(st.cuda_stream)),
+           "spgemm_mcl_change")
+
+
+def mcl_change(A: DeviceCsr, B: DeviceCsr) -> float:
+    torch = _torch()
+    out = torch.empty(1, dtype=torch.float64, device=A.rpt.device)
+    mcl_change_async(A, B, out)
+    return float(out.item())
+
+
+def components(M: DeviceCsr, stream=None):
+    """Connected components of the undirected graph of M's pattern (square):
+    (labels int32 device tensor, each the smallest vertex of its component;
+    rounds)."""
+    torch = _torch()
+    lib = load()
+    dev = M.rpt.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    lab = torch.empty(max(M.nrows, 1), dtype=torch.int32, device=dev)
+    ws = torch.empty(int(lib.spgemm_components_workspace()), dtype=torch.uint8, device=dev)
+    rounds = ctypes.c_int32()
+    _check(lib.spgemm_components(M.nrows, _VP(M.rpt.data_ptr()), _ptr(M.col), M.nnz,
+                                 _VP(lab.data_ptr()), _VP(ws.data_ptr()), _VP(st.cuda_stream),
+                                 ctypes.byref(rounds)), "spgemm_components")
+    return lab[:M.nrows], int(rounds.value)

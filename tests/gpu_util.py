@@ -57,19 +57,60 @@ def run_and_compare(a, b, options=None, exact=False, rows=None, b_sorted=None, l
     return c
 
 
-def structure_invariants(c):
+def structure_invariants(c, chunk=1 << 28):
     """Properties of any CSR product output: monotone row pointers and
-    strictly ascending columns inside every row (checked on the GPU)."""
+    strictly ascending columns inside every row (checked on the GPU, in
+    chunks of entries so that outputs of billions of entries fit)."""
     import torch
     rpt = c.rpt
-    assert int(rpt[0]) == 0 and int(rpt[-1]) == c.nnz
+    nnz = c.nnz
+    assert int(rpt[0]) == 0 and int(rpt[-1]) == nnz
     assert bool(torch.all(rpt[1:] >= rpt[:-1]))
-    if c.nnz > 1:
-        col = c.col.long()
-        inner = torch.ones(c.nnz - 1, dtype=torch.bool, device=col.device)
-        ends = rpt[1:-1]
-        ends = ends[(ends > 0) & (ends < c.nnz)]
-        inner[ends - 1] = False
-        d = col[1:] - col[:-1]
-        assert bool(torch.all(d[inner] > 0))
-        assert int(col.min()) >= 0 and int(col.max()) < c.ncols
+    if nnz == 0:
+        return
+    col = c.col
+    assert int(col.min()) >= 0 and int(col.max()) < c.ncols
+    if nnz < 2:
+        return
+    # first entry of every nonempty row
+    start = torch.zeros(nnz, dtype=torch.bool, device=col.device)
+    starts = rpt[:-1][rpt[1:] > rpt[:-1]]
+    start[starts] = True
+    for s in range(0, nnz - 1, chunk):
+        e = min(nnz, s + chunk + 1)
+        d = col[s + 1:e] - col[s:e - 1]          # int32: columns are below 2^31
+        assert bool(torch.all((d > 0) | start[s + 1:e])), f"entries [{s}, {e})"
+    del start
+
+
+def compare_all_rows(a, b, c, exact=False, block_entries=40_000_000, label=""):
+    """Checks EVERY row of the device result c = A*B against the oracle, in
+    blocks of consecutive rows of about block_entries output entries: each
+    block's columns and values are copied to the host, the oracle computes
+    the same rows, and oracle.compare checks them (structure bit for bit,
+    values within the tolerance or exactly)."""
+    import time
+    import torch
+    t0 = time.perf_counter()
+    rpt = c.rpt.cpu().numpy()
+    assert rpt.shape[0] == a.nrows + 1 and int(rpt[0]) == 0
+    m = a.nrows
+    # block bounds: consecutive rows, at most block_entries entries unless one
+    # row alone is larger
+    cuts = [0]
+    while cuts[-1] < m:
+        r0 = cuts[-1]
+        r1 = int(np.searchsorted(rpt, rpt[r0] + block_entries, side="right")) - 1
+        cuts.append(min(m, max(r1, r0 + 1)))
+    for k in range(len(cuts) - 1):
+        r0, r1 = cuts[k], cuts[k + 1]
+        s0, s1 = int(rpt[r0]), int(rpt[r1])
+        col = c.col[s0:s1].cpu().numpy()
+        val = c.val[s0:s1].cpu().numpy()
+        ref = oracle.product(a, b, np.arange(r0, r1, dtype=np.int64))
+        msg = oracle.compare(ref, rpt[r0:r1 + 1] - s0, col, val, exact_values=exact)
+        assert msg is None, f"{label} rows [{r0}, {r1}): {msg}"
+        del col, val, ref
+    torch.cuda.synchronize()
+    log(f"[gpu] {label}: all {m} rows ({int(rpt[-1])} entries) match the oracle in "
+        f"{len(cuts) - 1} blocks, {time.perf_counter() - t0:.1f} s")

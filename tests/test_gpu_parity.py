@@ -168,6 +168,35 @@ def test_heavy_rows_mixed():
     run_and_compare(a, b, options=forced_options(7, 512), label="heavy-chunks")
 
 
+def with_duplicates(m, seed, frac=0.3):
+    """Same matrix plus a second stored copy of a random fraction of its
+    entries (same row and column, its own value), appended at the row's end:
+    duplicate coordinates that the product must sum."""
+    rng = np.random.default_rng(seed)
+    rid = np.repeat(np.arange(m.nrows), np.diff(m.rpt))
+    pick = np.nonzero(rng.random(m.nnz) < frac)[0]
+    rows = np.concatenate([rid, rid[pick]])
+    cols = np.concatenate([m.col, m.col[pick]])
+    vals = np.concatenate([m.val, rng.choice(np.array([-2, -1, 1, 2], np.float32), pick.size)])
+    order = np.argsort(rows, kind="stable")
+    out = gen.from_coo(m.nrows, m.ncols, rows[order], cols[order], vals[order], merge=False)
+    # from_coo sorts by (row, col): the copies sit next to their originals
+    assert out.nnz == m.nnz + pick.size
+    return out
+
+
+@pytest.mark.parametrize("group", [None, 1, 4, 5, 7])
+def test_duplicate_entries_are_summed(group):
+    """Duplicate (row, col) entries in A and in B (valid input per the
+    header: they are summed).  B's rows are then not strictly ascending, so
+    the unsorted-B paths run.  Integer values: compared exactly."""
+    a = with_duplicates(gen.int_valued(gen.rmat(11, 8, seed=71), 72), 73)
+    b = with_duplicates(gen.int_valued(gen.rmat(11, 8, seed=74), 75), 76)
+    opt = None if group is None else forced_options(group, 256 if group == 7 else None)
+    c = run_and_compare(a, b, options=opt, exact=True, b_sorted=False, label=f"dup{group}")
+    structure_invariants(c)
+
+
 def test_cancellation_explicit_zeros():
     a = gen.from_coo(3, 2, [0, 0, 1, 2], [0, 1, 1, 0], np.array([1, 1, 2, 3], np.float32))
     b = gen.from_coo(2, 3, [0, 1, 0, 1], [0, 0, 2, 2], np.array([1, -1, 4, -4], np.float32))
@@ -286,15 +315,18 @@ def test_validation_rejects_malformed():
     da = spgemm.to_device(a)
     bad = spgemm.DeviceCsr(da.nrows, da.ncols, da.rpt.clone(), da.col.clone(), da.val, True)
     bad.col[3] = da.ncols + 5          # column out of range
-    opt = spgemm.make_options(validate=1)
+    opt = spgemm.make_options(validate=2)
     with pytest.raises(spgemm.SpgemmError) as e:
         spgemm.Plan(da, bad, opt)
     assert e.value.code == 3
+    # the cheap level checks row pointers only: the column is not looked at
+    spgemm.Plan(da, bad, spgemm.make_options(validate=1)).free()
     bad2 = spgemm.DeviceCsr(da.nrows, da.ncols, da.rpt.clone(), da.col, da.val, True)
     bad2.rpt[5] = bad2.rpt[6] + 1      # non-monotone row pointers
-    with pytest.raises(spgemm.SpgemmError) as e:
-        spgemm.Plan(bad2, da, opt)
-    assert e.value.code == 3
+    for level in (1, 2):
+        with pytest.raises(spgemm.SpgemmError) as e:
+            spgemm.Plan(bad2, da, spgemm.make_options(validate=level))
+        assert e.value.code == 3
     torch.cuda.synchronize()
 
 

@@ -86,6 +86,11 @@ def test_admission_budget_splits_batches():
     log(f"[gpu] serve budget: {stats}")
     assert stats["requests"] == len(reqs)
     assert stats["batches"] >= len(reqs) // 2
+    assert stats["budget_waits"] + stats["budget_cuts"] >= 1
+    assert stats["peak_admitted_bytes"] <= int(need * 1.5)
+    # the admission bound holds: no batch's exact footprint exceeds it
+    for bound, exact in stats["batch_bytes"]:
+        assert exact <= bound, (exact, bound)
     with pytest.raises(ValueError):
         serve.Server(budget_bytes=need // 2).run(reqs)
 
@@ -102,3 +107,79 @@ def test_poisson_arrivals_and_plain_baseline():
     pstats, pdone = serve.run_plain(reqs)
     log(f"[gpu] plain: {pstats}")
     assert sorted(d.nnz for d in pdone) == sorted(d.nnz for d in done)
+
+
+def test_features_built_on_admission_same_alone_and_in_the_mix():
+    """B built on the device when the request is admitted (and released when
+    it completes): same results as with B resident, and alone."""
+    reqs = []
+    for k in range(10):
+        n, d, f, rho = gen.gnn_request_params(700 + k, n_lo=300, n_hi=4000)
+        reqs += serve.gnn_requests([700 + k], "cuda", features_on_admission=True,
+                                   n=n, d=d, f=f, rho=rho)
+        reqs[-1].rid = k
+    assert all(r.b is None and r.make_b is not None for r in reqs)
+    stats, done = serve.Server(budget_bytes=4 << 30, max_batch=4, n_streams=2,
+                               keep_results=True).run(reqs)
+    assert stats["requests"] == len(reqs)
+    for bound, exact in stats["batch_bytes"]:
+        assert exact <= bound, (exact, bound)
+    for d in done:
+        r = reqs[d.rid]
+        xb = d.b.to_host()
+        ref = oracle.product(r.a.to_host(), xb)
+        k = d.nnz
+        assert oracle.compare(ref, d.rpt.cpu().numpy(), d.col[:k].cpu().numpy(),
+                              d.val[:k].cpu().numpy()) is None
+
+
+@pytest.mark.slow
+def test_config5_full_trace_sampled_results():
+    """The served workload as configured: 4,096 GNN aggregation requests,
+    graphs resident, features built on admission, backlogged under a 200 GB
+    HBM budget that binds (admission waits on it).  Every 64th result is
+    compared with the oracle after the run."""
+    import torch
+    reqs = serve.gnn_requests(range(4096), "cuda", features_on_admission=True, log=log)
+    keep = set(range(0, 4096, 64))
+    budget = 200 * 10 ** 9
+    srv = serve.Server(budget_bytes=budget, max_batch=1024, max_batch_ip=128 << 30, n_streams=4)
+    stats, done = srv.run(reqs, keep_rids=keep)
+    log(f"[gpu] config 5: {dict((k, v) for k, v in stats.items() if k != 'batch_bytes')}")
+    assert stats["requests"] == 4096
+    # the budget binds: batches closed early or admission waiting on it
+    assert stats["budget_waits"] + stats["budget_cuts"] >= 1
+    assert stats["peak_admitted_bytes"] <= budget
+    for bound, exact in stats["batch_bytes"]:
+        assert exact <= bound, (exact, bound)
+    checked = 0
+    for d in done:
+        if d.rid not in keep:
+            assert d.col is None
+            continue
+        r = reqs[d.rid]
+        ref = oracle.product(r.a.to_host(), d.b.to_host())
+        k = d.nnz
+        msg = oracle.compare(ref, d.rpt.cpu().numpy(), d.col[:k].cpu().numpy(),
+                             d.val[:k].cpu().numpy())
+        assert msg is None, f"request {d.rid}: {msg}"
+        checked += 1
+    assert checked == len(keep)
+    log(f"[gpu] config 5: {checked} sampled results match the oracle")
+    del reqs, done
+    torch.cuda.empty_cache()
+
+
+def test_device_feature_generator_matches_host():
+    """The one-kernel feature generator of the served requests equals the
+    reference generator run on the host, bit for bit."""
+    import torch
+    for seed in (3, 900, 4095):
+        n, f, nk = gen.gnn_features_shape(seed, n=5000)
+        kept = torch.from_numpy(gen.gnn_kept_columns(seed, f, nk)).cuda()
+        xd = gen.gnn_features_device(seed, kept, n, f)
+        xh = gen.gnn_features_t(seed, "cpu", n=n)
+        torch.cuda.synchronize()
+        assert torch.equal(xd.rpt.cpu(), xh.rpt)
+        assert torch.equal(xd.col.cpu(), xh.col)
+        assert torch.equal(xd.val.cpu(), xh.val)

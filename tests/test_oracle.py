@@ -260,3 +260,84 @@ def test_compare_detects_mismatches():
     r2 = rpt.copy()
     r2[4] += 1
     assert "row_ptr" in oracle.compare(ref, r2, col, val)
+
+
+def test_compare_row_selection_branch():
+    """compare(rows=...) checks exactly the selected rows of the full arrays:
+    a wrong column, a wrong row length or an out-of-tolerance value inside a
+    selected row is reported; the same mistakes outside the selection are
+    not looked at."""
+    a = gen.rmat(8, 8, seed=31)
+    full = oracle.product(a, a)
+    rpt, col, val = full.rpt.copy(), full.col.copy(), full.val.astype(np.float32)
+    lens = np.diff(rpt)
+    busy = np.nonzero(lens >= 3)[0]
+    sel = np.sort(busy[::3][:20])
+    other = np.setdiff1d(busy, sel)[0]
+    ref = oracle.product(a, a, sel)
+    assert oracle.compare(ref, rpt, col, val, rows=sel) is None
+    # wrong column in the middle of a selected row
+    r = sel[len(sel) // 2]
+    c2 = col.copy()
+    c2[rpt[r] + 1] = c2[rpt[r]]
+    msg = oracle.compare(ref, rpt, c2, val, rows=sel)
+    assert msg is not None and "col_idx" in msg
+    # the same mistake in a row outside the selection is not looked at
+    c3 = col.copy()
+    c3[rpt[other] + 1] = c3[rpt[other]]
+    assert oracle.compare(ref, rpt, c3, val, rows=sel) is None
+    # a selected row one entry shorter (its last entry handed to the next row)
+    r2 = rpt.copy()
+    r2[r + 1] -= 1
+    msg = oracle.compare(ref, r2, col, val, rows=sel)
+    assert msg is not None and "row lengths" in msg
+    # a value outside the tolerance in a selected row
+    v2 = val.copy()
+    j = rpt[r] + 2
+    v2[j] = np.float32(v2[j] + 1e-3 * max(1.0, abs(float(v2[j]))))
+    msg = oracle.compare(ref, rpt, col, v2, rows=sel)
+    assert msg is not None and "tolerance" in msg
+
+
+def test_compare_exact_branch_rejects_one_ulp():
+    """exact_values=True demands equal values: a one-ULP change of a single
+    FP32 entry (well inside the 1e-5 tolerance) is reported, and the same
+    arrays pass the tolerance check."""
+    a = gen.int_valued(gen.rmat(8, 8, seed=32), 5)
+    ref = oracle.product(a, a)
+    rpt, col = ref.rpt.copy(), ref.col.copy()
+    val = ref.val.astype(np.float32)
+    assert np.array_equal(val.astype(np.float64), ref.val)   # integers: exact in FP32
+    assert oracle.compare(ref, rpt, col, val, exact_values=True) is None
+    big = int(np.argmax(np.abs(val)))
+    for direction in (np.float32(np.inf), np.float32(-np.inf)):
+        v2 = val.copy()
+        v2[big] = np.nextafter(v2[big], direction)
+        msg = oracle.compare(ref, rpt, col, v2, exact_values=True)
+        assert msg is not None and "value differs" in msg
+        assert oracle.compare(ref, rpt, col, v2) is None
+    # selected rows with exact values
+    sel = np.array([big_row for big_row in range(a.nrows) if rpt[big_row] <= big < rpt[big_row + 1]])
+    part = oracle.product(a, a, sel)
+    v3 = val.copy()
+    v3[big] = np.nextafter(v3[big], np.float32(np.inf))
+    assert oracle.compare(part, rpt, col, val, rows=sel, exact_values=True) is None
+    assert "value differs" in oracle.compare(part, rpt, col, v3, rows=sel, exact_values=True)
+
+
+def test_compare_contiguous_block_slice():
+    """A block of consecutive rows is checked from slices of the full arrays:
+    row pointers rebased at the block's first entry."""
+    a = gen.rmat(9, 8, seed=33)
+    full = oracle.product(a, a)
+    val = full.val.astype(np.float32)
+    r0, r1 = 100, 260
+    blk = oracle.product(a, a, np.arange(r0, r1))
+    s0, s1 = full.rpt[r0], full.rpt[r1]
+    local = full.rpt[r0:r1 + 1] - s0
+    assert oracle.compare(blk, local, full.col[s0:s1], val[s0:s1]) is None
+    # or the block's pointers into the full arrays
+    assert oracle.compare(blk, full.rpt[r0:r1 + 1], full.col, val) is None
+    c2 = full.col[s0:s1].copy()
+    c2[-1] += 1
+    assert "col_idx" in oracle.compare(blk, local, c2, val[s0:s1])
