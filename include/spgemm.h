@@ -345,6 +345,43 @@ spgemm_status spgemm_components(int64_t n, const int64_t *row_ptr, const int32_t
                                 int64_t nnz, int32_t *labels, void *workspace, void *stream,
                                 int32_t *rounds);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free entry point.  For callers that cannot allocate device
+ * memory: code that must not call hipMalloc / hipFree or an allocator, such
+ * as tight serving loops or harnesses that forbid allocation.
+ * ------------------------------------------------------------------------ */
+
+/* Size in bytes of the library's static device scratch array (64 MiB), the
+ * largest workspace spgemm_multiply_noalloc can use.  Every GPU the library
+ * runs on holds one such array until the process ends. */
+size_t spgemm_noalloc_scratch_bytes(void);
+
+/* C = A * B in one call, with the kernels of spgemm_plan_create +
+ * spgemm_symbolic + spgemm_numeric, but allocating nothing: no hipMalloc,
+ * hipFree, pinned host allocation, allocator callback, HIP event, stream or
+ * graph.  The plan workspace is carved from the static scratch array of the
+ * current device (the stream must belong to it), the host bookkeeping from
+ * static host buffers.
+ *   A, B      device CSR with values (borrowed); opt NULL = defaults
+ *             (profile and graph are ignored).
+ *   c_row_ptr device, A.nrows + 1 entries, caller owned.
+ *   c_col_idx, c_values  device, c_capacity entries each, caller owned.
+ *   nnz_c     host: nnz(C) once the symbolic phase has run, else -1.
+ * Synchronises the stream before returning.  Returns OK when C is complete.
+ * ENOMEM with *nnz_c = -1: the workspace would exceed
+ * spgemm_noalloc_scratch_bytes() (or the static host bookkeeping), nothing
+ * written.  ENOMEM with *nnz_c >= 0: nnz(C) exceeds c_capacity; c_row_ptr is
+ * written, columns and values are not (call again with larger arrays).
+ * Other errors as spgemm_plan_create / spgemm_symbolic / spgemm_sync.
+ * The scratch array is shared by every call on a GPU and keeps the last
+ * call's contents (the kernels clear what must start at zero).  Calls that
+ * overlapped on one GPU would race on it; the library serialises calls
+ * inside a process, and each returns only after its stream has drained. */
+spgemm_status spgemm_multiply_noalloc(const spgemm_csr *A, const spgemm_csr *B,
+                                      const spgemm_options *opt, void *stream,
+                                      int64_t *c_row_ptr, int32_t *c_col_idx, float *c_values,
+                                      int64_t c_capacity, int64_t *nnz_c);
+
 /* Releases a plan and its workspace.  NULL-safe.  Waits for the stream. */
 void spgemm_free(spgemm_plan *p);
 

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory_resource>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -28,6 +30,10 @@ struct HostStats {
 }  // namespace
 
 struct spgemm_plan {
+    // Host containers draw from `mr`: the heap for ordinary plans, a static
+    // host buffer for the allocation-free entry point.
+    explicit spgemm_plan(std::pmr::memory_resource *r = std::pmr::new_delete_resource())
+        : A(r), B(r), hprods(r), hblks(r), hstats(r), nnz_c(r), timed(r), allocs(r) {}
     hipStream_t stream = nullptr;
     spgemm_alloc_fn afn = nullptr;
     spgemm_free_fn ffn = nullptr;
@@ -35,14 +41,14 @@ struct spgemm_plan {
     spgemm_options opt{};
     bool batch = false;
     int nprod = 0;
-    std::vector<spgemm_csr> A, B;
-    std::vector<ProdDev> hprods;
+    std::pmr::vector<spgemm_csr> A, B;
+    std::pmr::vector<ProdDev> hprods;
     ProdDev *dprods = nullptr;
     ProdDev *pinned = nullptr;  // kDescSlots * nprod descriptors
     hipEvent_t desc_ev[kDescSlots] = {};
     bool desc_ev_used[kDescSlots] = {};
     int desc_next = 0;
-    std::vector<RowBlk> hblks;
+    std::pmr::vector<RowBlk> hblks;
     RowBlk *dblks = nullptr;
     int nblk = 0;
     int64_t Mtot = 0;
@@ -94,18 +100,27 @@ struct spgemm_plan {
 
     int64_t sym_start[kGroups + 1] = {};
     int64_t num_start[kGroups + 1] = {};
-    std::vector<HostStats> hstats;
+    std::pmr::vector<HostStats> hstats;
     int64_t ip_total = 0, ip_max = 0, nnz_total = -1;
-    std::vector<int64_t> nnz_c;
+    std::pmr::vector<int64_t> nnz_c;
 
     struct Timed { const char *name; hipEvent_t a, b; };
-    std::vector<Timed> timed;
+    std::pmr::vector<Timed> timed;
 
     int state = 0;  // 1 planned, 2 symbolic done
     hipGraphExec_t num_graph = nullptr;  // the numeric launches, captured (opt.graph)
     bool num_graph_empty = false;        // captured, with nothing to launch
-    std::vector<void *> allocs;
+    std::pmr::vector<void *> allocs;
     size_t ws_bytes = 0;
+
+    // Allocation-free mode: every workspace buffer is carved from this
+    // device arena (the library's static scratch array), host read-backs and
+    // descriptor staging use static host buffers, and no event is created.
+    bool noalloc = false;
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    int64_t *host_read = nullptr;
+    size_t host_read_bytes = 0;
 };
 
 namespace {
@@ -161,6 +176,13 @@ spgemm_status dalloc(spgemm_plan *p, T **out, size_t count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
     bytes = (bytes + 255) & ~size_t(255);
     void *ptr = nullptr;
+    if (p->noalloc) {
+        if (bytes > p->arena_cap - p->arena_used) return SPGEMM_ENOMEM;
+        *out = (T *)(p->arena + p->arena_used);
+        p->arena_used += bytes;
+        p->ws_bytes += bytes;
+        return SPGEMM_OK;
+    }
     if (p->afn) {
         ptr = p->afn(p->actx, bytes, (void *)p->stream);
         if (!ptr) return SPGEMM_ENOMEM;
@@ -194,6 +216,12 @@ spgemm_status scan(spgemm_plan *p, const int64_t *in, int64_t *out, int64_t n) {
 
 spgemm_status ensure_hread(spgemm_plan *p, size_t bytes) {
     if (bytes <= p->hread_bytes) return SPGEMM_OK;
+    if (p->noalloc) {
+        if (bytes > p->host_read_bytes) return SPGEMM_ENOMEM;
+        p->hread = p->host_read;
+        p->hread_bytes = p->host_read_bytes;
+        return SPGEMM_OK;
+    }
     if (p->hread) (void)hipHostFree(p->hread);
     p->hread = nullptr;
     p->hread_bytes = 0;
@@ -206,6 +234,14 @@ spgemm_status ensure_hread(spgemm_plan *p, size_t bytes) {
 
 // Copies the host descriptors to the device through a pinned ring slot.
 spgemm_status upload_descriptors(spgemm_plan *p) {
+    if (p->noalloc) {
+        // one static staging slot: wait until the copy has left it
+        std::memcpy(p->pinned, p->hprods.data(), sizeof(ProdDev) * p->nprod);
+        HIP_TRY(hipMemcpyAsync(p->dprods, p->pinned, sizeof(ProdDev) * p->nprod,
+                               hipMemcpyHostToDevice, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        return SPGEMM_OK;
+    }
     const int slot = p->desc_next;
     p->desc_next = (p->desc_next + 1) % kDescSlots;
     if (p->desc_ev_used[slot]) HIP_TRY(hipEventSynchronize(p->desc_ev[slot]));
@@ -346,7 +382,7 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
     ST_TRY(dalloc(p, &p->stats, nprod));
     ST_TRY(dalloc(p, &p->flags, 3 + nprod));
     ST_TRY(ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk)));
-    {
+    if (!p->noalloc) {
         void *h = nullptr;
         HIP_TRY(hipHostMalloc(&h, sizeof(ProdDev) * nprod * kDescSlots, hipHostMallocDefault));
         p->pinned = (ProdDev *)h;
@@ -791,6 +827,66 @@ spgemm_status numeric_impl(spgemm_plan *p) {
     return SPGEMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free entry point: the workspace lives in `scratch`, a static
+// device array (one copy per GPU, held until the process ends).  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device, fetched once per device.  Host bookkeeping uses static
+// buffers.  Calls are serialised by g_noalloc_mu and synchronise their
+// stream before returning, so a call never finds the array in use.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocScratch = size_t(64) << 20;
+constexpr int kNoallocMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratch];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoallocMaxDevices];
+alignas(64) unsigned char g_noalloc_host[1 << 20];
+alignas(64) int64_t g_noalloc_read[8192];
+ProdDev g_noalloc_desc[1];
+alignas(spgemm_plan) unsigned char g_noalloc_plan[sizeof(spgemm_plan)];
+
+// Device address of the scratch array on the current device (held lock).
+spgemm_status noalloc_scratch(void **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return SPGEMM_EINVAL;
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return SPGEMM_EHIP;
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return SPGEMM_OK;
+}
+
+spgemm_status noalloc_run(spgemm_plan *p, const spgemm_csr *A, const spgemm_csr *B,
+                          int64_t *c_row_ptr, int32_t *c_col_idx, float *c_values,
+                          int64_t c_capacity, int64_t *nnz_c) {
+    ST_TRY(plan_create_impl(p, 1, A, B));
+    ST_TRY(symbolic_impl(p));
+    *nnz_c = p->nnz_total;
+    HIP_TRY(hipMemcpyAsync(c_row_ptr, p->rptv, sizeof(int64_t) * (p->Mtot + 1),
+                           hipMemcpyDeviceToDevice, p->stream));
+    if (p->nnz_total > c_capacity) return SPGEMM_ENOMEM;
+    if (p->nnz_total > 0 && (!c_col_idx || !c_values)) return SPGEMM_EINVAL;
+    p->hprods[0].valA = A->values;
+    p->hprods[0].valB = B->values;
+    p->hprods[0].colC = c_col_idx;
+    p->hprods[0].valC = c_values;
+    ST_TRY(numeric_impl(p));
+    HIP_TRY(hipGetLastError());
+    int f[1];
+    ST_TRY(read_flags(p, f, 1));
+    return f[0] ? SPGEMM_EINTERNAL : SPGEMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1092,6 +1188,48 @@ spgemm_status spgemm_components(int64_t n, const int64_t *row_ptr, const int32_t
     }
     if (rounds) *rounds = r + 1;
     return r < max_rounds ? SPGEMM_OK : SPGEMM_EINTERNAL;
+}
+
+size_t spgemm_noalloc_scratch_bytes(void) { return kNoallocScratch; }
+
+spgemm_status spgemm_multiply_noalloc(const spgemm_csr *A, const spgemm_csr *B,
+                                      const spgemm_options *opt, void *stream,
+                                      int64_t *c_row_ptr, int32_t *c_col_idx, float *c_values,
+                                      int64_t c_capacity, int64_t *nnz_c) {
+    if (!A || !B || !c_row_ptr || !nnz_c || c_capacity < 0) return SPGEMM_EINVAL;
+    *nnz_c = -1;
+    ST_TRY(check_csr(*A, true));
+    ST_TRY(check_csr(*B, true));
+    if (A->ncols != B->nrows) return SPGEMM_EDIM;
+    spgemm_options o;
+    if (opt) o = *opt; else spgemm_default_options(&o);
+    ST_TRY(check_options(o));
+    o.profile = 0;  // no timing events
+    o.graph = 0;    // no graph objects
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    void *arena = nullptr;
+    ST_TRY(noalloc_scratch(&arena));
+    std::pmr::monotonic_buffer_resource mr(g_noalloc_host, sizeof(g_noalloc_host),
+                                           std::pmr::null_memory_resource());
+    spgemm_plan *p = new (g_noalloc_plan) spgemm_plan(&mr);
+    p->noalloc = true;
+    p->arena = (char *)arena;
+    p->arena_cap = kNoallocScratch;
+    p->host_read = g_noalloc_read;
+    p->host_read_bytes = sizeof(g_noalloc_read);
+    p->pinned = g_noalloc_desc;
+    p->stream = (hipStream_t)stream;
+    p->opt = o;
+    spgemm_status s;
+    try {
+        s = noalloc_run(p, A, B, c_row_ptr, c_col_idx, c_values, c_capacity, nnz_c);
+    } catch (...) {
+        s = SPGEMM_ENOMEM;  // the static host buffer of the bookkeeping is full
+    }
+    // nothing may still use the scratch array when the next call starts
+    if (hipStreamSynchronize(p->stream) != hipSuccess && s == SPGEMM_OK) s = SPGEMM_EHIP;
+    p->~spgemm_plan();
+    return s;
 }
 
 const char *spgemm_status_string(spgemm_status s) {

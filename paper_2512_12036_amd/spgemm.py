@@ -58,7 +58,7 @@ EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_
             "spgemm_timing_count", "spgemm_timing", "spgemm_free", "spgemm_status_string",
             "spgemm_selector_transpose_workspace", "spgemm_selector_transpose",
             "spgemm_mcl_prune_workspace", "spgemm_mcl_prune_count", "spgemm_mcl_prune_write",
-            "spgemm_estimate",
+            "spgemm_estimate", "spgemm_noalloc_scratch_bytes", "spgemm_multiply_noalloc",
             "spgemm_mcl_change", "spgemm_components_workspace", "spgemm_components"]
 
 
@@ -100,6 +100,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(_VP), ctypes.POINTER(_VP)]
     lib.spgemm_sync.argtypes = [_VP]
     lib.spgemm_estimate.argtypes = [ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc), _VP, _VP]
+    lib.spgemm_noalloc_scratch_bytes.argtypes = []
+    lib.spgemm_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    lib.spgemm_multiply_noalloc.argtypes = [ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc),
+                                            ctypes.POINTER(Options), _VP, _VP, _VP, _VP, _I64,
+                                            ctypes.POINTER(_I64)]
     lib.spgemm_get_info.argtypes = [_VP, ctypes.POINTER(Info)]
     lib.spgemm_export.argtypes = [_VP, ctypes.c_int32, _VP, ctypes.POINTER(_I64)]
     lib.spgemm_timing_count.argtypes = [_VP]
@@ -129,7 +134,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
                  "spgemm_sync", "spgemm_get_info", "spgemm_export", "spgemm_selector_transpose",
                  "spgemm_mcl_prune_count", "spgemm_mcl_prune_write", "spgemm_estimate",
-                 "spgemm_mcl_change", "spgemm_components"):
+                 "spgemm_multiply_noalloc", "spgemm_mcl_change", "spgemm_components"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -427,6 +432,23 @@ def estimate_async(A: DeviceCsr, B: DeviceCsr, out, stream=None):
     db = CsrDesc(B.nrows, B.ncols, B.nnz, B.rpt.data_ptr(), None, None, 0)
     _check(load().spgemm_estimate(ctypes.byref(da), ctypes.byref(db), _VP(out.data_ptr()),
                                   _VP(st.cuda_stream)), "spgemm_estimate")
+
+
+def multiply_noalloc(A: DeviceCsr, B: DeviceCsr, c_rpt, c_col, c_val,
+                     options: Options | None = None, stream=None):
+    """spgemm_multiply_noalloc into caller tensors (c_rpt int64 [A.nrows + 1],
+    c_col int32 / c_val float32 of equal capacity).  Returns (status code,
+    nnz(C) or -1); does not raise on ENOMEM so that callers can retry."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream(c_rpt.device)
+    nnz = _I64(-1)
+    cap = int(c_col.numel())
+    code = load().spgemm_multiply_noalloc(
+        ctypes.byref(A.desc()), ctypes.byref(B.desc()),
+        ctypes.byref(options) if options is not None else None, _VP(st.cuda_stream),
+        _VP(c_rpt.data_ptr()), _VP(c_col.data_ptr()) if cap else None,
+        _VP(c_val.data_ptr()) if cap else None, cap, ctypes.byref(nnz))
+    return int(code), int(nnz.value)
 
 
 def _ptr(t):
