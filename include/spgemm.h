@@ -346,6 +346,61 @@ spgemm_status spgemm_components(int64_t n, const int64_t *row_ptr, const int32_t
                                 int32_t *rounds);
 
 /* ------------------------------------------------------------------------
+ * The GNN layer with a pruning layer (paper Section V-C): forward
+ * X_l = A TopK(X_{l-1}, k) W_l (Eq. 1-2), the product A TopK(X) being the
+ * SpGEMM of this library, and backward
+ * dL/dX_{l-1} = M_k (.) (A^T (dL/dX_l) W_l^T) (Eq. 3).  Dense matrices are
+ * row-major FP32 device arrays.
+ * ------------------------------------------------------------------------ */
+
+/* TopK(X, k) per row (per sample): the k entries of largest magnitude of
+ * every row of the dense n x f matrix X (leading dimension ldx >= f), equal
+ * magnitudes in column order, as compressed rows with ascending columns:
+ * row_ptr (n + 1 int64), col_idx and values (n * min(k, f) each), all
+ * device, caller owned.  The pattern is the mask M_k of Eq. 2.  Enqueued on
+ * `stream`.  EINVAL for NULL pointers, negative sizes or ldx < f. */
+spgemm_status spgemm_topk_rows(int64_t n, int64_t f, const float *x, int64_t ldx, int32_t k,
+                               int64_t *row_ptr, int32_t *col_idx, float *values, void *stream);
+
+/* Writes the m x n CSR matrix into the dense row-major array `dense`
+ * (leading dimension ldd >= n; every other entry set to 0).  Enqueued. */
+spgemm_status spgemm_csr_to_dense(int64_t m, int64_t n, const int64_t *row_ptr,
+                                  const int32_t *col_idx, const float *values, float *dense,
+                                  int64_t ldd, void *stream);
+
+/* Dense C = op(A) op(B) in FP32 on the matrix cores: op(A) is M x K with
+ * element (i, k) at A[i * a_row + k * a_col], op(B) is K x N with element
+ * (k, j) at B[k * b_row + j * b_col] (so a transpose is a swap of the two
+ * strides), C is M x N at C[i * ldc + j] (ldc >= N), overwritten.  Products
+ * and sums in FP32.  Enqueued.  EINVAL for NULL pointers, negative sizes or
+ * ldc < N; EDIM for M >= 64 * 65535. */
+spgemm_status spgemm_gemm_f32(int64_t M, int64_t N, int64_t K, const float *A, int64_t a_row,
+                              int64_t a_col, const float *B, int64_t b_row, int64_t b_col,
+                              float *C, int64_t ldc, void *stream);
+
+/* The backward product of Eq. 3 evaluated where the mask keeps an entry:
+ * for every stored entry e = (i, c) of the mask (an m-row CSR pattern:
+ * rpt_mask, col_mask), out[e] = sum over the stored entries (i, r, a) of
+ * row i of A^T (rpt_t, col_t, val_t) of a * dense[r * ldd + c].  out has
+ * the mask's nnz entries (device).  FP32.  Enqueued. */
+spgemm_status spgemm_masked_spmm(int64_t m, const int64_t *rpt_t, const int32_t *col_t,
+                                 const float *val_t, const float *dense, int64_t ldd,
+                                 const int64_t *rpt_mask, const int32_t *col_mask, float *out,
+                                 void *stream);
+
+/* CSR transpose of the m x n matrix (nnz entries): rpt_t (n + 1), col_t and
+ * val_t (nnz; val_t may be NULL when values is NULL), device, caller owned.
+ * Entries of an output row are in no fixed order (the result is not
+ * SPGEMM_ROWS_SORTED).  workspace: spgemm_transpose_workspace(n) bytes of
+ * device memory.  Enqueued.  EINVAL for NULL pointers or negative sizes,
+ * EDIM for m >= 2^31. */
+size_t spgemm_transpose_workspace(int64_t ncols);
+spgemm_status spgemm_transpose(int64_t m, int64_t n, const int64_t *row_ptr,
+                               const int32_t *col_idx, const float *values, int64_t nnz,
+                               int64_t *rpt_t, int32_t *col_t, float *val_t, void *workspace,
+                               void *stream);
+
+/* ------------------------------------------------------------------------
  * Allocation-free entry point.  For callers that cannot allocate device
  * memory: code that must not call hipMalloc / hipFree or an allocator, such
  * as tight serving loops or harnesses that forbid allocation.

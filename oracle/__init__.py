@@ -17,6 +17,8 @@ path (``paper_2512_12036_amd``) never does, and shares no code with it.
 * ``mcl_prune_topk``, ``mcl_change`` and ``components`` are the top-k
   pruning, the convergence measure and the cluster interpretation of
   Algorithm 6.
+* ``topk_rows``, ``gnn_forward`` and ``gnn_backward`` are the GNN layer
+  with a pruning layer (paper Section V-C, Eq. 1-3).
 * ``transpose`` builds S^T for graph contraction (paper Algorithm 7).
 
 Every function here is pinned by ``tests/test_oracle*.py`` against closed
@@ -294,6 +296,64 @@ def components(n: int, rpt, col) -> np.ndarray:
                         nxt.append(w)
             frontier = nxt
     return label.astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# GNN layer with a pruning layer (paper Section V-C, Eq. 1-3), in FP64.
+# --------------------------------------------------------------------------
+def topk_rows(x, k: int):
+    """TopK(X, k) per row of the dense matrix x: the k entries of largest
+    magnitude (equal magnitudes: lower column first), as (rpt, col, val) with
+    ascending columns; the pattern is the mask M_k of Eq. 2."""
+    x = np.asarray(x)
+    n, f = x.shape
+    kk = min(k, f)
+    cols = np.zeros((n, kk), dtype=np.int32)
+    for i in range(n):
+        order = sorted(range(f), key=lambda j: (-abs(float(x[i, j])), j))[:kk]
+        cols[i] = np.sort(order)
+    rpt = np.arange(n + 1, dtype=np.int64) * kk
+    col = cols.reshape(-1)
+    val = x[np.repeat(np.arange(n), kk), col]
+    return rpt, col, val
+
+
+def gnn_forward(a, x, w, k: int):
+    """X_l = A TopK(X, k) W (Eq. 1-2) with the sparse product by the
+    definition (``product``) and the dense one by numpy, in FP64.  Returns
+    (X_l, TopK(X) as a Csr with the input's precision, H = A TopK(X) as a
+    dense FP64 array, |A| |TopK(X)| for the bounds)."""
+    from paper_2512_12036_amd import gen
+    rpt, col, val = topk_rows(x, k)
+    xk = gen.Csr(x.shape[0], x.shape[1], rpt, col, val.astype(np.float32))
+    h = product(a, xk)
+    hd = np.zeros((a.nrows, x.shape[1]))
+    hb = np.zeros((a.nrows, x.shape[1]))
+    rid = np.repeat(np.arange(a.nrows), np.diff(h.rpt))
+    hd[rid, h.col] = h.val
+    hb[rid, h.col] = h.absb
+    return hd @ np.asarray(w, dtype=np.float64), xk, hd, hb
+
+
+def gnn_backward(a, g, w, xk, hd):
+    """Eq. 3: dL/dX = M_k (.) (A^T (G W^T)), on the mask's pattern (values in
+    xk's order), and dL/dW = H^T G, in FP64.  Also the bounds sum |.||.| of
+    every result entry."""
+    from scipy.sparse import csr_matrix
+    g = np.asarray(g, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    d = g @ w.T
+    db = np.abs(g) @ np.abs(w.T)
+    at = csr_matrix((np.asarray(a.val, dtype=np.float64), a.col, a.rpt),
+                    shape=(a.nrows, a.ncols)).T.tocsr()
+    full = at @ d
+    fullb = abs(at) @ db
+    rid = np.repeat(np.arange(xk.nrows), np.diff(xk.rpt))
+    dx = np.asarray(full)[rid, xk.col]
+    dxb = np.asarray(fullb)[rid, xk.col]
+    dw = hd.T @ g
+    dwb = np.abs(hd).T @ np.abs(g)
+    return dx, dxb, dw, dwb
 
 
 def transpose(nrows: int, ncols: int, rpt, col, val):

@@ -1190,6 +1190,66 @@ spgemm_status spgemm_components(int64_t n, const int64_t *row_ptr, const int32_t
     return r < max_rounds ? SPGEMM_OK : SPGEMM_EINTERNAL;
 }
 
+spgemm_status spgemm_topk_rows(int64_t n, int64_t f, const float *x, int64_t ldx, int32_t k,
+                               int64_t *row_ptr, int32_t *col_idx, float *values, void *stream) {
+    if (n < 0 || f < 0 || k < 0 || ldx < f || !row_ptr) return SPGEMM_EINVAL;
+    const int64_t kk = std::min<int64_t>(k, f);
+    if (n > 0 && kk > 0 && (!x || !col_idx || !values)) return SPGEMM_EINVAL;
+    if (f >= (int64_t(1) << 31) || n >= (int64_t(1) << 31)) return SPGEMM_EDIM;
+    hipStream_t st = (hipStream_t)stream;
+    launch_rows_uniform(row_ptr, n, kk, st);
+    launch_topk_rows(n, f, x, ldx, (int)kk, col_idx, values, st);
+    return launch_check();
+}
+
+spgemm_status spgemm_csr_to_dense(int64_t m, int64_t n, const int64_t *row_ptr,
+                                  const int32_t *col_idx, const float *values, float *dense,
+                                  int64_t ldd, void *stream) {
+    if (m < 0 || n < 0 || ldd < n || !row_ptr || (m > 0 && n > 0 && !dense)) return SPGEMM_EINVAL;
+    launch_csr_to_dense(m, n, row_ptr, col_idx, values, dense, ldd, (hipStream_t)stream);
+    return launch_check();
+}
+
+spgemm_status spgemm_gemm_f32(int64_t M, int64_t N, int64_t K, const float *A, int64_t a_row,
+                              int64_t a_col, const float *B, int64_t b_row, int64_t b_col,
+                              float *C, int64_t ldc, void *stream) {
+    if (M < 0 || N < 0 || K < 0 || ldc < N) return SPGEMM_EINVAL;
+    if (M > 0 && N > 0 && (!C || (K > 0 && (!A || !B)))) return SPGEMM_EINVAL;
+    if (M / 64 >= 65535) return SPGEMM_EDIM;
+    launch_gemm_f32(M, N, K, A, a_row, a_col, B, b_row, b_col, C, ldc, (hipStream_t)stream);
+    return launch_check();
+}
+
+spgemm_status spgemm_masked_spmm(int64_t m, const int64_t *rpt_t, const int32_t *col_t,
+                                 const float *val_t, const float *dense, int64_t ldd,
+                                 const int64_t *rpt_mask, const int32_t *col_mask, float *out,
+                                 void *stream) {
+    if (m < 0 || !rpt_t || !rpt_mask) return SPGEMM_EINVAL;
+    launch_masked_spmm(m, rpt_t, col_t, val_t, dense, ldd, rpt_mask, col_mask, out,
+                       (hipStream_t)stream);
+    return launch_check();
+}
+
+size_t spgemm_transpose_workspace(int64_t ncols) {
+    if (ncols < 0) return 0;
+    return align256(sizeof(int64_t) * (size_t)(ncols + 1)) + align256(scan_temp_bytes(ncols));
+}
+
+spgemm_status spgemm_transpose(int64_t m, int64_t n, const int64_t *row_ptr,
+                               const int32_t *col_idx, const float *values, int64_t nnz,
+                               int64_t *rpt_t, int32_t *col_t, float *val_t, void *workspace,
+                               void *stream) {
+    if (m < 0 || n < 0 || nnz < 0 || !row_ptr || !rpt_t || !workspace) return SPGEMM_EINVAL;
+    if (nnz > 0 && (!col_idx || !col_t || (values && !val_t))) return SPGEMM_EINVAL;
+    if (m >= (int64_t(1) << 31)) return SPGEMM_EDIM;
+    char *w = (char *)workspace;
+    int64_t *work = (int64_t *)w;
+    void *tmp = w + align256(sizeof(int64_t) * (size_t)(n + 1));
+    launch_transpose(m, n, row_ptr, col_idx, values, nnz, rpt_t, col_t, val_t, work, tmp,
+                     (hipStream_t)stream);
+    return launch_check();
+}
+
 size_t spgemm_noalloc_scratch_bytes(void) { return kNoallocScratch; }
 
 spgemm_status spgemm_multiply_noalloc(const spgemm_csr *A, const spgemm_csr *B,

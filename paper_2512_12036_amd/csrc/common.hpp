@@ -226,4 +226,20 @@ void launch_cc_init(int64_t n, int32_t *lab, hipStream_t s);
 void launch_cc_round(int64_t n, const int64_t *rpt, const int32_t *col, int64_t nnz, int32_t *lab,
                      int *changed, hipStream_t s);
 
+// GNN layer pieces (k_gnn.hip).
+void launch_rows_uniform(int64_t *rpt, int64_t n, int64_t k, hipStream_t s);
+void launch_topk_rows(int64_t n, int64_t f, const float *x, int64_t ldx, int k, int32_t *col,
+                      float *val, hipStream_t s);
+void launch_csr_to_dense(int64_t m, int64_t n, const int64_t *rpt, const int32_t *col,
+                         const float *val, float *d, int64_t ldd, hipStream_t s);
+void launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float *A, int64_t sar, int64_t sac,
+                     const float *B, int64_t sbr, int64_t sbc, float *C, int64_t ldc,
+                     hipStream_t s);
+void launch_masked_spmm(int64_t m, const int64_t *rpt_t, const int32_t *col_t, const float *val_t,
+                        const float *d, int64_t ldd, const int64_t *rpt_m, const int32_t *col_m,
+                        float *out, hipStream_t s);
+void launch_transpose(int64_t m, int64_t n, const int64_t *rpt, const int32_t *col,
+                      const float *val, int64_t nnz, int64_t *rpt_t, int32_t *col_t,
+                      float *val_t, int64_t *work, void *scan_tmp, hipStream_t s);
+
 }  // namespace spg

@@ -59,7 +59,9 @@ EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_
             "spgemm_selector_transpose_workspace", "spgemm_selector_transpose",
             "spgemm_mcl_prune_workspace", "spgemm_mcl_prune_count", "spgemm_mcl_prune_write",
             "spgemm_estimate", "spgemm_noalloc_scratch_bytes", "spgemm_multiply_noalloc",
-            "spgemm_mcl_change", "spgemm_components_workspace", "spgemm_components"]
+            "spgemm_mcl_change", "spgemm_components_workspace", "spgemm_components",
+            "spgemm_topk_rows", "spgemm_csr_to_dense", "spgemm_gemm_f32", "spgemm_masked_spmm",
+            "spgemm_transpose_workspace", "spgemm_transpose"]
 
 
 class SpgemmError(RuntimeError):
@@ -130,6 +132,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spgemm_components_workspace.restype = ctypes.c_size_t
     lib.spgemm_components.argtypes = [_I64, _VP, _VP, _I64, _VP, _VP, _VP,
                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.spgemm_topk_rows.argtypes = [_I64, _I64, _VP, _I64, ctypes.c_int32, _VP, _VP, _VP, _VP]
+    lib.spgemm_csr_to_dense.argtypes = [_I64, _I64, _VP, _VP, _VP, _VP, _I64, _VP]
+    lib.spgemm_gemm_f32.argtypes = [_I64, _I64, _I64, _VP, _I64, _I64, _VP, _I64, _I64, _VP, _I64,
+                                    _VP]
+    lib.spgemm_masked_spmm.argtypes = [_I64, _VP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP]
+    lib.spgemm_transpose_workspace.argtypes = [_I64]
+    lib.spgemm_transpose_workspace.restype = ctypes.c_size_t
+    lib.spgemm_transpose.argtypes = [_I64, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]
     for name in ("spgemm_plan_create", "spgemm_plan_create_batch", "spgemm_symbolic",
                  "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
                  "spgemm_sync", "spgemm_get_info", "spgemm_export", "spgemm_selector_transpose",
@@ -537,3 +547,83 @@ def components(M: DeviceCsr, stream=None):
                                  _VP(lab.data_ptr()), _VP(ws.data_ptr()), _VP(st.cuda_stream),
                                  ctypes.byref(rounds)), "spgemm_components")
     return lab[:M.nrows], int(rounds.value)
+
+
+# ---------------------------------------------------------------------------
+# GNN layer pieces (paper Section V-C)
+# ---------------------------------------------------------------------------
+def _st(dev, stream):
+    torch = _torch()
+    return _VP((stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream)
+
+
+def topk_rows(x, k: int, stream=None) -> DeviceCsr:
+    """TopK(X, k) per row of a dense row-major float32 device tensor, as CSR
+    with ascending columns (its pattern is the mask M_k)."""
+    torch = _torch()
+    n, f = x.shape
+    kk = min(int(k), f)
+    dev = x.device
+    rpt = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(n * kk, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(n * kk, 1), dtype=torch.float32, device=dev)
+    _check(load().spgemm_topk_rows(n, f, _VP(x.data_ptr()) if x.numel() else None, x.stride(0),
+                                   int(k), _VP(rpt.data_ptr()), _VP(col.data_ptr()),
+                                   _VP(val.data_ptr()), _st(dev, stream)), "spgemm_topk_rows")
+    return DeviceCsr(n, f, rpt, col[:n * kk], val[:n * kk], True)
+
+
+def to_dense(m: DeviceCsr, stream=None):
+    torch = _torch()
+    d = torch.empty((m.nrows, m.ncols), dtype=torch.float32, device=m.rpt.device)
+    _check(load().spgemm_csr_to_dense(m.nrows, m.ncols, _VP(m.rpt.data_ptr()), _ptr(m.col),
+                                      _ptr(m.val), _VP(d.data_ptr()) if d.numel() else None,
+                                      max(m.ncols, 0), _st(m.rpt.device, stream)),
+           "spgemm_csr_to_dense")
+    return d
+
+
+def gemm(a, b, stream=None):
+    """a @ b for 2-D float32 device tensors (any strides, e.g. transposed
+    views) on the matrix cores; returns a new row-major tensor."""
+    torch = _torch()
+    M, K = a.shape
+    K2, N = b.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    c = torch.empty((M, N), dtype=torch.float32, device=a.device)
+    _check(load().spgemm_gemm_f32(M, N, K, _VP(a.data_ptr()) if a.numel() else None,
+                                  a.stride(0), a.stride(1),
+                                  _VP(b.data_ptr()) if b.numel() else None, b.stride(0),
+                                  b.stride(1), _VP(c.data_ptr()) if c.numel() else None, N,
+                                  _st(a.device, stream)), "spgemm_gemm_f32")
+    return c
+
+
+def masked_spmm(at: DeviceCsr, d, mask: DeviceCsr, stream=None):
+    """Values, on mask's pattern, of (A^T d) given at = A^T (CSR) and the
+    dense row-major d."""
+    torch = _torch()
+    out = torch.empty(max(mask.nnz, 1), dtype=torch.float32, device=d.device)
+    _check(load().spgemm_masked_spmm(at.nrows, _VP(at.rpt.data_ptr()), _ptr(at.col),
+                                     _ptr(at.val), _VP(d.data_ptr()) if d.numel() else None,
+                                     d.stride(0), _VP(mask.rpt.data_ptr()), _ptr(mask.col),
+                                     _VP(out.data_ptr()), _st(d.device, stream)),
+           "spgemm_masked_spmm")
+    return out[:mask.nnz]
+
+
+def transpose(m: DeviceCsr, stream=None) -> DeviceCsr:
+    """CSR transpose on the device (rows of the result not column-sorted)."""
+    torch = _torch()
+    lib = load()
+    dev = m.rpt.device
+    rpt = torch.empty(m.ncols + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(m.nnz, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(m.nnz, 1), dtype=torch.float32, device=dev)
+    ws = torch.empty(int(lib.spgemm_transpose_workspace(m.ncols)), dtype=torch.uint8, device=dev)
+    _check(lib.spgemm_transpose(m.nrows, m.ncols, _VP(m.rpt.data_ptr()), _ptr(m.col),
+                                _ptr(m.val), m.nnz, _VP(rpt.data_ptr()), _VP(col.data_ptr()),
+                                _VP(val.data_ptr()), _VP(ws.data_ptr()), _st(dev, stream)),
+           "spgemm_transpose")
+    return DeviceCsr(m.ncols, m.nrows, rpt, col[:m.nnz], val[:m.nnz], False)

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "spgemm.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(spgemm_[a-z_]+)\s*\(", text)
+    names = re.findall(r"\b(spgemm_[a-z0-9_]+)\s*\(", text)
     return sorted(set(n for n in names if not n.endswith("_fn")))
 
 

@@ -1,0 +1,132 @@
+"""The GNN layer with a pruning layer (paper Section V-C, Eq. 1-3) on the
+GPU against the oracle, step by step (teacher-forced: every oracle step
+starts from the GPU's previous result), and its pieces: the TopK mask (bit
+for bit), the FP32 GEMM on the matrix cores (bit for bit on integers,
+within the FP32 summation bound otherwise, transposed operands included),
+the masked backward product and the CSR transpose."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_12036_amd import gen, gnn, spgemm
+
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24  # FP32 unit roundoff
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    spgemm.load()
+
+
+def csr_host(m):
+    return m.to_host()
+
+
+@pytest.mark.parametrize("n,f,k", [(1000, 37, 5), (257, 512, 64), (300, 90, 90), (50, 8, 20),
+                                   (2000, 300, 1)])
+def test_topk_rows_bit_exact(n, f, k):
+    import torch
+    rng = np.random.default_rng(n + f)
+    x = (np.round(rng.normal(size=(n, f)) * 3) / 3).astype(np.float32)   # many ties
+    xt = torch.from_numpy(x).cuda()
+    g = csr_host(spgemm.topk_rows(xt, k))
+    rpt, col, val = oracle.topk_rows(x, k)
+    assert np.array_equal(g.rpt, rpt) and np.array_equal(g.col, col)
+    assert np.array_equal(g.val, val)
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb", [(300, 77, 129, False, False), (64, 64, 16, False, False),
+                                         (1, 5, 3, False, False), (513, 200, 257, True, False),
+                                         (129, 300, 70, False, True), (97, 65, 33, True, True)])
+def test_gemm_f32(M, N, K, ta, tb):
+    import torch
+    rng = np.random.default_rng(M * N + K)
+    a = rng.normal(size=(K, M) if ta else (M, K)).astype(np.float32)
+    b = rng.normal(size=(N, K) if tb else (K, N)).astype(np.float32)
+    at = torch.from_numpy(a).cuda()
+    bt = torch.from_numpy(b).cuda()
+    av = at.t() if ta else at
+    bv = bt.t() if tb else bt
+    c = spgemm.gemm(av, bv).cpu().numpy().astype(np.float64)
+    a64 = (a.T if ta else a).astype(np.float64)
+    b64 = (b.T if tb else b).astype(np.float64)
+    want = a64 @ b64
+    bound = np.abs(a64) @ np.abs(b64)
+    assert np.all(np.abs(c - want) <= K * U * bound + 1e-30)
+    # integers: every product and partial sum exact in FP32
+    ai = rng.integers(-4, 5, size=a.shape).astype(np.float32)
+    bi = rng.integers(-4, 5, size=b.shape).astype(np.float32)
+    ci = spgemm.gemm(torch.from_numpy(ai).cuda().t() if ta else torch.from_numpy(ai).cuda(),
+                     torch.from_numpy(bi).cuda().t() if tb else torch.from_numpy(bi).cuda())
+    wi = (ai.T if ta else ai).astype(np.float64) @ (bi.T if tb else bi).astype(np.float64)
+    assert np.array_equal(ci.cpu().numpy().astype(np.float64), wi)
+
+
+def test_transpose_matches_oracle():
+    a = gen.rmat(12, 8, seed=51)
+    t = csr_host(spgemm.transpose(spgemm.to_device(a)))
+    trpt, tcol, tval = oracle.transpose(a.nrows, a.ncols, a.rpt, a.col, a.val)
+    assert np.array_equal(t.rpt, trpt)
+    for i in range(t.nrows):
+        s, e = t.rpt[i], t.rpt[i + 1]
+        o = np.argsort(t.col[s:e])
+        assert np.array_equal(t.col[s:e][o], tcol[s:e]) and np.array_equal(t.val[s:e][o],
+                                                                          tval[s:e])
+
+
+def problem(seed, n, f, fo):
+    """A_hat of the served generator (n nodes), X with ReLU-like rows, W."""
+    import torch
+    a = gen.gnn_graph_t(seed, "cpu", n=n)
+    a = gen.Csr(a.nrows, a.ncols, a.rpt.numpy(), a.col.numpy(), a.val.numpy())
+    rng = np.random.default_rng(seed)
+    x = np.maximum(rng.normal(size=(n, f)), 0.0).astype(np.float32)
+    w = (rng.normal(size=(f, fo)) / np.sqrt(f)).astype(np.float32)
+    g = rng.normal(size=(n, fo)).astype(np.float32)
+    return a, x, w, g
+
+
+@pytest.mark.parametrize("n,f,fo,k", [(3000, 64, 32, 8), (20000, 256, 128, 32)])
+def test_layer_teacher_forced(n, f, fo, k):
+    import torch
+    a, x, w, g = problem(n + f, n, f, fo)
+    da = spgemm.to_device(a)
+    xt, wt, gt = (torch.from_numpy(v).cuda() for v in (x, w, g))
+    out, cache = gnn.layer_forward(da, xt, wt, k)
+    xk_d, hd_d = cache
+    xk = csr_host(xk_d)
+    # mask: bit for bit
+    rpt, col, val = oracle.topk_rows(x, k)
+    assert np.array_equal(xk.col, col) and np.array_equal(xk.val, val)
+    # H = A TopK(X): the SpGEMM against the oracle's product
+    ref = oracle.product(a, xk)
+    h = hd_d.cpu().numpy().astype(np.float64)
+    rid = np.repeat(np.arange(a.nrows), np.diff(ref.rpt))
+    hr = np.zeros_like(h)
+    hr[rid, ref.col] = ref.val
+    hb = np.zeros_like(h)
+    hb[rid, ref.col] = ref.absb
+    assert np.all(np.abs(h - hr) <= 1e-5 * hb + 1e-30)
+    # X_l = H W from the GPU's H
+    o = out.cpu().numpy().astype(np.float64)
+    want = h @ w.astype(np.float64)
+    bound = np.abs(h) @ np.abs(w.astype(np.float64))
+    assert np.all(np.abs(o - want) <= f * U * bound + 1e-30)
+    # backward, symmetric A_hat: A^T = A
+    dx_d, dw_d = gnn.layer_backward(da, gt, wt, cache)
+    dx, dxb, dw, dwb = oracle.gnn_backward(a, g.astype(np.float64), w.astype(np.float64), xk, h)
+    gx = dx_d.val.cpu().numpy().astype(np.float64)
+    # D = G W^T (fo terms), then at most deg + 1 terms per entry
+    deg = int(np.diff(a.rpt).max())
+    tol = (fo + deg + 2) * U
+    assert np.all(np.abs(gx - dx) <= tol * dxb + 1e-30)
+    gw = dw_d.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(gw - dw) <= n * U * dwb + 1e-30)
+    log(f"[gpu] GNN layer n={n} f={f} fo={fo} k={k}: forward and backward match the oracle")
