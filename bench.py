@@ -216,13 +216,13 @@ def cpu_baseline(a):
                            rows1, 2.0 * float(ip[rows1].sum()))
 
 
-def measure_product(da, db, steps: int, warmup: int, label: str):
+def measure_product(da, db, steps: int, warmup: int, label: str, opt=None):
     """Times `steps` whole passes (plan, symbolic, allocation of C, numeric,
     flag check, release) of C = A * B after `warmup` untimed ones, with the
     launch groups timed by HIP events on the plan's stream."""
     import torch
     from paper_2512_12036_amd import spgemm
-    opt = spgemm.make_options(profile=1)
+    opt = opt if opt is not None else spgemm.make_options(profile=1)
     stream = torch.cuda.current_stream(da.rpt.device)
 
     def step():
@@ -340,6 +340,26 @@ def run_er2k(args):
         rows = np.arange(a.nrows, dtype=np.int64)
         out["cpu_baseline"] = cpu_baseline_of(a, a, rows, float(r["info"].flops),
                                               "the whole product", rows, float(r["info"].flops))
+    return out
+
+
+def run_tiny(args):
+    """Rows of a few products each (the smallest group): C = A*A with A an
+    Erdos-Renyi 2^20 x 2^20 matrix of 4 nonzeros per row (about 16 products
+    per row), with the lane-group kernels and with the thread-per-row
+    range-stream kernels (options.row_thread)."""
+    from paper_2512_12036_amd import gen, spgemm
+    log("[bench] generating the tiny-row workload ...")
+    a = gen.er(1 << 20, 4 << 20, seed=61, lo=0.0, hi=1.0)
+    da = spgemm.to_device(a)
+    out = {"workload": "C = A*A, A Erdos-Renyi 2^20 x 2^20 with 4 nonzeros per row, FP32 (0,1]"}
+    for rt in (0, 1):
+        r = measure_product(da, da, max(10, args.steps), max(3, args.warmup), f"tiny rt={rt}",
+                            spgemm.make_options(profile=1, row_thread=rt))
+        out["row_thread" if rt else "lane_groups"] = {
+            "ms_per_step": round(r["ms"], 3),
+            "gflops": round(r["info"].flops / (r["ms"] * 1e-3) / 1e9, 2),
+            "phases_ms": {k: round(v, 4) for k, v in sorted(r["avg"].items())}}
     return out
 
 
@@ -605,6 +625,9 @@ def main():
 
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the ER, contraction and MCL workloads")
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset of rmat18, er2k, contraction, mcl, tiny, served "
+                         "(a study run: the JSON line then holds only those)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -612,6 +635,16 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the row-block "
               f"sharding over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        runs = {"rmat18": run_rmat18, "er2k": run_er2k, "contraction": run_contraction,
+                "mcl": run_mcl, "tiny": run_tiny,
+                "served": lambda a: run_served(a.serve_requests,
+                                               [(64, 8 << 30, 4), (1024, 128 << 30, 4)])}
+        out = {}
+        for name in args.only.split(","):
+            out[name] = runs[name](args)
+        print(json.dumps(out), flush=True)
+        return
     out = run_rmat18(args)
     if not args.no_configs:
         out["configs"] = {"er2k": run_er2k(args), "contraction": run_contraction(args),

@@ -165,6 +165,15 @@ typedef struct {
      * needs more fails with SPGEMM_EOVERFLOW: spgemm_plan_create for the
      * symbolic items, spgemm_symbolic for the numeric ones. */
     int64_t item_limit;
+    /* 1: rows of group 1 (the smallest) are handled one thread per row, in
+     * the manner of the paper's AIA kernel (Section IV-D): a gather pass
+     * first resolves rpt_B[col_A[j]] and rpt_B[col_A[j] + 1] of the group's
+     * A nonzeros into one sequential stream per row, which each workgroup
+     * stages in LDS; each thread then walks its row with a private LDS
+     * table.  Requires sym_upper[1] and num_upper[1] <= 32.  0 = off (the
+     * lane-group kernels). */
+    int32_t row_thread;
+    int32_t reserved;        /* must be 0 */
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;

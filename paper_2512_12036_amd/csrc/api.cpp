@@ -91,6 +91,10 @@ struct spgemm_plan {
     // small merged (small: at most half the rank cap outputs)
     int64_t n_s1 = 0, n_s0 = 0, n_m1 = 0, n_m0 = 0;
     int64_t *dflag2 = nullptr, *dfpos2 = nullptr;
+    // thread-per-row group 1 (opt.row_thread): per-row stream offsets and
+    // the streams of both phases
+    int64_t *rt_lens = nullptr, *rt_off_sym = nullptr, *rt_off_num = nullptr;
+    RangeEnt *rt_stream = nullptr;
     int wmax = 0;       // widest chunk over the products
     bool fast = true;   // every B sorted with < 2^30 entries (32-bit chunk indexing)
 
@@ -266,6 +270,9 @@ spgemm_status check_options(const spgemm_options &o) {
         return SPGEMM_EINVAL;
     if (o.validate < 0 || o.validate > 2) return SPGEMM_EINVAL;
     if (o.item_limit < 0) return SPGEMM_EINVAL;
+    if (o.row_thread < 0 || o.row_thread > 1 || o.reserved != 0) return SPGEMM_EINVAL;
+    if (o.row_thread && (o.sym_upper[1] > kRtSlots / 2 || o.num_upper[1] > kRtSlots / 2))
+        return SPGEMM_EINVAL;
     if (o.profile < 0 || o.profile > 1) return SPGEMM_EINVAL;
     if (o.chunks_per_item != 1 && o.chunks_per_item != 2 && o.chunks_per_item != 4 &&
         o.chunks_per_item != 8)
@@ -593,6 +600,20 @@ spgemm_status create_common(spgemm_plan **out, int32_t nprod, const spgemm_csr *
     return SPGEMM_OK;
 }
 
+// Workspace of the thread-per-row group: offsets for the rows of group 1 in
+// either phase and one stream with room for every A nonzero of the plan.
+spgemm_status rt_prepare(spgemm_plan *p) {
+    if (p->rt_stream) return SPGEMM_OK;
+    int64_t nnz_a = 0;
+    for (int q = 0; q < p->nprod; ++q) nnz_a += p->A[q].nnz;
+    const int64_t rows = std::max(p->sym_start[2] - p->sym_start[1], int64_t(1));
+    ST_TRY(dalloc(p, &p->rt_lens, p->Mtot + 1));
+    ST_TRY(dalloc(p, &p->rt_off_sym, rows + 1));
+    ST_TRY(dalloc(p, &p->rt_off_num, p->Mtot + 1));
+    ST_TRY(dalloc(p, &p->rt_stream, std::max<int64_t>(nnz_a, 1)));
+    return SPGEMM_OK;
+}
+
 spgemm_status symbolic_impl(spgemm_plan *p) {
     if (p->state != 1) return SPGEMM_ESTATE;
     const int64_t M = p->Mtot;
@@ -600,9 +621,20 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
     static const char *const sym_names[kGroups] = {"sym.g0", "sym.g1", "sym.g2", "sym.g3",
                                                    "sym.g4", "sym.g5", "sym.g6", "sym.g7"};
     launch_fill_i64(p->row_nnz, M, 0, st);
+    if (p->opt.row_thread) ST_TRY(rt_prepare(p));
     for (int g = 1; g <= 4; ++g) {
         if (p->sym_start[g + 1] == p->sym_start[g]) continue;
         TimeScope ts(p, sym_names[g]);
+        if (g == 1 && p->opt.row_thread) {
+            const int64_t cnt = p->sym_start[2] - p->sym_start[1];
+            const uint64_t *items = p->map_sym + p->sym_start[1];
+            ST_TRY(ensure_scan_tmp(p, cnt));
+            launch_rt_offsets(p->dprods, items, cnt, p->rt_lens, p->rt_off_sym, p->scan_tmp, st);
+            launch_rt_gather(p->dprods, items, cnt, p->rt_off_sym, p->rt_stream, false, st);
+            launch_sym_rowthread(p->dprods, items, cnt, p->rt_off_sym, p->rt_stream,
+                                 p->row_nnz, p->flags, st);
+            continue;
+        }
         launch_sym_group(g, p->dprods, p->map_sym + p->sym_start[g],
                          p->sym_start[g + 1] - p->sym_start[g], p->row_nnz, p->flags, st);
     }
@@ -720,6 +752,13 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
             if (p->n_items < 0 || p->n_items > nitems || p->n_s1 < 0) return SPGEMM_EINTERNAL;
         }
     }
+    if (p->opt.row_thread && p->num_start[2] > p->num_start[1]) {
+        const int64_t cnt = p->num_start[2] - p->num_start[1];
+        ST_TRY(ensure_scan_tmp(p, cnt));
+        launch_rt_offsets(p->dprods, p->map_num + p->num_start[1], cnt, p->rt_lens,
+                          p->rt_off_num, p->scan_tmp, st);
+        ST_TRY(launch_check());
+    }
     p->state = 2;
     return SPGEMM_OK;
 }
@@ -734,6 +773,14 @@ spgemm_status numeric_launch(spgemm_plan *p, hipStream_t st) {
     for (int g = 1; g <= 4; ++g) {
         if (p->num_start[g + 1] == p->num_start[g]) continue;
         TimeScope ts(p, num_names[g]);
+        if (g == 1 && p->opt.row_thread) {
+            const int64_t cnt = p->num_start[2] - p->num_start[1];
+            const uint64_t *items = p->map_num + p->num_start[1];
+            launch_rt_gather(p->dprods, items, cnt, p->rt_off_num, p->rt_stream, true, st);
+            launch_num_rowthread(p->dprods, items, cnt, p->rt_off_num, p->rt_stream, p->rptv,
+                                 p->flags, st);
+            continue;
+        }
         launch_num_group(g, p->dprods, p->map_num + p->num_start[g],
                          p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st);
     }

@@ -65,6 +65,15 @@ struct ChunkDesc {
     int32_t pad2;
 };
 
+// One entry of the thread-per-row stream: the B range named by one A
+// nonzero and that nonzero's value (numeric phase).
+struct RangeEnt {
+    int64_t b0;      // rpt_B[col]
+    int32_t len;     // rpt_B[col + 1] - rpt_B[col]
+    float a;         // A's value
+};
+constexpr int kRtSlots = 64;  // table slots per row of the thread-per-row kernels
+
 // A block of up to kRowBlock consecutive rows of one product.
 struct RowBlk {
     int32_t p;
@@ -225,6 +234,20 @@ void launch_mcl_change(int64_t m, const int64_t *rpt_a, const int32_t *col_a, co
 void launch_cc_init(int64_t n, int32_t *lab, hipStream_t s);
 void launch_cc_round(int64_t n, const int64_t *rpt, const int32_t *col, int64_t nnz, int32_t *lab,
                      int *changed, hipStream_t s);
+
+// Thread-per-row kernels for the smallest group (k_rowthread.hip): per-row
+// stream offsets (lens -> off, count + 1), the ranged gather and the two
+// phases.
+void launch_rt_offsets(const ProdDev *prods, const uint64_t *items, int64_t count, int64_t *lens,
+                       int64_t *off, void *scan_tmp, hipStream_t s);
+void launch_rt_gather(const ProdDev *prods, const uint64_t *items, int64_t count,
+                      const int64_t *off, RangeEnt *stream, bool values, hipStream_t s);
+void launch_sym_rowthread(const ProdDev *prods, const uint64_t *items, int64_t count,
+                          const int64_t *off, const RangeEnt *stream, int64_t *row_nnz, int *err,
+                          hipStream_t s);
+void launch_num_rowthread(const ProdDev *prods, const uint64_t *items, int64_t count,
+                          const int64_t *off, const RangeEnt *stream, const int64_t *rptv,
+                          int *err, hipStream_t s);
 
 // GNN layer pieces (k_gnn.hip).
 void launch_rows_uniform(int64_t *rpt, int64_t n, int64_t k, hipStream_t s);

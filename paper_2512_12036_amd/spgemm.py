@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
                 ("chunk_wgs_per_cu", ctypes.c_int32), ("chunk_threads", ctypes.c_int32),
                 ("sym_chunk_threads", ctypes.c_int32), ("num_rank_cap", ctypes.c_int32),
                 ("chunk_merge", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("item_limit", _I64)]
+                ("item_limit", _I64), ("row_thread", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -164,7 +165,7 @@ def default_options() -> Options:
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
                  profile=None, chunks_per_item=None, chunk_wgs_per_cu=None,
                  chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None,
-                 chunk_merge=None, graph=None, item_limit=None) -> Options:
+                 chunk_merge=None, graph=None, item_limit=None, row_thread=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -194,6 +195,8 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.graph = int(graph)
     if item_limit is not None:
         o.item_limit = int(item_limit)
+    if row_thread is not None:
+        o.row_thread = int(row_thread)
     return o
 
 

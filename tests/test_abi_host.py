@@ -78,7 +78,8 @@ def _create(a, b, o):
                                          ("sym_chunk_threads", 32), ("num_rank_cap", 300),
                                          ("chunk_merge", 3), ("chunk_merge", 16),
                                          ("graph", 2), ("graph", -1), ("validate", 3),
-                                         ("item_limit", -1)])
+                                         ("item_limit", -1), ("row_thread", 2),
+                                         ("reserved", 1)])
 def test_bad_options_rejected(field, value):
     o = spgemm.default_options()
     setattr(o, field, value)

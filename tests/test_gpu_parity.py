@@ -336,3 +336,56 @@ def test_dimension_mismatch():
     with pytest.raises(spgemm.SpgemmError) as e:
         spgemm.Plan(a, b)
     assert e.value.code == 2
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_row_thread_group1(exact):
+    """Group 1 handled one thread per row with the gathered range stream
+    (options.row_thread), on rows of every length the group takes, empty
+    rows included; integer values compared exactly."""
+    a = gen.skewed_csr(5001, 3000, seed=81, max_len=6, heavy_rows=0)
+    b = gen.skewed_csr(3000, 4000, seed=82, max_len=5, heavy_rows=0)
+    if exact:
+        a, b = gen.int_valued(a, 83), gen.int_valued(b, 84)
+    opt = forced_options(1)
+    opt.row_thread = 1
+    c = run_and_compare(a, b, options=opt, exact=exact, label=f"rowthread-{exact}")
+    structure_invariants(c)
+    # default grouping with the option on: group 1 rows only take the new path
+    o2 = spgemm.make_options(row_thread=1)
+    run_and_compare(gen.er(2000, 16000, seed=85), gen.er(2000, 16000, seed=85), options=o2,
+                    label="rowthread-er2k")
+    # unsorted B and columns of B fewer than the table (ncols <= 32)
+    bs = gen.shuffle_rows(b, 86)
+    run_and_compare(a, bs, options=opt, exact=exact, b_sorted=False, label="rowthread-unsorted")
+    narrow = gen.random_csr(3000, 20, 0.3, 87)
+    run_and_compare(a, narrow, options=opt, label="rowthread-narrow")
+
+
+def test_row_thread_batch_and_graph():
+    import torch
+    As = [gen.int_valued(gen.skewed_csr(700 + 37 * q, 900, seed=90 + q, max_len=5,
+                                        heavy_rows=0), q) for q in range(5)]
+    Bs = [gen.int_valued(gen.skewed_csr(900, 1000 + q, seed=95 + q, max_len=4,
+                                        heavy_rows=0), q + 7) for q in range(5)]
+    opt = forced_options(1)
+    opt.row_thread = 1
+    for graph in (0, 1):
+        opt.graph = graph
+        plan = spgemm.Plan([spgemm.to_device(a) for a in As], [spgemm.to_device(b) for b in Bs],
+                           opt)
+        try:
+            plan.symbolic()
+            cols, vals = plan.allocate_outputs()
+            for rep in range(3):
+                plan.numeric(cols, vals)
+                plan.sync()
+                torch.cuda.synchronize()
+                for q in range(5):
+                    ref = oracle.product(As[q], Bs[q])
+                    k = plan.nnz[q]
+                    assert oracle.compare(ref, plan.rpts[q].cpu().numpy(),
+                                          cols[q][:k].cpu().numpy(), vals[q][:k].cpu().numpy(),
+                                          exact_values=True) is None, (graph, rep, q)
+        finally:
+            plan.free()
