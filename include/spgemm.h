@@ -409,6 +409,20 @@ spgemm_status spgemm_transpose(int64_t m, int64_t n, const int64_t *row_ptr,
                                int64_t *rpt_t, int32_t *col_t, float *val_t, void *workspace,
                                void *stream);
 
+/* SAMPLE of matrix-based bulk sampling (paper Section V-C): s draws per row
+ * of the m-row CSR matrix P (row_ptr, col_idx, values: nonnegative weights,
+ * one distribution per row) by inverse transform sampling.  Draw t of row r
+ * uses u[r * s + t] in [0, 1) (device, caller supplied, so the random
+ * numbers are inputs): with S the FP32 sum of the row's weights in storage
+ * order, it takes the column of the first entry whose FP32 running sum (the
+ * same order) exceeds u * S, or the last entry if rounding leaves none; a
+ * row of zero total weight draws self[r].  out (device, m * s int32) gets
+ * the drawn columns, row-major.  Enqueued.  EINVAL for NULL pointers or
+ * negative sizes. */
+spgemm_status spgemm_its_sample(int64_t m, int32_t s, const int64_t *row_ptr,
+                                const int32_t *col_idx, const float *values, const float *u,
+                                const int32_t *self, int32_t *out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Allocation-free entry point.  For callers that cannot allocate device
  * memory: code that must not call hipMalloc / hipFree or an allocator, such

@@ -19,6 +19,8 @@ path (``paper_2512_12036_amd``) never does, and shares no code with it.
   Algorithm 6.
 * ``topk_rows``, ``gnn_forward`` and ``gnn_backward`` are the GNN layer
   with a pruning layer (paper Section V-C, Eq. 1-3).
+* ``its_sample``, ``induced`` and ``graphsage_bulk`` are matrix-based bulk
+  sampling (paper Section V-C).
 * ``transpose`` builds S^T for graph contraction (paper Algorithm 7).
 
 Every function here is pinned by ``tests/test_oracle*.py`` against closed
@@ -354,6 +356,84 @@ def gnn_backward(a, g, w, xk, hd):
     dw = hd.T @ g
     dwb = np.abs(hd).T @ np.abs(g)
     return dx, dxb, dw, dwb
+
+
+# --------------------------------------------------------------------------
+# Matrix-based bulk sampling (paper Section V-C), GraphSAGE form.
+# --------------------------------------------------------------------------
+def its_sample(rpt, col, val, u, s: int, self_v):
+    """Inverse transform sampling, s draws per row: with S the FP32 sum of
+    the row's weights in storage order, draw t of row r takes the column of
+    the first entry whose FP32 running sum exceeds u[r, t] * S (FP32), the
+    last entry if none does, and self_v[r] for a row of zero weight.  The
+    sums are sequential FP32 sums, the same arithmetic the device performs,
+    so the drawn integers are decided identically."""
+    rpt = np.asarray(rpt, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float32)
+    col = np.asarray(col)
+    u = np.asarray(u, dtype=np.float32).reshape(-1)
+    m = rpt.shape[0] - 1
+    out = np.zeros(m * s, dtype=np.int32)
+    for r in range(m):
+        w = val[rpt[r]:rpt[r + 1]]
+        c = col[rpt[r]:rpt[r + 1]]
+        run = np.cumsum(w, dtype=np.float32)       # sequential FP32
+        tot = run[-1] if w.shape[0] else np.float32(0)
+        if not tot > 0:
+            out[r * s:(r + 1) * s] = self_v[r]
+            continue
+        x = u[r * s:(r + 1) * s] * tot             # FP32 products
+        # first entry whose running sum exceeds x (sums never decrease)
+        hit = np.searchsorted(run, x, side="right")
+        out[r * s:(r + 1) * s] = c[np.minimum(hit, w.shape[0] - 1)]
+    return out
+
+
+def induced(a, rows, cols):
+    """EXTRACT(A, Q^l, Q^{l-1}): the len(rows) x len(cols) matrix with entry
+    (r, c) = A[rows[r], cols[c]] wherever A stores that entry, columns
+    ascending; values in FP64.  Every stored entry of a selected row is
+    repeated once for each position c at which its column was drawn."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    prpt, pcol, pval = product_rows_of(a, rows)
+    order = np.argsort(cols, kind="stable")
+    first = np.searchsorted(cols[order], pcol, side="left")
+    mult = np.searchsorted(cols[order], pcol, side="right") - first
+    rid = np.repeat(np.repeat(np.arange(len(rows)), np.diff(prpt)), mult)
+    base = np.repeat(first, mult)
+    step = np.arange(mult.sum()) - np.repeat(np.cumsum(mult) - mult, mult)
+    c = order[base + step]
+    v = np.repeat(np.asarray(pval, dtype=np.float64), mult)
+    srt = np.lexsort((c, rid))
+    rpt = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rid, minlength=len(rows)), out=rpt[1:])
+    return rpt, c[srt].astype(np.int32), v[srt]
+
+
+def graphsage_bulk(a, batch, fanouts, uniforms):
+    """The layers of bulk sampling from the batch down: per layer the
+    frontier, the drawn vertices and EXTRACT(A, frontier, draws)."""
+    frontier = np.asarray(batch, dtype=np.int64)
+    layers = []
+    for s, u in zip(fanouts, uniforms):
+        rows = product_rows_of(a, frontier)
+        drawn = its_sample(rows[0], rows[1], rows[2], u, s, frontier)
+        layers.append(dict(frontier=frontier, sampled=drawn,
+                           a_l=induced(a, frontier, drawn)))
+        frontier = drawn.astype(np.int64)
+    return layers
+
+
+def product_rows_of(a, vertices):
+    """P = Q A for the one-hot Q of `vertices`: A's rows, in that order."""
+    vertices = np.asarray(vertices, dtype=np.int64)
+    rpt = np.asarray(a.rpt, dtype=np.int64)
+    lens = rpt[vertices + 1] - rpt[vertices]
+    prpt = np.zeros(len(vertices) + 1, dtype=np.int64)
+    np.cumsum(lens, out=prpt[1:])
+    idx = np.repeat(rpt[vertices] - prpt[:-1], lens) + np.arange(prpt[-1])
+    return prpt, np.asarray(a.col)[idx], np.asarray(a.val)[idx]
 
 
 def transpose(nrows: int, ncols: int, rpt, col, val):

@@ -1297,6 +1297,15 @@ spgemm_status spgemm_transpose(int64_t m, int64_t n, const int64_t *row_ptr,
     return launch_check();
 }
 
+spgemm_status spgemm_its_sample(int64_t m, int32_t s, const int64_t *row_ptr,
+                                const int32_t *col_idx, const float *values, const float *u,
+                                const int32_t *self, int32_t *out, void *stream) {
+    if (m < 0 || s < 0 || !row_ptr) return SPGEMM_EINVAL;
+    if (m > 0 && s > 0 && (!u || !self || !out)) return SPGEMM_EINVAL;
+    launch_its_sample(m, s, row_ptr, col_idx, values, u, self, out, (hipStream_t)stream);
+    return launch_check();
+}
+
 size_t spgemm_noalloc_scratch_bytes(void) { return kNoallocScratch; }
 
 spgemm_status spgemm_multiply_noalloc(const spgemm_csr *A, const spgemm_csr *B,

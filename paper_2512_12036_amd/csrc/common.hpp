@@ -229,6 +229,9 @@ void launch_mcl_write(int64_t m, const int64_t *rpt, const int32_t *col, const f
 void launch_mcl_change(int64_t m, const int64_t *rpt_a, const int32_t *col_a, const float *val_a,
                        int64_t nnz_a, const int64_t *rpt_b, const int32_t *col_b,
                        const float *val_b, int64_t nnz_b, double *out, hipStream_t s);
+// Inverse transform sampling, s draws per row (bulk sampling).
+void launch_its_sample(int64_t m, int s, const int64_t *rpt, const int32_t *col, const float *val,
+                       const float *u, const int32_t *self, int32_t *out, hipStream_t st);
 // Connected components (labels = smallest vertex of the component): init,
 // then rounds of hook + compress until a round hooks nothing (*changed = 0).
 void launch_cc_init(int64_t n, int32_t *lab, hipStream_t s);

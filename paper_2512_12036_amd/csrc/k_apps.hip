@@ -42,7 +42,7 @@ __global__ void k_label_scatter(const int32_t *__restrict__ labels, int64_t n, i
 }
 
 __device__ __forceinline__ float mcl_pow(float x, float p) {
-    return p == 2.f ? x * x : __powf(x, p);
+    return p == 1.f ? x : p == 2.f ? x * x : __powf(x, p);
 }
 
 // Top-k of a row: among the entries kept by the threshold, the k largest
@@ -307,6 +307,48 @@ __global__ void k_cc_compress(int64_t n, int32_t *lab) {
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Inverse transform sampling (matrix-based bulk sampling, paper Section
+// V-C): one thread per draw (row r, draw t).  The row's weights are summed
+// in storage order in FP32 (S), x = u[r s + t] * S, and the draw is the
+// column of the first entry whose running FP32 sum exceeds x (the last
+// entry if rounding leaves none).  Sequential sums make the choice exactly
+// reproducible.  A row of zero total weight (or no entries) draws
+// `self[r]`, the row's own vertex.
+__global__ void k_its_sample(int64_t m, int s, const int64_t *__restrict__ rpt,
+                             const int32_t *__restrict__ col, const float *__restrict__ val,
+                             const float *__restrict__ u, const int32_t *__restrict__ self,
+                             int32_t *__restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m * s) return;
+    const int64_t r = q / s;
+    const int64_t a = rpt[r], b = rpt[r + 1];
+    float tot = 0.f;
+    for (int64_t j = a; j < b; ++j) tot += val[j];
+    if (!(tot > 0.f)) {
+        out[q] = self[r];
+        return;
+    }
+    const float x = u[q] * tot;
+    float acc = 0.f;
+    int32_t pick = col[b - 1];
+    for (int64_t j = a; j < b; ++j) {
+        acc += val[j];
+        if (acc > x) {
+            pick = col[j];
+            break;
+        }
+    }
+    out[q] = pick;
+}
+
+void launch_its_sample(int64_t m, int s, const int64_t *rpt, const int32_t *col, const float *val,
+                       const float *u, const int32_t *self, int32_t *out, hipStream_t st) {
+    const int64_t n = m * s;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_its_sample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, s,
+                       rpt, col, val, u, self, out);
 }
 
 void launch_selector_t(const int32_t *labels, int64_t n, int64_t k, int64_t *rpt, int32_t *col,

@@ -62,7 +62,7 @@ EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_
             "spgemm_estimate", "spgemm_noalloc_scratch_bytes", "spgemm_multiply_noalloc",
             "spgemm_mcl_change", "spgemm_components_workspace", "spgemm_components",
             "spgemm_topk_rows", "spgemm_csr_to_dense", "spgemm_gemm_f32", "spgemm_masked_spmm",
-            "spgemm_transpose_workspace", "spgemm_transpose"]
+            "spgemm_transpose_workspace", "spgemm_transpose", "spgemm_its_sample"]
 
 
 class SpgemmError(RuntimeError):
@@ -141,6 +141,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spgemm_transpose_workspace.argtypes = [_I64]
     lib.spgemm_transpose_workspace.restype = ctypes.c_size_t
     lib.spgemm_transpose.argtypes = [_I64, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]
+    lib.spgemm_its_sample.argtypes = [_I64, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
     for name in ("spgemm_plan_create", "spgemm_plan_create_batch", "spgemm_symbolic",
                  "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
                  "spgemm_sync", "spgemm_get_info", "spgemm_export", "spgemm_selector_transpose",
@@ -630,3 +631,16 @@ def transpose(m: DeviceCsr, stream=None) -> DeviceCsr:
                                 _VP(val.data_ptr()), _VP(ws.data_ptr()), _st(dev, stream)),
            "spgemm_transpose")
     return DeviceCsr(m.ncols, m.nrows, rpt, col[:m.nnz], val[:m.nnz], False)
+
+
+def its_sample(p: DeviceCsr, s: int, u, self_v, stream=None):
+    """s inverse-transform draws per row of p (weights); u: float32 device
+    tensor of p.nrows * s uniforms in [0, 1); self_v: int32 device tensor of
+    each row's own vertex (drawn when the row has no weight).  Returns the
+    drawn columns, int32 [p.nrows * s]."""
+    torch = _torch()
+    out = torch.empty(max(p.nrows * s, 1), dtype=torch.int32, device=p.rpt.device)
+    _check(load().spgemm_its_sample(p.nrows, int(s), _VP(p.rpt.data_ptr()), _ptr(p.col),
+                                    _ptr(p.val), _ptr(u), _ptr(self_v), _VP(out.data_ptr()),
+                                    _st(p.rpt.device, stream)), "spgemm_its_sample")
+    return out[:p.nrows * s]
