@@ -20,6 +20,10 @@
 using namespace spg;
 
 namespace {
+#include "tuned_defaults.inc"
+}  // namespace
+
+namespace {
 
 constexpr int kDescSlots = 4;  // pinned descriptor staging buffers (ring)
 
@@ -941,17 +945,21 @@ extern "C" {
 void spgemm_default_options(spgemm_options *opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
-    // tuned on gfx950 (R-MAT scale 18 self-product; see the autotuner)
-    const int64_t sym[kGroups - 1] = {0, 32, 64, 128, 256, 1024, 1024};
-    const int64_t num[kGroups - 1] = {0, 32, 64, 128, 256, 1024, 1024};
+    // the autotuner's result for this architecture (tuned/<arch>.json,
+    // compiled in by the build)
     for (int g = 0; g < kGroups - 1; ++g) {
-        opt->sym_upper[g] = sym[g];
-        opt->num_upper[g] = num[g];
+        opt->sym_upper[g] = kTunedSym[g];
+        opt->num_upper[g] = kTunedNum[g];
     }
-    opt->chunk_cols = 8192;
+    opt->chunk_cols = kTuned_chunk_cols;
+    opt->chunks_per_item = kTuned_chunks_per_item;
+    opt->chunk_wgs_per_cu = kTuned_chunk_wgs_per_cu;
+    opt->chunk_threads = kTuned_chunk_threads;
+    opt->sym_chunk_threads = kTuned_sym_chunk_threads;
+    opt->num_rank_cap = kTuned_num_rank_cap;
+    opt->chunk_merge = kTuned_chunk_merge;
+    opt->row_thread = kTuned_row_thread;
     opt->validate = 0;
-    opt->chunks_per_item = 1;
-    opt->num_rank_cap = 2048;
 }
 
 spgemm_status spgemm_plan_create(spgemm_plan **out, const spgemm_csr *A, const spgemm_csr *B,

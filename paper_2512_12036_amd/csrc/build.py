@@ -33,10 +33,34 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+TUNED = os.path.join(PKG, "tuned")
+
+
+def write_tuned_defaults() -> str:
+    """The library's default options, compiled in from tuned/<arch>.json
+    (written by the autotuner): a C++ include in the build folder."""
+    import json
+    with open(os.path.join(TUNED, f"{ARCH}.json")) as f:
+        o = json.load(f)["options"]
+    lines = ["// Generated from paper_2512_12036_amd/tuned/%s.json by csrc/build.py." % ARCH,
+             "constexpr int64_t kTunedSym[kGroups - 1] = {%s};" % ", ".join(map(str, o["sym_upper"])),
+             "constexpr int64_t kTunedNum[kGroups - 1] = {%s};" % ", ".join(map(str, o["num_upper"]))]
+    for k in ("chunk_cols", "chunks_per_item", "chunk_wgs_per_cu", "chunk_threads",
+              "sym_chunk_threads", "num_rank_cap", "chunk_merge", "row_thread"):
+        lines.append("constexpr int32_t kTuned_%s = %d;" % (k, int(o[k])))
+    os.makedirs(BUILD, exist_ok=True)
+    path = os.path.join(BUILD, "tuned_defaults.inc")
+    text = "\n".join(lines) + "\n"
+    if not os.path.exists(path) or open(path).read() != text:
+        with open(path, "w") as f:
+            f.write(text)
+    return path
+
+
 def common_flags() -> list[str]:
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", HERE]
+            "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", HERE, "-I", BUILD]
 
 
 def _compile(src: str) -> str:
@@ -63,6 +87,7 @@ def _link(objs, lib):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    write_tuned_defaults()
     with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES + GEN_SOURCES))
     _link(objs[:len(SOURCES)], LIB)

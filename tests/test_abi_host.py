@@ -135,3 +135,14 @@ def test_library_has_no_unresolved_internal_symbols():
     out = subprocess.check_output(["nm", "-D", "--undefined-only", lib]).decode()
     missing = [l for l in out.splitlines() if "spg" in l]
     assert not missing, missing
+
+
+def test_defaults_come_from_the_tuned_file():
+    """spgemm_default_options returns what the autotuner wrote for gfx950
+    (paper_2512_12036_amd/tuned/gfx950.json), compiled in by the build."""
+    import json
+    with open(os.path.join(ROOT, "paper_2512_12036_amd", "tuned", "gfx950.json")) as f:
+        want = json.load(f)["options"]
+    from paper_2512_12036_amd import autotune
+    assert autotune.options_dict(spgemm.default_options()) == want
+    assert autotune.legal(want)
