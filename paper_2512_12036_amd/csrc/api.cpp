@@ -120,6 +120,13 @@ struct spgemm_plan {
     bool num_graph_empty = false;        // captured, with nothing to launch
     std::pmr::vector<void *> allocs;
     size_t ws_bytes = 0;
+    // Workspace pooling: the buffers of one planning stage are carved from a
+    // single reservation, so a stage costs one allocator call.  `measuring`
+    // makes dalloc only add up the sizes (a dry run of the stage).
+    bool measuring = false;
+    size_t measured = 0;
+    char *res = nullptr;
+    size_t res_cap = 0, res_used = 0;
 
     // Allocation-free mode: every workspace buffer is carved from this
     // device arena (the library's static scratch array), host read-backs and
@@ -184,11 +191,21 @@ spgemm_status dalloc(spgemm_plan *p, T **out, size_t count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
     bytes = (bytes + 255) & ~size_t(255);
     void *ptr = nullptr;
+    if (p->measuring) {
+        p->measured += bytes;
+        *out = nullptr;
+        return SPGEMM_OK;
+    }
     if (p->noalloc) {
         if (bytes > p->arena_cap - p->arena_used) return SPGEMM_ENOMEM;
         *out = (T *)(p->arena + p->arena_used);
         p->arena_used += bytes;
         p->ws_bytes += bytes;
+        return SPGEMM_OK;
+    }
+    if (p->res && bytes <= p->res_cap - p->res_used) {
+        *out = (T *)(p->res + p->res_used);
+        p->res_used += bytes;
         return SPGEMM_OK;
     }
     if (p->afn) {
@@ -211,9 +228,49 @@ spgemm_status ensure_scan_tmp(spgemm_plan *p, int64_t n) {
     if (need <= p->scan_tmp_bytes) return SPGEMM_OK;
     char *t = nullptr;
     ST_TRY(dalloc(p, &t, need));
+    if (p->measuring) return SPGEMM_OK;
     p->scan_tmp = t;
     p->scan_tmp_bytes = need;
     return SPGEMM_OK;
+}
+
+// One allocation of `bytes` that the following dallocs are carved from.
+spgemm_status reserve(spgemm_plan *p, size_t bytes) {
+    p->res = nullptr;
+    p->res_cap = p->res_used = 0;
+    if (p->noalloc || bytes == 0) return SPGEMM_OK;
+    void *ptr = nullptr;
+    if (p->afn) {
+        ptr = p->afn(p->actx, bytes, (void *)p->stream);
+        if (!ptr) return SPGEMM_ENOMEM;
+    } else {
+        if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return SPGEMM_ENOMEM;
+        }
+    }
+    p->allocs.push_back(ptr);
+    p->ws_bytes += bytes;
+    p->res = (char *)ptr;
+    p->res_cap = bytes;
+    return SPGEMM_OK;
+}
+
+// Runs the allocations of a planning stage twice: a dry run adds up their
+// sizes, one reservation of that total follows, and the real run carves
+// every buffer from it.  `stage` may only allocate.
+template <typename F>
+spgemm_status alloc_stage(spgemm_plan *p, F &&stage) {
+    p->measuring = true;
+    p->measured = 0;
+    spgemm_status s = stage();
+    p->measuring = false;
+    if (s != SPGEMM_OK) return s;
+    ST_TRY(reserve(p, p->measured));
+    s = stage();
+    p->res = nullptr;
+    p->res_cap = p->res_used = 0;
+    return s;
 }
 
 spgemm_status scan(spgemm_plan *p, const int64_t *in, int64_t *out, int64_t n) {
@@ -379,20 +436,22 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
     if ((int64_t)p->hblks.size() >= (int64_t(1) << 31)) return SPGEMM_EOVERFLOW;
 
     const int64_t M = p->Mtot;
-    ST_TRY(dalloc(p, &p->dprods, nprod));
-    ST_TRY(dalloc(p, &p->dblks, p->hblks.size()));
-    ST_TRY(dalloc(p, &p->ip, M));
-    ST_TRY(dalloc(p, &p->row_nnz, M));
-    ST_TRY(dalloc(p, &p->rptv, M + 1));
-    ST_TRY(dalloc(p, &p->map_sym, M));
-    ST_TRY(dalloc(p, &p->map_num, M));
-    ST_TRY(dalloc(p, &p->hslot, M));
-    ST_TRY(dalloc(p, &p->blkcnt, (size_t)kGroups * p->nblk));
-    ST_TRY(dalloc(p, &p->blkoff, (size_t)kGroups * p->nblk + 1));
-    ST_TRY(dalloc(p, &p->starts, 2 * (kGroups + 1)));
-    ST_TRY(dalloc(p, &p->stats, nprod));
-    ST_TRY(dalloc(p, &p->flags, 3 + nprod));
-    ST_TRY(ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk)));
+    ST_TRY(alloc_stage(p, [&]() -> spgemm_status {
+        ST_TRY(dalloc(p, &p->dprods, nprod));
+        ST_TRY(dalloc(p, &p->dblks, p->hblks.size()));
+        ST_TRY(dalloc(p, &p->ip, M));
+        ST_TRY(dalloc(p, &p->row_nnz, M));
+        ST_TRY(dalloc(p, &p->rptv, M + 1));
+        ST_TRY(dalloc(p, &p->map_sym, M));
+        ST_TRY(dalloc(p, &p->map_num, M));
+        ST_TRY(dalloc(p, &p->hslot, M));
+        ST_TRY(dalloc(p, &p->blkcnt, (size_t)kGroups * p->nblk));
+        ST_TRY(dalloc(p, &p->blkoff, (size_t)kGroups * p->nblk + 1));
+        ST_TRY(dalloc(p, &p->starts, 2 * (kGroups + 1)));
+        ST_TRY(dalloc(p, &p->stats, nprod));
+        ST_TRY(dalloc(p, &p->flags, 3 + nprod));
+        return ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk));
+    }));
     if (!p->noalloc) {
         void *h = nullptr;
         HIP_TRY(hipHostMalloc(&h, sizeof(ProdDev) * nprod * kDescSlots, hipHostMallocDefault));
@@ -494,53 +553,61 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         const int64_t nh = p->nh;
         const uint64_t *hitems = p->map_sym + p->sym_start[kGroups - 1];
         const int64_t nitems = p->h_items / p->opt.chunks_per_item;  // upper bound when merging
-        ST_TRY(dalloc(p, &p->nchv, nh));
-        ST_TRY(dalloc(p, &p->ibase, nh + 1));
-        ST_TRY(dalloc(p, &p->cbase, nh + 1));
-        ST_TRY(dalloc(p, &p->chunk_cnt, p->h_items));
-        ST_TRY(dalloc(p, &p->chunk_pos, p->h_items + 1));
-        ST_TRY(dalloc(p, &p->hitem_row, nitems));
-        ST_TRY(dalloc(p, &p->sdesc, nitems));
         p->wpc = (p->wmax + 31) / 32;
-        ST_TRY(dalloc(p, &p->sbits, (size_t)p->h_items * p->wpc));
+        // every buffer of the chunk preparation, in one reservation
+        int64_t *ntile = nullptr, *tbase = nullptr;
+        int32_t *tile_row = nullptr;
+        unsigned long long *ipc = nullptr;
+        std::pmr::vector<int32_t *> bsv(nprod, nullptr, p->hblks.get_allocator());
+        ST_TRY(alloc_stage(p, [&]() -> spgemm_status {
+            ST_TRY(dalloc(p, &p->nchv, nh));
+            ST_TRY(dalloc(p, &p->ibase, nh + 1));
+            ST_TRY(dalloc(p, &p->cbase, nh + 1));
+            ST_TRY(dalloc(p, &p->chunk_cnt, p->h_items));
+            ST_TRY(dalloc(p, &p->chunk_pos, p->h_items + 1));
+            ST_TRY(dalloc(p, &p->hitem_row, nitems));
+            ST_TRY(dalloc(p, &p->sdesc, nitems));
+            ST_TRY(dalloc(p, &p->sbits, (size_t)p->h_items * p->wpc));
+            for (int q = 0; q < nprod; ++q) {
+                const ProdDev &P = p->hprods[q];
+                if (ps[q].h_rows == 0 || P.b_sorted != 1) continue;
+                ST_TRY(dalloc(p, &bsv[q], (size_t)P.k * (P.nch + 1)));
+            }
+            if (p->merge > 1) ST_TRY(dalloc(p, &p->mstart, p->h_items));
+            if (p->fast) {
+                ST_TRY(dalloc(p, &p->slen, nh));
+                ST_TRY(dalloc(p, &p->sbase, nh + 1));
+                ST_TRY(dalloc(p, &p->sabs, p->h_split));
+                ST_TRY(dalloc(p, &ntile, nh));
+                ST_TRY(dalloc(p, &tbase, nh + 1));
+                ST_TRY(dalloc(p, &tile_row, p->h_tiles));
+                if (p->merge > 1) ST_TRY(dalloc(p, &ipc, p->h_items));
+            }
+            return ensure_scan_tmp(p, std::max(nh, p->h_items));
+        }));
         TimeScope ts(p, "plan.split");
         bool reupload = false;
         for (int q = 0; q < nprod; ++q) {
             ProdDev &P = p->hprods[q];
-            if (ps[q].h_rows == 0 || P.b_sorted != 1) continue;
-            int32_t *bs = nullptr;
-            ST_TRY(dalloc(p, &bs, (size_t)P.k * (P.nch + 1)));
-            launch_bsplit(P.rptB, P.colB, P.k, P.W, P.nch, bs, p->stream);
-            P.bsplit = bs;
+            if (!bsv[q]) continue;
+            launch_bsplit(P.rptB, P.colB, P.k, P.W, P.nch, bsv[q], p->stream);
+            P.bsplit = bsv[q];
             reupload = true;
         }
         if (reupload) ST_TRY(upload_descriptors(p));
         launch_nch_of(p->dprods, hitems, nh, 1, p->nchv, p->stream);
         ST_TRY(launch_check());
         ST_TRY(scan(p, p->nchv, p->cbase, nh));
-        if (p->merge > 1) ST_TRY(dalloc(p, &p->mstart, p->h_items));
         if (p->fast) {
-            ST_TRY(dalloc(p, &p->slen, nh));
-            ST_TRY(dalloc(p, &p->sbase, nh + 1));
-            ST_TRY(dalloc(p, &p->sabs, p->h_split));
             launch_row_splitlen(p->dprods, hitems, nh, p->slen, p->stream);
             ST_TRY(launch_check());
             ST_TRY(scan(p, p->slen, p->sbase, nh));
             // one workgroup per tile of A nonzeros of every row
-            int64_t *ntile = nullptr, *tbase = nullptr;
-            int32_t *tile_row = nullptr;
-            unsigned long long *ipc = nullptr;
-            ST_TRY(dalloc(p, &ntile, nh));
-            ST_TRY(dalloc(p, &tbase, nh + 1));
-            ST_TRY(dalloc(p, &tile_row, p->h_tiles));
             launch_sabs_tiles(p->dprods, hitems, nh, ntile, p->stream);
             ST_TRY(launch_check());
             ST_TRY(scan(p, ntile, tbase, nh));
             launch_expand(tbase, nh, tile_row, p->stream);
-            if (p->merge > 1) {
-                ST_TRY(dalloc(p, &ipc, p->h_items));
-                launch_fill_i64((int64_t *)ipc, p->h_items, 0, p->stream);
-            }
+            if (p->merge > 1) launch_fill_i64((int64_t *)ipc, p->h_items, 0, p->stream);
             launch_sabs(p->dprods, hitems, p->h_tiles, tile_row, tbase, p->sbase, p->sabs,
                         p->cbase, ipc, p->stream);
             ST_TRY(launch_check());
@@ -611,11 +678,13 @@ spgemm_status rt_prepare(spgemm_plan *p) {
     int64_t nnz_a = 0;
     for (int q = 0; q < p->nprod; ++q) nnz_a += p->A[q].nnz;
     const int64_t rows = std::max(p->sym_start[2] - p->sym_start[1], int64_t(1));
-    ST_TRY(dalloc(p, &p->rt_lens, p->Mtot + 1));
-    ST_TRY(dalloc(p, &p->rt_off_sym, rows + 1));
-    ST_TRY(dalloc(p, &p->rt_off_num, p->Mtot + 1));
-    ST_TRY(dalloc(p, &p->rt_stream, std::max<int64_t>(nnz_a, 1)));
-    return SPGEMM_OK;
+    return alloc_stage(p, [&]() -> spgemm_status {
+        ST_TRY(dalloc(p, &p->rt_lens, p->Mtot + 1));
+        ST_TRY(dalloc(p, &p->rt_off_sym, rows + 1));
+        ST_TRY(dalloc(p, &p->rt_off_num, p->Mtot + 1));
+        ST_TRY(dalloc(p, &p->rt_stream, std::max<int64_t>(nnz_a, 1)));
+        return ensure_scan_tmp(p, p->Mtot);
+    });
 }
 
 spgemm_status symbolic_impl(spgemm_plan *p) {
@@ -707,10 +776,22 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
         const uint64_t *ditems = p->map_num + p->num_start[kGroups - 1];
         // with merging an upper bound; the exact count is dbase[nd]
         const int64_t nitems = p->d_items / p->opt.chunks_per_item;
-        ST_TRY(dalloc(p, &p->dnchv, p->nd));
-        ST_TRY(dalloc(p, &p->dbase, p->nd + 1));
-        ST_TRY(dalloc(p, &p->ditem_row, nitems));
-        ST_TRY(dalloc(p, &p->ndesc, nitems));
+        const bool split_lists = num_chunk_rank_used(p->fast, p->opt.chunks_per_item,
+                                                     p->opt.num_rank_cap);
+        ST_TRY(alloc_stage(p, [&]() -> spgemm_status {
+            ST_TRY(dalloc(p, &p->dnchv, p->nd));
+            ST_TRY(dalloc(p, &p->dbase, p->nd + 1));
+            ST_TRY(dalloc(p, &p->ditem_row, nitems));
+            ST_TRY(dalloc(p, &p->ndesc, nitems));
+            if (split_lists) {
+                ST_TRY(dalloc(p, &p->ndesc_split, nitems));
+                ST_TRY(dalloc(p, &p->dflag, nitems));
+                ST_TRY(dalloc(p, &p->dfpos, nitems + 1));
+                ST_TRY(dalloc(p, &p->dflag2, nitems));
+                ST_TRY(dalloc(p, &p->dfpos2, nitems + 1));
+            }
+            return ensure_scan_tmp(p, std::max(p->nd, nitems));
+        }));
         const int64_t *nlim = p->merge > 1 ? p->dbase + p->nd : nullptr;
         if (p->merge > 1)
             launch_num_nitems(p->dprods, ditems, p->nd, p->hslot, p->nchv, p->dnchv, st);
@@ -727,11 +808,6 @@ spgemm_status symbolic_impl(spgemm_plan *p) {
         if (num_chunk_rank_used(p->fast, p->opt.chunks_per_item, p->opt.num_rank_cap)) {
             // dense chunks first, then the rank-accumulated items by kind and
             // size, so that each launch covers its own items only
-            ST_TRY(dalloc(p, &p->ndesc_split, nitems));
-            ST_TRY(dalloc(p, &p->dflag, nitems));
-            ST_TRY(dalloc(p, &p->dfpos, nitems + 1));
-            ST_TRY(dalloc(p, &p->dflag2, nitems));
-            ST_TRY(dalloc(p, &p->dfpos2, nitems + 1));
             launch_desc_flag(p->ndesc, nitems, p->chunk_cnt, p->opt.num_rank_cap, nlim, p->dflag,
                              p->dflag2, st);
             ST_TRY(launch_check());

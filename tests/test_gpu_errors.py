@@ -72,7 +72,7 @@ def test_allocator_failure_at_every_point():
     assert lib.spgemm_symbolic(h, ctypes.c_void_p(rpt.data_ptr()), ctypes.byref(nnz), None) == 0
     total = ok.calls
     lib.spgemm_free(h)
-    assert not ok.live and total > 10
+    assert not ok.live and total >= 2   # one reservation per planning stage
     log(f"[gpu] a plan + symbolic phase makes {total} allocations")
     saw_create, saw_symbolic = False, False
     for k in range(1, total + 1):
