@@ -259,8 +259,57 @@ spgemm_status spgemm_numeric_batch(spgemm_plan *p, const float *const *a_values,
 spgemm_status spgemm_estimate(const spgemm_csr *A, const spgemm_csr *B, int64_t *out,
                               void *stream);
 
+/* ------------------------------------------------------------------------
+ * Device-driven batch plans: no host synchronisation and no host round trip
+ * between the phases.  Every row-group launch covers an upper bound of its
+ * rows and takes the group's part of the row map from device memory, and C
+ * is written into one arena the caller sizes from an upper bound
+ * (spgemm_estimate's sum of min(IP, ncols)).  The whole execution can be
+ * captured as one HIP graph.  For products whose B has at most
+ * min(sym_upper[6], num_upper[6]) columns (no row is then column chunked),
+ * such as the served aggregation requests.
+ * ------------------------------------------------------------------------ */
+
+/* Creates a device-driven plan for nprod products (host arrays of
+ * descriptors, as spgemm_plan_create_batch): checks, allocates the per-row
+ * workspace (one allocator call) and uploads the descriptors; no kernel runs
+ * and the stream is not synchronised.  EINVAL also when a B has more columns
+ * than the bound above, or options.validate / options.row_thread are set;
+ * EOVERFLOW when the products' A have 2^26 rows or more in total (the
+ * group launches cover every row of the batch). */
+spgemm_status spgemm_plan_create_device(spgemm_plan **out, int32_t nprod, const spgemm_csr *A,
+                                        const spgemm_csr *B, const spgemm_options *opt,
+                                        void *stream, spgemm_alloc_fn alloc_fn,
+                                        spgemm_free_fn free_fn, void *alloc_ctx);
+
+/* Runs the whole product for every product of a device-driven plan,
+ * enqueued on the plan's stream with no host synchronisation: intermediate
+ * products and grouping (paper Algorithm 1, Section III-B), the allocation
+ * phase and row-pointer scan (Algorithms 2-4), the regrouping and the
+ * accumulation phase with its ordered gathering (Algorithms 4-5,
+ * Section III-D).
+ *   a_values, b_values  host arrays of nprod device pointers (FP32 values);
+ *   c_row_ptr           host array of nprod device pointers, A_p.nrows + 1
+ *                       int64 each: product p's own row pointers;
+ *   c_offsets           device, nprod + 1 int64: product p's C occupies
+ *                       arena entries [c_offsets[p], c_offsets[p + 1]);
+ *   c_col, c_val        the arena (device, capacity entries each).
+ * All caller owned.  When the batch's nnz(C) exceeds capacity nothing is
+ * written to the arena and spgemm_sync reports SPGEMM_ENOMEM (c_offsets then
+ * holds the sizes needed).  May be called again (new values, or the same).
+ * With options.graph = 1 the first call captures every launch into one
+ * HIP graph and later calls replay it (re-captured when c_row_ptr,
+ * c_offsets or capacity change).  ESTATE on a plan not made by
+ * spgemm_plan_create_device; symbolic / numeric calls on such a plan return
+ * ESTATE. */
+spgemm_status spgemm_execute_arena(spgemm_plan *p, const float *const *a_values,
+                                   const float *const *b_values, int64_t *const *c_row_ptr,
+                                   int64_t *c_offsets, int32_t *c_col, float *c_val,
+                                   int64_t capacity);
+
 /* Waits for the plan's stream and reports a kernel-raised error flag
- * (EINTERNAL) or a failed launch (EHIP). */
+ * (EINTERNAL), a C too large for its arena (ENOMEM, device-driven plans) or
+ * a failed launch (EHIP). */
 spgemm_status spgemm_sync(spgemm_plan *p);
 
 /* Fills *info (host).  Never synchronises. */

@@ -37,7 +37,8 @@ struct spgemm_plan {
     // Host containers draw from `mr`: the heap for ordinary plans, a static
     // host buffer for the allocation-free entry point.
     explicit spgemm_plan(std::pmr::memory_resource *r = std::pmr::new_delete_resource())
-        : A(r), B(r), hprods(r), hblks(r), hstats(r), nnz_c(r), timed(r), allocs(r) {}
+        : A(r), B(r), hprods(r), hblks(r), hstats(r), nnz_c(r), timed(r), allocs(r),
+          dev_rpt(r) {}
     hipStream_t stream = nullptr;
     spgemm_alloc_fn afn = nullptr;
     spgemm_free_fn ffn = nullptr;
@@ -116,6 +117,15 @@ struct spgemm_plan {
     std::pmr::vector<Timed> timed;
 
     int state = 0;  // 1 planned, 2 symbolic done
+    // device-driven plans (spgemm_plan_create_device): every phase sized
+    // from device-side counts, C in a caller's arena; the whole execution
+    // optionally captured as one graph
+    bool device_driven = false;
+    int sym_hi = 0, num_hi = 0;          // last row group that can hold rows
+    hipGraphExec_t dev_graph = nullptr;  // captured execution (opt.graph)
+    std::pmr::vector<int64_t *> dev_rpt; // the row-pointer arrays it was captured with
+    int64_t *dev_off = nullptr;
+    int64_t dev_cap = -1;
     hipGraphExec_t num_graph = nullptr;  // the numeric launches, captured (opt.graph)
     bool num_graph_empty = false;        // captured, with nothing to launch
     std::pmr::vector<void *> allocs;
@@ -380,8 +390,10 @@ spgemm_status read_flags(spgemm_plan *p, int *out, int n) {
     return SPGEMM_OK;
 }
 
-spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
-                               const spgemm_csr *B) {
+// Host side of plan creation: descriptors, row blocks, the per-row
+// workspace, the pinned staging; the descriptors and row blocks are
+// uploaded.  No kernel runs yet.
+spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const spgemm_csr *B) {
     p->nprod = nprod;
     p->A.assign(A, A + nprod);
     p->B.assign(B, B + nprod);
@@ -447,7 +459,9 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         ST_TRY(dalloc(p, &p->hslot, M));
         ST_TRY(dalloc(p, &p->blkcnt, (size_t)kGroups * p->nblk));
         ST_TRY(dalloc(p, &p->blkoff, (size_t)kGroups * p->nblk + 1));
-        ST_TRY(dalloc(p, &p->starts, 2 * (kGroups + 1)));
+        // group starts (symbolic, numeric), then the device-sized launches'
+        // work counters (symbolic, numeric)
+        ST_TRY(dalloc(p, &p->starts, 4 * (kGroups + 1)));
         ST_TRY(dalloc(p, &p->stats, nprod));
         ST_TRY(dalloc(p, &p->flags, 3 + nprod));
         return ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk));
@@ -466,6 +480,13 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         HIP_TRY(hipMemcpyAsync(p->dblks, p->hblks.data(), sizeof(RowBlk) * p->hblks.size(),
                                hipMemcpyHostToDevice, p->stream));
 
+    return SPGEMM_OK;
+}
+
+spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
+                               const spgemm_csr *B) {
+    ST_TRY(plan_setup(p, nprod, A, B));
+    const int64_t M = p->Mtot;
     if (p->opt.validate) {
         int f[3];
         for (int q = 0; q < nprod; ++q) {
@@ -636,6 +657,121 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         }
     }
     p->state = 1;
+    return SPGEMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-driven plans: no host synchronisation anywhere.  Every launch of a
+// row group covers an upper bound of its rows (all rows of the batch) and
+// takes the group's range of the row map from the device; C is written into
+// one arena at the batch-wide row pointers.  Restricted to products whose B
+// has no more columns than the block groups take, so that no row is column
+// chunked (that path sizes its work items on the host).
+// ---------------------------------------------------------------------------
+int last_group(const int64_t *upper, int64_t max_ncols) {
+    // keys never exceed B's columns; B of at most 512 columns keeps its rows
+    // in the 64-lane group (direct-mapped tables)
+    int hi = 0;
+    for (int g = 1; g <= 6; ++g)
+        if (upper[g - 1] < max_ncols) hi = g;
+    if (max_ncols <= kDirectG4 && hi > 4) hi = 4;
+    return hi;
+}
+
+spgemm_status device_plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A,
+                                const spgemm_csr *B) {
+    if (p->opt.validate || p->opt.row_thread) return SPGEMM_EINVAL;
+    int64_t max_ncols = 0;
+    for (int q = 0; q < nprod; ++q) max_ncols = std::max(max_ncols, B[q].ncols);
+    if (max_ncols > p->opt.sym_upper[kGroups - 2] || max_ncols > p->opt.num_upper[kGroups - 2])
+        return SPGEMM_EINVAL;  // rows could need the column-chunked path
+    int64_t rows = 0;
+    for (int q = 0; q < nprod; ++q) rows += A[q].nrows;
+    // the group launches cover every row of the batch: 64 threads per row
+    // in the widest group, within a grid's 2^32 work-items
+    if (rows > kMaxDeviceRows) return SPGEMM_EOVERFLOW;
+    ST_TRY(plan_setup(p, nprod, A, B));
+    p->sym_hi = last_group(p->opt.sym_upper, max_ncols);
+    p->num_hi = last_group(p->opt.num_upper, max_ncols);
+    p->device_driven = true;
+    p->dev_rpt.assign(nprod, nullptr);
+    p->state = 1;
+    return SPGEMM_OK;
+}
+
+// Every kernel of a device-driven execution, in order, on `st`.
+spgemm_status device_launch_all(spgemm_plan *p, hipStream_t st, int64_t *const *c_row_ptr,
+                                int64_t *c_offsets, int64_t capacity) {
+    const int64_t M = p->Mtot;
+    const int nprod = p->nprod;
+    // the flag and statistics words start at zero (fill kernels, no memset)
+    launch_fill_i64((int64_t *)p->stats, (int64_t)(sizeof(ProdStats) / 8) * nprod, 0, st);
+    launch_fill_i64((int64_t *)p->flags, (3 + nprod + 1) / 2, 0, st);
+    launch_fill_i64(p->starts + kWorkCtr, 2 * (kGroups + 1), 0, st);
+    // Algorithm 1 and the symbolic grouping
+    const GroupBounds gs = bounds_of(p->opt.sym_upper);
+    launch_ipcount(p->dprods, p->dblks, p->nblk, gs, p->ip, p->blkcnt, p->stats, M, st);
+    launch_scan_i64(p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk, p->scan_tmp, st);
+    launch_scatter(p->dprods, p->dblks, p->nblk, gs, p->ip, p->blkoff, p->map_sym, p->hslot,
+                   nullptr, st);
+    launch_group_starts(p->blkoff, p->nblk, p->starts, st);
+    // allocation phase and row pointers
+    launch_fill_i64(p->row_nnz, M, 0, st);
+    for (int g = 1; g <= std::min(p->sym_hi, 4); ++g)
+        launch_sym_group(g, p->dprods, p->map_sym, M, p->row_nnz, p->flags, st, p->starts, g);
+    for (int g = 5; g <= p->sym_hi; ++g)
+        launch_sym_block(g, p->opt.sym_upper[g], p->dprods, p->map_sym, p->ip, M, p->row_nnz,
+                         p->flags, st, p->starts, g);
+    launch_scan_i64(p->row_nnz, p->rptv, M, p->scan_tmp, st);
+    // numeric grouping by output length
+    const GroupBounds gn = bounds_of(p->opt.num_upper);
+    launch_count_groups(p->dprods, p->dblks, p->nblk, gn, p->row_nnz, p->ip, p->blkcnt, p->stats,
+                        st);
+    launch_scan_i64(p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk, p->scan_tmp, st);
+    launch_scatter(p->dprods, p->dblks, p->nblk, gn, p->row_nnz, p->blkoff, p->map_num, nullptr,
+                   p->ip, st);
+    launch_group_starts(p->blkoff, p->nblk, p->starts + (kGroups + 1), st);
+    // the arena: capacity check (kErrCapacity stops the numeric kernels),
+    // each product's offset and its own row pointers
+    launch_arena_check(p->rptv, M, capacity, p->flags, p->dprods, nprod, c_offsets, st);
+    for (int q = 0; q < nprod; ++q)
+        launch_rows_local(p->rptv, p->hprods[q].row_base, p->hprods[q].m, c_row_ptr[q], st);
+    // accumulation phase
+    const int64_t *ns = p->starts + (kGroups + 1);
+    for (int g = 1; g <= std::min(p->num_hi, 4); ++g)
+        launch_num_group(g, p->dprods, p->map_num, M, p->rptv, p->flags, st, ns, g);
+    for (int g = 5; g <= p->num_hi; ++g)
+        launch_num_block(g, p->opt.num_upper[g], p->dprods, p->map_num, M, p->rptv, p->flags, st,
+                         ns, g);
+    return launch_check();
+}
+
+spgemm_status capture_device(spgemm_plan *p, int64_t *const *c_row_ptr, int64_t *c_offsets,
+                             int64_t capacity) {
+    if (p->dev_graph) (void)hipGraphExecDestroy(p->dev_graph);
+    p->dev_graph = nullptr;
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    spgemm_status s = SPGEMM_OK;
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) {
+        s = device_launch_all(p, cs, c_row_ptr, c_offsets, capacity);
+        e = hipStreamEndCapture(cs, &g);  // always ends the capture
+    }
+    if (s == SPGEMM_OK && e == hipSuccess) e = hipGraphInstantiate(&p->dev_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (s != SPGEMM_OK) return s;
+    if (e != hipSuccess) {
+        report_hip("device plan capture", e, __LINE__);
+        p->dev_graph = nullptr;
+        (void)hipGetLastError();
+        return SPGEMM_EHIP;
+    }
+    for (int q = 0; q < p->nprod; ++q) p->dev_rpt[q] = c_row_ptr[q];
+    p->dev_off = c_offsets;
+    p->dev_cap = capacity;
     return SPGEMM_OK;
 }
 
@@ -1068,6 +1204,7 @@ spgemm_status spgemm_symbolic(spgemm_plan *p, int64_t *c_row_ptr, int64_t *nnz_c
 
 spgemm_status spgemm_symbolic_batch(spgemm_plan *p, int64_t *const *c_row_ptr, int64_t *nnz_c) {
     if (!p || !c_row_ptr || !nnz_c) return SPGEMM_EINVAL;
+    if (p->device_driven) return SPGEMM_ESTATE;
     for (int q = 0; q < p->nprod; ++q)
         if (!c_row_ptr[q]) return SPGEMM_EINVAL;
     spgemm_status s;
@@ -1098,7 +1235,7 @@ spgemm_status spgemm_numeric_batch(spgemm_plan *p, const float *const *a_values,
                                    const float *const *b_values, int32_t *const *c_col_idx,
                                    float *const *c_values) {
     if (!p || !a_values || !b_values || !c_col_idx || !c_values) return SPGEMM_EINVAL;
-    if (p->state != 2) return SPGEMM_ESTATE;
+    if (p->state != 2 || p->device_driven) return SPGEMM_ESTATE;
     for (int q = 0; q < p->nprod; ++q) {
         if ((p->A[q].nnz > 0 && !a_values[q]) || (p->B[q].nnz > 0 && !b_values[q]))
             return SPGEMM_EINVAL;
@@ -1124,11 +1261,77 @@ spgemm_status spgemm_estimate(const spgemm_csr *A, const spgemm_csr *B, int64_t 
     return launch_check();
 }
 
+spgemm_status spgemm_plan_create_device(spgemm_plan **out, int32_t nprod, const spgemm_csr *A,
+                                        const spgemm_csr *B, const spgemm_options *opt,
+                                        void *stream, spgemm_alloc_fn alloc_fn,
+                                        spgemm_free_fn free_fn, void *alloc_ctx) {
+    if (!out) return SPGEMM_EINVAL;
+    *out = nullptr;
+    if (nprod <= 0 || !A || !B) return SPGEMM_EINVAL;
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return SPGEMM_EINVAL;
+    spgemm_options o;
+    if (opt) o = *opt; else spgemm_default_options(&o);
+    ST_TRY(check_options(o));
+    spgemm_plan *p = new (std::nothrow) spgemm_plan();
+    if (!p) return SPGEMM_ENOMEM;
+    p->stream = (hipStream_t)stream;
+    p->afn = alloc_fn;
+    p->ffn = free_fn;
+    p->actx = alloc_ctx;
+    p->opt = o;
+    p->batch = true;
+    spgemm_status s;
+    try {
+        s = device_plan_setup(p, nprod, A, B);
+    } catch (...) {
+        s = SPGEMM_ENOMEM;
+    }
+    if (s != SPGEMM_OK) {
+        spgemm_free(p);
+        return s;
+    }
+    *out = p;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_execute_arena(spgemm_plan *p, const float *const *a_values,
+                                   const float *const *b_values, int64_t *const *c_row_ptr,
+                                   int64_t *c_offsets, int32_t *c_col, float *c_val,
+                                   int64_t capacity) {
+    if (!p || !a_values || !b_values || !c_row_ptr || !c_offsets || capacity < 0)
+        return SPGEMM_EINVAL;
+    if (!p->device_driven) return SPGEMM_ESTATE;
+    if (capacity > 0 && (!c_col || !c_val)) return SPGEMM_EINVAL;
+    for (int q = 0; q < p->nprod; ++q) {
+        if (!c_row_ptr[q]) return SPGEMM_EINVAL;
+        if ((p->A[q].nnz > 0 && !a_values[q]) || (p->B[q].nnz > 0 && !b_values[q]))
+            return SPGEMM_EINVAL;
+        p->hprods[q].valA = a_values[q];
+        p->hprods[q].valB = b_values[q];
+        p->hprods[q].colC = c_col;
+        p->hprods[q].valC = c_val;
+        p->hprods[q].c_arena = 1;
+    }
+    ST_TRY(upload_descriptors(p));
+    if (!p->opt.graph || p->opt.profile) {
+        TimeScope ts(p, "device.all");
+        return device_launch_all(p, p->stream, c_row_ptr, c_offsets, capacity);
+    }
+    bool same = p->dev_graph && p->dev_off == c_offsets && p->dev_cap == capacity;
+    for (int q = 0; same && q < p->nprod; ++q) same = p->dev_rpt[q] == c_row_ptr[q];
+    if (!same) ST_TRY(capture_device(p, c_row_ptr, c_offsets, capacity));
+    HIP_TRY(hipGraphLaunch(p->dev_graph, p->stream));
+    return SPGEMM_OK;
+}
+
 spgemm_status spgemm_sync(spgemm_plan *p) {
     if (!p) return SPGEMM_EINVAL;
     HIP_TRY(hipGetLastError());
     int f[1];
     ST_TRY(read_flags(p, f, 1));
+    static const bool debug = std::getenv("SPGEMM_DEBUG") != nullptr;
+    if (debug && f[0]) std::fprintf(stderr, "spgemm: kernel error flags 0x%x\n", f[0]);
+    if (f[0] == kErrCapacity) return SPGEMM_ENOMEM;  // C did not fit the arena
     return f[0] ? SPGEMM_EINTERNAL : SPGEMM_OK;
 }
 
@@ -1171,6 +1374,7 @@ void spgemm_free(spgemm_plan *p) {
     if (!p) return;
     (void)hipStreamSynchronize(p->stream);
     if (p->num_graph) (void)hipGraphExecDestroy(p->num_graph);
+    if (p->dev_graph) (void)hipGraphExecDestroy(p->dev_graph);
     for (void *ptr : p->allocs) {
         if (p->ffn) p->ffn(p->actx, ptr, (void *)p->stream);
         else (void)hipFree(ptr);

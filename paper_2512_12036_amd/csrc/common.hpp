@@ -30,6 +30,7 @@ constexpr int kErrProbe = 1;         // hash probe sequence exceeded the table
 constexpr int kErrCount = 2;         // numeric count != symbolic count
 constexpr int kErrChunk = 4;         // chunk count != symbolic chunk count
 constexpr int kErrRow = 8;           // group-kernel row exceeds group capacity
+constexpr int kErrCapacity = 16;     // C does not fit the caller's arena (nothing written)
 
 // One product C = A * B as seen by the kernels.
 struct ProdDev {
@@ -47,7 +48,8 @@ struct ProdDev {
     int32_t W;          // columns per chunk
     int32_t nch;        // chunks per row (multiple of 8)
     int32_t b_sorted;   // rows of B strictly ascending: 1 yes, 0 no, 2 detect
-    int32_t pad;
+    int32_t c_arena;    // 1: colC / valC are one arena shared by the batch, indexed by
+                        // the batch-wide row pointers (device-driven plans)
 };
 
 // One work item of group 7: the chunks q, q + Q, ... (K of them) of one row,
@@ -96,6 +98,33 @@ struct ProdStats {
     unsigned long long h_tiles;   // sum of ceil(alen / kSabsJ) over symbolic group-7 rows
     unsigned long long pad[5];
 };
+
+// First output slot of batch row g in its product's C arrays.
+__device__ __forceinline__ int64_t c_base(const ProdDev &P, const int64_t *rptv, int64_t g) {
+    return P.c_arena ? rptv[g] : rptv[g] - rptv[P.row_base];
+}
+
+// Device-driven launches cover an upper bound of a group's rows and read the
+// group's place in the row map from the device (gstart[gsel .. gsel + 1]).
+__device__ __forceinline__ void group_range(const int64_t *gstart, int gsel,
+                                            const uint64_t *__restrict__ &items, int64_t &count) {
+    if (gstart) {
+        const int64_t b = gstart[gsel];
+        items += b;
+        count = gstart[gsel + 1] - b;
+    }
+}
+
+// Rows of a device-driven batch: its group launches cover every row.
+constexpr int64_t kMaxDeviceRows = (int64_t(1) << 32) / 64 - 1;
+
+// The block kernels' device-sized launches take rows one at a time from a
+// work counter kWorkCtr entries after the group's start (zeroed before the
+// launch), so a long row holds up no rows behind it.
+constexpr int kWorkCtr = 2 * (kGroups + 1);
+__device__ __forceinline__ int64_t take_block(const int64_t *gstart, int gsel) {
+    return (int64_t)atomicAdd((unsigned long long *)(gstart + kWorkCtr + gsel), 1ull);
+}
 
 __device__ __forceinline__ uint64_t pack_item(int p, int64_t i) {
     return ((uint64_t)(uint32_t)p << 32) | (uint64_t)(uint32_t)i;
@@ -174,19 +203,28 @@ void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t
                      const int64_t *cbase, const int64_t *sbase, const int64_t *rptv,
                      const int32_t *mstart, const int64_t *nlim, ChunkDesc *desc, hipStream_t s);
 
+// With gstart (device), `count` is an upper bound of the group's rows and
+// the kernels take the group's range of the map from gstart[gsel .. gsel+1].
 void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items,
-                      int64_t count, int64_t *row_nnz, int *err, hipStream_t s);
+                      int64_t count, int64_t *row_nnz, int *err, hipStream_t s,
+                      const int64_t *gstart = nullptr, int gsel = 0);
 void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       const int64_t *ipv, int64_t count, int64_t *row_nnz, int *err,
-                      hipStream_t s);
+                      hipStream_t s, const int64_t *gstart = nullptr, int gsel = 0);
 void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
                       int64_t *row_nnz, uint32_t *sbits, int wpc, int wgs_per_cu, int threads,
                       int *err, hipStream_t s);
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
-                      int64_t count, const int64_t *rptv, int *err, hipStream_t s);
+                      int64_t count, const int64_t *rptv, int *err, hipStream_t s,
+                      const int64_t *gstart = nullptr, int gsel = 0);
 void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
-                      int64_t count, const int64_t *rptv, int *err, hipStream_t s);
+                      int64_t count, const int64_t *rptv, int *err, hipStream_t s,
+                      const int64_t *gstart = nullptr, int gsel = 0);
+// Device-driven plans: kErrCapacity when the batch's nnz(C) exceeds the
+// arena; each product's first slot in the arena (nprod + 1 entries).
+void launch_arena_check(const int64_t *rptv, int64_t mtot, int64_t capacity, int *err,
+                        const ProdDev *prods, int nprod, int64_t *offsets, hipStream_t s);
 void launch_num_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc *desc,
                       const uint32_t *sabs, int64_t nitems, int kper, const int64_t *chunk_cnt,
                       const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int wgs_per_cu,

@@ -279,7 +279,7 @@ __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__
     ChunkDesc d;
     d.a0 = P.rptA[i];
     d.alen = (int32_t)(P.rptA[i + 1] - d.a0);
-    d.out0 = rptv[g] - rptv[P.row_base];
+    d.out0 = c_base(P, rptv, g);
     d.prod = p;
     const int64_t h = hslot[g];
     d.slot0 = cbase[h];

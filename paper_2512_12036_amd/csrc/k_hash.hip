@@ -231,11 +231,12 @@ __device__ __forceinline__ void group_products(const ProdDev &P, int64_t i, int 
     }
 }
 
+// The rows blk * R .. blk * R + R - 1 of the group (one block's share).
 template <int G>
-__global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ prods,
-                                                    const uint64_t *__restrict__ items,
-                                                    int64_t count, int64_t *__restrict__ row_nnz,
-                                                    int *__restrict__ err) {
+__device__ __forceinline__ void sym_group_rows(const ProdDev *__restrict__ prods,
+                                               const uint64_t *__restrict__ items, int64_t count,
+                                               int64_t *__restrict__ row_nnz,
+                                               int *__restrict__ err, int64_t blk) {
     constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v;
     __shared__ int keys[R * T];
     __shared__ int64_t st_s[256];
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     for (int s = threadIdx.x; s < R * T; s += 256) keys[s] = kEmptyKey;
     __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
-    const int64_t it = (int64_t)blockIdx.x * R + gi;
+    const int64_t it = blk * R + gi;
     if (it >= count) return;  // group-uniform; no block barrier follows
     const uint64_t e = items[it];
     const ProdDev &P = prods[item_prod(e)];
@@ -261,11 +262,30 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     if (lane == 0) row_nnz[P.row_base + i] = cnt;
 }
 
-template <int G>
-__global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ prods,
+// A workgroup takes the R rows of block blockIdx.x.  Host-sized launches
+// cover the group exactly; device-sized ones (DEV) cover an upper bound of
+// its rows, read the group's range from the device and exit past its end.
+// Empty workgroups cost a few hundred cycles, far less than a work counter
+// shared by a whole grid of short blocks.
+template <int G, bool DEV>
+__global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ prods,
                                                     const uint64_t *__restrict__ items,
-                                                    int64_t count, const int64_t *__restrict__ rptv,
-                                                    int *__restrict__ err) {
+                                                    int64_t count, int64_t *__restrict__ row_nnz,
+                                                    int *__restrict__ err,
+                                                    const int64_t *__restrict__ gstart, int gsel) {
+    constexpr int R = 256 / G;
+    if constexpr (DEV) {
+        group_range(gstart, gsel, items, count);
+        if ((int64_t)blockIdx.x * R >= count) return;  // block-uniform
+    }
+    sym_group_rows<G>(prods, items, count, row_nnz, err, blockIdx.x);
+}
+
+template <int G>
+__device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods,
+                                               const uint64_t *__restrict__ items, int64_t count,
+                                               const int64_t *__restrict__ rptv,
+                                               int *__restrict__ err, int64_t blk) {
     constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v, PER = T / G;
     __shared__ int keys[R * T];
     __shared__ float vals[R * (T + G)];  // per group: T slots + G dummy slots
@@ -276,7 +296,7 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     for (int s = threadIdx.x; s < R * (T + G); s += 256) vals[s] = 0.f;
     __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
-    const int64_t it = (int64_t)blockIdx.x * R + gi;
+    const int64_t it = blk * R + gi;
     const bool active = it < count;
     int *tab = keys + gi * T;
     float *tv = vals + gi * (T + G);
@@ -327,7 +347,7 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
     const int64_t expect = rptv[g + 1] - rptv[g];
     if (lane == 0 && n != expect) atomicOr(err, kErrCount);
     if (direct) {  // already in column order
-        const int64_t base = rptv[g] - rptv[P.row_base];
+        const int64_t base = c_base(P, rptv, g);
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             if (kk[r] != kEmptyKey) {
@@ -349,7 +369,7 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
 #pragma unroll
         for (int r = 0; r < PER; ++r) rank[r] += kf < kk[r];
     }
-    const int64_t base = rptv[g] - rptv[P.row_base];
+    const int64_t base = c_base(P, rptv, g);
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         if (kk[r] != kEmptyKey && rank[r] < expect) {
@@ -357,6 +377,21 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
             gst(P.valC + base + rank[r], vv[r]);
         }
     }
+}
+
+template <int G, bool DEV>
+__global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ prods,
+                                                    const uint64_t *__restrict__ items,
+                                                    int64_t count, const int64_t *__restrict__ rptv,
+                                                    int *__restrict__ err,
+                                                    const int64_t *__restrict__ gstart, int gsel) {
+    constexpr int R = 256 / G;
+    if constexpr (DEV) {
+        group_range(gstart, gsel, items, count);
+        if ((int64_t)blockIdx.x * R >= count) return;  // block-uniform
+        if (*err & kErrCapacity) return;  // C does not fit its arena (block-uniform)
+    }
+    num_group_rows<G>(prods, items, count, rptv, err, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,16 +427,16 @@ __device__ __forceinline__ void block_products(const ProdDev &P, int64_t i, int6
 }
 
 template <int WG, int TMAX>
-__global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ prods,
-                                                   const uint64_t *__restrict__ items,
-                                                   const int64_t *__restrict__ ipv,
-                                                   int64_t *__restrict__ row_nnz,
-                                                   int *__restrict__ err) {
+__device__ __forceinline__ void sym_block_row(const ProdDev *__restrict__ prods,
+                                              const uint64_t *__restrict__ items,
+                                              const int64_t *__restrict__ ipv,
+                                              int64_t *__restrict__ row_nnz,
+                                              int *__restrict__ err, int64_t it) {
     __shared__ int keys[TMAX];
     __shared__ int64_t st_s[WG];
     __shared__ int st_e[WG + 1];
     __shared__ int wsum[WG / 64];
-    const uint64_t e = items[blockIdx.x];
+    const uint64_t e = items[it];
     const ProdDev &P = prods[item_prod(e)];
     const int64_t i = item_row(e);
     const int64_t g = P.row_base + i;
@@ -429,11 +464,38 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
     if (threadIdx.x == 0) row_nnz[g] = tot;
 }
 
-template <int WG, int TMAX>
-__global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ prods,
+// One row per workgroup: row blockIdx.x, or (DEV) rows from the group's
+// work counter until the group is exhausted (the rows are long, so the
+// counter is touched rarely, while an upper bound of the group's rows would
+// be a grid of all the batch's rows).
+template <int WG, int TMAX, bool DEV>
+__global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ prods,
                                                    const uint64_t *__restrict__ items,
-                                                   const int64_t *__restrict__ rptv,
-                                                   int *__restrict__ err) {
+                                                   const int64_t *__restrict__ ipv,
+                                                   int64_t *__restrict__ row_nnz,
+                                                   int *__restrict__ err, int64_t count,
+                                                   const int64_t *__restrict__ gstart, int gsel) {
+    if constexpr (!DEV) {
+        sym_block_row<WG, TMAX>(prods, items, ipv, row_nnz, err, blockIdx.x);
+    } else {
+        group_range(gstart, gsel, items, count);
+        __shared__ int64_t next;
+        if (threadIdx.x == 0) next = take_block(gstart, gsel);
+        __syncthreads();
+        for (int64_t it = next; it < count; it = next) {
+            sym_block_row<WG, TMAX>(prods, items, ipv, row_nnz, err, it);
+            __syncthreads();  // table free again, and every thread has read `next`
+            if (threadIdx.x == 0) next = take_block(gstart, gsel);
+            __syncthreads();
+        }
+    }
+}
+
+template <int WG, int TMAX>
+__device__ __forceinline__ void num_block_row(const ProdDev *__restrict__ prods,
+                                              const uint64_t *__restrict__ items,
+                                              const int64_t *__restrict__ rptv,
+                                              int *__restrict__ err, int64_t it) {
     __shared__ int keys[TMAX];
     __shared__ float vals[TMAX + 64];
     __shared__ int64_t st_s[WG];
@@ -441,7 +503,7 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     __shared__ float st_a[WG];
     __shared__ int wsum[WG / 64];
     __shared__ int fill;
-    const uint64_t e = items[blockIdx.x];
+    const uint64_t e = items[it];
     const ProdDev &P = prods[item_prod(e)];
     const int64_t i = item_row(e);
     const int64_t g = P.row_base + i;
@@ -475,7 +537,7 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     if (direct) {
         // the occupied slots are the row's columns in order: a scan of the
         // occupancy places them, no compaction or sort
-        const int64_t base = rptv[g] - rptv[P.row_base];
+        const int64_t base = c_base(P, rptv, g);
         int done = 0;
         for (int r0 = 0; r0 < T; r0 += WG) {
             const int q = r0 + threadIdx.x;
@@ -538,7 +600,7 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
             __syncthreads();
         }
     }
-    const int64_t base = rptv[g] - rptv[P.row_base];
+    const int64_t base = c_base(P, rptv, g);
     const int nout = (int)(n < expect ? n : expect);
     for (int q = threadIdx.x; q < nout; q += WG) {
         gst(P.colC + base + q, keys[q]);
@@ -546,48 +608,90 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
     }
 }
 
+template <int WG, int TMAX, bool DEV>
+__global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ prods,
+                                                   const uint64_t *__restrict__ items,
+                                                   const int64_t *__restrict__ rptv,
+                                                   int *__restrict__ err, int64_t count,
+                                                   const int64_t *__restrict__ gstart, int gsel) {
+    if constexpr (!DEV) {
+        num_block_row<WG, TMAX>(prods, items, rptv, err, blockIdx.x);
+    } else {
+        group_range(gstart, gsel, items, count);
+        if (*err & kErrCapacity) return;  // C does not fit its arena (block-uniform)
+        __shared__ int64_t next;
+        if (threadIdx.x == 0) next = take_block(gstart, gsel);
+        __syncthreads();
+        for (int64_t it = next; it < count; it = next) {
+            num_block_row<WG, TMAX>(prods, items, rptv, err, it);
+            __syncthreads();  // table free again, and every thread has read `next`
+            if (threadIdx.x == 0) next = take_block(gstart, gsel);
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.  Group g: 1..4 -> G = 8, 16, 32, 64; 5 -> 256-thread block,
 // 6 -> 512-thread block.
 // ---------------------------------------------------------------------------
+// Host-sized launches cover the group exactly.  Device-sized ones (gstart)
+// cover an upper bound: the group kernels every row of the batch, the block
+// kernels a grid of kDeviceGridCap workgroups that take rows from the work
+// counter.
+constexpr int64_t kDeviceGridCap = 8192;  // 32 workgroups per compute unit
+
+template <typename K, typename... Args>
+static void launch_rows(K host, K dev, int64_t blocks, int64_t dev_blocks, int threads,
+                        hipStream_t s, const int64_t *gstart, Args... args) {
+    if (gstart)
+        hipLaunchKernelGGL(dev, dim3((unsigned)dev_blocks), dim3(threads), 0, s, args...);
+    else
+        hipLaunchKernelGGL(host, dim3((unsigned)blocks), dim3(threads), 0, s, args...);
+}
+
 template <int G>
 static void sym_group_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
-                             int64_t *row_nnz, int *err, hipStream_t s) {
+                             int64_t *row_nnz, int *err, hipStream_t s, const int64_t *gstart,
+                             int gsel) {
     constexpr int R = 256 / G;
     const int64_t nb = (count + R - 1) / R;
-    hipLaunchKernelGGL(k_sym_group<G>, dim3((unsigned)nb), dim3(256), 0, s, prods, items, count,
-                       row_nnz, err);
+    launch_rows(k_sym_group<G, false>, k_sym_group<G, true>, nb, nb, 256, s, gstart,
+                prods, items, count, row_nnz, err, gstart, gsel);
 }
 
 void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
-                      int64_t *row_nnz, int *err, hipStream_t s) {
+                      int64_t *row_nnz, int *err, hipStream_t s, const int64_t *gstart,
+                      int gsel) {
     if (count <= 0) return;
     switch (g) {
-        case 1: sym_group_launch<8>(prods, items, count, row_nnz, err, s); break;
-        case 2: sym_group_launch<16>(prods, items, count, row_nnz, err, s); break;
-        case 3: sym_group_launch<32>(prods, items, count, row_nnz, err, s); break;
-        case 4: sym_group_launch<64>(prods, items, count, row_nnz, err, s); break;
+        case 1: sym_group_launch<8>(prods, items, count, row_nnz, err, s, gstart, gsel); break;
+        case 2: sym_group_launch<16>(prods, items, count, row_nnz, err, s, gstart, gsel); break;
+        case 3: sym_group_launch<32>(prods, items, count, row_nnz, err, s, gstart, gsel); break;
+        case 4: sym_group_launch<64>(prods, items, count, row_nnz, err, s, gstart, gsel); break;
         default: break;
     }
 }
 
 template <int G>
 static void num_group_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
-                             const int64_t *rptv, int *err, hipStream_t s) {
+                             const int64_t *rptv, int *err, hipStream_t s, const int64_t *gstart,
+                             int gsel) {
     constexpr int R = 256 / G;
     const int64_t nb = (count + R - 1) / R;
-    hipLaunchKernelGGL(k_num_group<G>, dim3((unsigned)nb), dim3(256), 0, s, prods, items, count,
-                       rptv, err);
+    launch_rows(k_num_group<G, false>, k_num_group<G, true>, nb, nb, 256, s, gstart,
+                prods, items, count, rptv, err, gstart, gsel);
 }
 
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
-                      const int64_t *rptv, int *err, hipStream_t s) {
+                      const int64_t *rptv, int *err, hipStream_t s, const int64_t *gstart,
+                      int gsel) {
     if (count <= 0) return;
     switch (g) {
-        case 1: num_group_launch<8>(prods, items, count, rptv, err, s); break;
-        case 2: num_group_launch<16>(prods, items, count, rptv, err, s); break;
-        case 3: num_group_launch<32>(prods, items, count, rptv, err, s); break;
-        case 4: num_group_launch<64>(prods, items, count, rptv, err, s); break;
+        case 1: num_group_launch<8>(prods, items, count, rptv, err, s, gstart, gsel); break;
+        case 2: num_group_launch<16>(prods, items, count, rptv, err, s, gstart, gsel); break;
+        case 3: num_group_launch<32>(prods, items, count, rptv, err, s, gstart, gsel); break;
+        case 4: num_group_launch<64>(prods, items, count, rptv, err, s, gstart, gsel); break;
         default: break;
     }
 }
@@ -598,43 +702,60 @@ static int table_for(int64_t upper, int lo, int hi) {
     return t;
 }
 
+template <int WG, int TMAX>
+static void sym_block_launch(const ProdDev *prods, const uint64_t *items, const int64_t *ipv,
+                             int64_t count, int64_t *row_nnz, int *err, hipStream_t s,
+                             const int64_t *gstart, int gsel) {
+    launch_rows(k_sym_block<WG, TMAX, false>, k_sym_block<WG, TMAX, true>, count,
+                std::min(count, kDeviceGridCap), WG, s, gstart,
+                prods, items, ipv, row_nnz, err, count, gstart, gsel);
+}
+
+template <int WG, int TMAX>
+static void num_block_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
+                             const int64_t *rptv, int *err, hipStream_t s, const int64_t *gstart,
+                             int gsel) {
+    launch_rows(k_num_block<WG, TMAX, false>, k_num_block<WG, TMAX, true>, count,
+                std::min(count, kDeviceGridCap), WG, s, gstart,
+                prods, items, rptv, err, count, gstart, gsel);
+}
+
 // LDS tables are sized to the group's upper bound (twice the largest key,
 // a power of two), so a group tuned to small rows keeps a high occupancy.
 void launch_sym_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       const int64_t *ipv, int64_t count, int64_t *row_nnz, int *err,
-                      hipStream_t s) {
+                      hipStream_t s, const int64_t *gstart, int gsel) {
     if (count <= 0) return;
-    const dim3 grid((unsigned)count);
     if (g == 5) {
         switch (table_for(upper, 2048, 8192)) {
-            case 2048: hipLaunchKernelGGL((k_sym_block<256, 2048>), grid, dim3(256), 0, s, prods, items, ipv, row_nnz, err); break;
-            case 4096: hipLaunchKernelGGL((k_sym_block<256, 4096>), grid, dim3(256), 0, s, prods, items, ipv, row_nnz, err); break;
-            default: hipLaunchKernelGGL((k_sym_block<256, 8192>), grid, dim3(256), 0, s, prods, items, ipv, row_nnz, err); break;
+            case 2048: sym_block_launch<256, 2048>(prods, items, ipv, count, row_nnz, err, s, gstart, gsel); break;
+            case 4096: sym_block_launch<256, 4096>(prods, items, ipv, count, row_nnz, err, s, gstart, gsel); break;
+            default: sym_block_launch<256, 8192>(prods, items, ipv, count, row_nnz, err, s, gstart, gsel); break;
         }
     } else {
         switch (table_for(upper, 8192, 32768)) {
-            case 8192: hipLaunchKernelGGL((k_sym_block<512, 8192>), grid, dim3(512), 0, s, prods, items, ipv, row_nnz, err); break;
-            case 16384: hipLaunchKernelGGL((k_sym_block<512, 16384>), grid, dim3(512), 0, s, prods, items, ipv, row_nnz, err); break;
-            default: hipLaunchKernelGGL((k_sym_block<512, 32768>), grid, dim3(512), 0, s, prods, items, ipv, row_nnz, err); break;
+            case 8192: sym_block_launch<512, 8192>(prods, items, ipv, count, row_nnz, err, s, gstart, gsel); break;
+            case 16384: sym_block_launch<512, 16384>(prods, items, ipv, count, row_nnz, err, s, gstart, gsel); break;
+            default: sym_block_launch<512, 32768>(prods, items, ipv, count, row_nnz, err, s, gstart, gsel); break;
         }
     }
 }
 
 void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
-                      int64_t count, const int64_t *rptv, int *err, hipStream_t s) {
+                      int64_t count, const int64_t *rptv, int *err, hipStream_t s,
+                      const int64_t *gstart, int gsel) {
     if (count <= 0) return;
-    const dim3 grid((unsigned)count);
     if (g == 5) {
         switch (table_for(upper, 1024, 4096)) {
-            case 1024: hipLaunchKernelGGL((k_num_block<256, 1024>), grid, dim3(256), 0, s, prods, items, rptv, err); break;
-            case 2048: hipLaunchKernelGGL((k_num_block<256, 2048>), grid, dim3(256), 0, s, prods, items, rptv, err); break;
-            default: hipLaunchKernelGGL((k_num_block<256, 4096>), grid, dim3(256), 0, s, prods, items, rptv, err); break;
+            case 1024: num_block_launch<256, 1024>(prods, items, count, rptv, err, s, gstart, gsel); break;
+            case 2048: num_block_launch<256, 2048>(prods, items, count, rptv, err, s, gstart, gsel); break;
+            default: num_block_launch<256, 4096>(prods, items, count, rptv, err, s, gstart, gsel); break;
         }
     } else {
         switch (table_for(upper, 4096, 16384)) {
-            case 4096: hipLaunchKernelGGL((k_num_block<512, 4096>), grid, dim3(512), 0, s, prods, items, rptv, err); break;
-            case 8192: hipLaunchKernelGGL((k_num_block<512, 8192>), grid, dim3(512), 0, s, prods, items, rptv, err); break;
-            default: hipLaunchKernelGGL((k_num_block<512, 16384>), grid, dim3(512), 0, s, prods, items, rptv, err); break;
+            case 4096: num_block_launch<512, 4096>(prods, items, count, rptv, err, s, gstart, gsel); break;
+            case 8192: num_block_launch<512, 8192>(prods, items, count, rptv, err, s, gstart, gsel); break;
+            default: num_block_launch<512, 16384>(prods, items, count, rptv, err, s, gstart, gsel); break;
         }
     }
 }

@@ -538,6 +538,21 @@ void launch_ip_estimate(const int64_t *rptA, const int32_t *colA, const int64_t 
                        colA, rptB, m, ncols, (unsigned long long *)out);
 }
 
+__global__ void k_arena_check(const int64_t *__restrict__ rptv, int64_t mtot, int64_t capacity,
+                              int *__restrict__ err, const ProdDev *__restrict__ prods, int nprod,
+                              int64_t *__restrict__ offsets) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0 && rptv[mtot] > capacity) atomicOr(err, kErrCapacity);
+    if (q < nprod) offsets[q] = rptv[prods[q].row_base];
+    if (q == nprod) offsets[q] = rptv[mtot];
+}
+
+void launch_arena_check(const int64_t *rptv, int64_t mtot, int64_t capacity, int *err,
+                        const ProdDev *prods, int nprod, int64_t *offsets, hipStream_t s) {
+    hipLaunchKernelGGL(k_arena_check, dim3((unsigned)((nprod + 1 + 255) / 256)), dim3(256), 0, s,
+                       rptv, mtot, capacity, err, prods, nprod, offsets);
+}
+
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m, int64_t *dst,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_rows_local, dim3((unsigned)((m + 256) / 256)), dim3(256), 0, s, rptv,

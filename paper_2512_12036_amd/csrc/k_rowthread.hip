@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64) void k_num_rowthread(const ProdDev *__restrict_
             ++n;
         }
     }
-    const int64_t base = rptv[P.row_base + i] - rptv[P.row_base];
+    const int64_t base = c_base(P, rptv, P.row_base + i);
     if ((int64_t)n != rptv[P.row_base + i + 1] - rptv[P.row_base + i]) {
         atomicOr(err, kErrCount);
         return;

@@ -14,6 +14,11 @@ their own HIP streams, so the numeric phase of one batch overlaps the planning
 of the next, and requests that arrive while others are on the GPU join the
 next batch (continuous batching).
 
+With device_driven, a batch is a device-driven plan (spgemm_plan_create_device
+and spgemm_execute_arena): the whole batch runs with no host synchronisation,
+C in one arena sized by the requests' nnz bounds, and the host only reads the
+batch's error flags and output offsets once it has completed.
+
 Admission control: each request carries an upper bound of its device
 footprint, taken before it is admitted: the plan workspace bound
 (``workspace_bound``, from the plan's allocations), C's arrays at the bound
@@ -54,6 +59,7 @@ class Request:
     bound_bytes: int = 0           # admission bound of the device footprint
     make_b: Callable | None = None  # builds B on the current stream
     b_bytes: int = 0               # device bytes of B when built on admission
+    nnz_bound: int = 0             # sum over rows of min(IP, ncols) >= nnz(C)
 
 
 @dataclasses.dataclass
@@ -117,8 +123,9 @@ class Server:
     def __init__(self, budget_bytes: int = 200 * 10 ** 9, max_batch: int = 64,
                  max_batch_ip: int = 8 << 30, n_streams: int = 4,
                  options: spgemm.Options | None = None, keep_results: bool = False,
-                 device="cuda"):
+                 device="cuda", device_driven: bool = False):
         import torch
+        self.device_driven = device_driven
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.max_batch_ip = max_batch_ip
@@ -161,6 +168,13 @@ class Server:
             nonlocal in_use
             fl["plan"].sync()          # raises on a kernel error flag
             fl["plan"].free()
+            if "arena" in fl:          # device-driven: each request's slice of the arena
+                rpts, off, col, val = fl.pop("arena")
+                o = off.cpu().tolist()
+                fl["rpts"] = rpts
+                fl["nnz"] = [o[k + 1] - o[k] for k in range(len(fl["reqs"]))]
+                fl["cols"] = [col[o[k]:o[k + 1]] for k in range(len(fl["reqs"]))]
+                fl["vals"] = [val[o[k]:o[k + 1]] for k in range(len(fl["reqs"]))]
             for k, r in enumerate(fl["reqs"]):
                 keep = kept(r.rid)
                 done.append(Done(r.rid, fl["rpts"][k] if keep else None,
@@ -209,12 +223,27 @@ class Server:
                     in_use += need
                     peak = max(peak, in_use)
                     t_admit = time.perf_counter() - t0
+                    arena = None
                     with torch.cuda.stream(s):
                         bs = [r.b if r.b is not None else r.make_b() for r in batch]
-                        plan = spgemm.Plan([r.a for r in batch], bs, self.options, s)
-                        nnz = plan.symbolic()
-                        cols, vals = plan.allocate_outputs()
-                        plan.numeric(cols, vals)
+                        if self.device_driven:
+                            # no host synchronisation: C of the whole batch in
+                            # one arena sized by the requests' nnz bounds
+                            plan = spgemm.DevicePlan([r.a for r in batch], bs, self.options, s)
+                            cap = sum(r.nnz_bound for r in batch)
+                            rpts = [torch.empty(r.a.nrows + 1, dtype=torch.int64, device=s.device)
+                                    for r in batch]
+                            off = torch.empty(len(batch) + 1, dtype=torch.int64, device=s.device)
+                            col = torch.empty(max(cap, 1), dtype=torch.int32, device=s.device)
+                            val = torch.empty(max(cap, 1), dtype=torch.float32, device=s.device)
+                            plan.execute(rpts, off, col[:cap], val[:cap])
+                            arena = (rpts, off, col, val)
+                            nnz = [r.nnz_bound for r in batch]
+                        else:
+                            plan = spgemm.Plan([r.a for r in batch], bs, self.options, s)
+                            nnz = plan.symbolic()
+                            cols, vals = plan.allocate_outputs()
+                            plan.numeric(cols, vals)
                         ev = torch.cuda.Event(enable_timing=True)
                         ev.record(s)
                     exact = plan.info().workspace_bytes + sum(
@@ -224,13 +253,19 @@ class Server:
                     batch_bytes.append((need, exact))
                     in_use += held - need
                     peak = max(peak, in_use)
-                    fl = dict(plan=plan, reqs=batch, rpts=plan.rpts, cols=cols, vals=vals,
-                              nnz=nnz, event=ev, t_admit=t_admit, batch=nbatch, bs=bs)
+                    if arena is not None:
+                        fl = dict(plan=plan, reqs=batch, arena=arena, event=ev,
+                                  t_admit=t_admit, batch=nbatch, bs=bs)
+                    else:
+                        fl = dict(plan=plan, reqs=batch, rpts=plan.rpts, cols=cols, vals=vals,
+                                  nnz=nnz, event=ev, t_admit=t_admit, batch=nbatch, bs=bs)
                     fl_bytes[id(fl)] = held
                     stream_of[id(fl)] = si
                     inflight.append(fl)
                     nbatch += 1
-                    del bs, cols, vals, plan
+                    del bs, plan, arena
+                    if not self.device_driven:
+                        del cols, vals
                     continue
             if inflight:
                 if pending and not waiting:
@@ -352,7 +387,7 @@ def gnn_requests(seeds, device="cuda", features_on_admission: bool = False,
         est = estimate_many(pairs, device)
         for (rid, a, x, make, b_bytes, f, n), (ip, nnz_bound) in zip(items, est):
             out.append(Request(rid, a, x, 0.0, ip, footprint(a, n, f, ip, nnz_bound, b_bytes),
-                               make, b_bytes))
+                               make, b_bytes, nnz_bound))
         del pairs
         if log is not None:
             log(f"[serve] {len(out)} / {len(seeds)} requests generated")

@@ -62,7 +62,8 @@ EXPORTED = ["spgemm_default_options", "spgemm_plan_create", "spgemm_plan_create_
             "spgemm_estimate", "spgemm_noalloc_scratch_bytes", "spgemm_multiply_noalloc",
             "spgemm_mcl_change", "spgemm_components_workspace", "spgemm_components",
             "spgemm_topk_rows", "spgemm_csr_to_dense", "spgemm_gemm_f32", "spgemm_masked_spmm",
-            "spgemm_transpose_workspace", "spgemm_transpose", "spgemm_its_sample"]
+            "spgemm_transpose_workspace", "spgemm_transpose", "spgemm_its_sample",
+            "spgemm_plan_create_device", "spgemm_execute_arena"]
 
 
 class SpgemmError(RuntimeError):
@@ -142,6 +143,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spgemm_transpose_workspace.restype = ctypes.c_size_t
     lib.spgemm_transpose.argtypes = [_I64, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]
     lib.spgemm_its_sample.argtypes = [_I64, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
+    lib.spgemm_plan_create_device.argtypes = [pp, ctypes.c_int32, ctypes.POINTER(CsrDesc),
+                                              ctypes.POINTER(CsrDesc), ctypes.POINTER(Options),
+                                              _VP, ALLOC_FN, FREE_FN, _VP]
+    lib.spgemm_execute_arena.argtypes = [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                         ctypes.POINTER(_VP), _VP, _VP, _VP, _I64]
     for name in ("spgemm_plan_create", "spgemm_plan_create_batch", "spgemm_symbolic",
                  "spgemm_symbolic_batch", "spgemm_numeric", "spgemm_numeric_batch",
                  "spgemm_sync", "spgemm_get_info", "spgemm_export", "spgemm_selector_transpose",
@@ -223,8 +229,13 @@ class _TorchAllocator:
             except Exception:
                 return None
 
+        delete = torch.cuda.caching_allocator_delete
+
         def _free(ctx, ptr, stream):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                delete(ptr)
+            except (AttributeError, TypeError):
+                pass  # interpreter shutdown: torch's modules are gone already
 
         self.alloc = ALLOC_FN(_alloc)
         self.free = FREE_FN(_free)
@@ -644,3 +655,62 @@ def its_sample(p: DeviceCsr, s: int, u, self_v, stream=None):
                                     _ptr(p.val), _ptr(u), _ptr(self_v), _VP(out.data_ptr()),
                                     _st(p.rpt.device, stream)), "spgemm_its_sample")
     return out[:p.nrows * s]
+
+
+class DevicePlan:
+    """A device-driven batch plan (spgemm_plan_create_device): the whole
+    product runs with no host synchronisation, C in one arena."""
+
+    def __init__(self, As, Bs, options: Options | None = None, stream=None):
+        torch = _torch()
+        lib = load()
+        self._lib = lib
+        self.As, self.Bs = list(As), list(Bs)
+        dev = self.As[0].rpt.device
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._alloc = _TorchAllocator(dev)
+        self._handle = _VP()
+        n = len(self.As)
+        da = (CsrDesc * n)(*[a.desc(False) for a in self.As])
+        db = (CsrDesc * n)(*[b.desc(False) for b in self.Bs])
+        opt = options if options is not None else default_options()
+        _check(lib.spgemm_plan_create_device(ctypes.byref(self._handle), n, da, db,
+                                             ctypes.byref(opt), _VP(self.stream.cuda_stream),
+                                             self._alloc.alloc, self._alloc.free, None),
+               "spgemm_plan_create_device")
+
+    def execute(self, rpts, offsets, col, val, a_vals=None, b_vals=None):
+        """Enqueues the whole product into caller tensors: rpts (one int64
+        tensor of A_p.nrows + 1 per product), offsets (int64, nprod + 1),
+        the arena col (int32) / val (float32) of equal capacity."""
+        n = len(self.As)
+        a_vals = a_vals if a_vals is not None else [a.val for a in self.As]
+        b_vals = b_vals if b_vals is not None else [b.val for b in self.Bs]
+        cap = int(col.numel())
+        _check(self._lib.spgemm_execute_arena(
+            self._handle, (_VP * n)(*[t.data_ptr() for t in a_vals]),
+            (_VP * n)(*[t.data_ptr() for t in b_vals]),
+            (_VP * n)(*[r.data_ptr() for r in rpts]), _VP(offsets.data_ptr()),
+            _VP(col.data_ptr()) if cap else None, _VP(val.data_ptr()) if cap else None, cap),
+            "spgemm_execute_arena")
+
+    def sync(self):
+        _check(self._lib.spgemm_sync(self._handle), "spgemm_sync")
+
+    def info(self) -> Info:
+        return Plan.info(self)
+
+    def timings(self):
+        return Plan.timings(self)
+
+    def free(self):
+        if self._handle:
+            self._lib.spgemm_free(self._handle)
+            self._handle = _VP()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

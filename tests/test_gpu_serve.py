@@ -183,3 +183,26 @@ def test_device_feature_generator_matches_host():
         assert torch.equal(xd.rpt.cpu(), xh.rpt)
         assert torch.equal(xd.col.cpu(), xh.col)
         assert torch.equal(xd.val.cpu(), xh.val)
+
+
+def test_device_driven_server_same_results():
+    """Batches as device-driven plans (no host synchronisation, C in one
+    arena per batch): every result equals the oracle and the ordinary
+    server's, request by request."""
+    reqs = []
+    for k in range(12):
+        n, d, f, rho = gen.gnn_request_params(900 + k, n_lo=300, n_hi=4000)
+        reqs += serve.gnn_requests([900 + k], "cuda", features_on_admission=True,
+                                   n=n, d=d, f=f, rho=rho)
+        reqs[-1].rid = k
+    stats, done = serve.Server(budget_bytes=4 << 30, max_batch=4, n_streams=2,
+                               keep_results=True, device_driven=True).run(reqs)
+    assert stats["requests"] == len(reqs)
+    for bound, exact in stats["batch_bytes"]:
+        assert exact <= bound, (exact, bound)
+    for d in done:
+        r = reqs[d.rid]
+        ref = oracle.product(r.a.to_host(), d.b.to_host())
+        assert d.nnz == ref.nnz
+        assert oracle.compare(ref, d.rpt.cpu().numpy(), d.col.cpu().numpy(),
+                              d.val.cpu().numpy()) is None, d.rid
