@@ -124,7 +124,7 @@ def test_device_plan_row_limit():
     h = ctypes.c_void_p()
     st = lib.spgemm_plan_create_device(ctypes.byref(h), 2, da, db, None,
                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
-                                       None, None, None)
+                                       spgemm.ALLOC_FN(), spgemm.FREE_FN(), None)
     assert st == 4 and not h.value  # SPGEMM_EOVERFLOW, no plan
 
 
