@@ -268,6 +268,39 @@ def dominant_roofline(per_launch, avg, units, chunk_cols=None):
     return roofline_entry(dom, per_launch[dom], alg_bytes_of(dom, units), traffic, kernel)
 
 
+# Counter calibration (--calib-copy-mib): kernels of known HBM traffic, run
+# before the steps so that a counter pass sees them beside the kernels it
+# measures.  Their buffers are far larger than the 256 MB last-level cache.
+#  * a plain copy of CALIB MiB: CALIB MiB read, CALIB MiB written;
+#  * a 4 GiB float32 buffer read at a 64-byte stride (one float of every
+#    64-byte segment, a float32 strided copy): every segment, so every byte
+#    of the buffer, is fetched; 256 MiB written;
+#  * the same buffer as int32 at a 128-byte stride (an int32 strided copy):
+#    one word per 128-byte line, so 2 GiB fetched if lines are fetched in
+#    64-byte halves and 4 GiB if whole; 128 MiB written.
+CALIB_GATHER_BYTES = 4 << 30
+
+
+def calibration_kernels(copy_mib, dev):
+    import torch
+    n = copy_mib * (1 << 20) // 4
+    src = torch.rand(n, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    g = torch.rand(CALIB_GATHER_BYTES // 4, device=dev)
+    torch.cuda.synchronize()
+    s64 = g.view(-1, 16)[:, 0].contiguous()
+    torch.cuda.synchronize()
+    s128 = g.view(torch.int32).view(-1, 32)[:, 0].contiguous()
+    torch.cuda.synchronize()
+    del g, s64, s128
+    torch.cuda.empty_cache()
+    log(f"[bench] calibration copy of {copy_mib} MiB and strided reads of 4 GiB done")
+
+
 def run_rmat18(args):
     import torch
     from paper_2512_12036_amd import spgemm
@@ -278,15 +311,7 @@ def run_rmat18(args):
     da = spgemm.to_device(a, dev)
     torch.cuda.synchronize()
     if args.calib_copy_mib:
-        # a plain copy of known size: the scale for the HBM byte counters
-        n = args.calib_copy_mib * (1 << 20) // 4
-        src = torch.rand(n, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+        calibration_kernels(args.calib_copy_mib, dev)
     r = measure_product(da, da, args.steps, args.warmup, "R-MAT 18")
     info, avg, per_launch = r["info"], r["avg"], r["per_launch"]
     ms = r["ms"]
@@ -625,6 +650,238 @@ def run_served(n_req: int, configs):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Reduction of the counter passes (rocprofv3 --pmc, csv output) of
+#   bench.py --steps 1 --warmup 0 --no-cpu --serve-requests 0 --no-configs
+#            --calib-copy-mib 1024
+# into profiles/num_chunk_rmat18_hbm_traffic.md and the traffic file.
+COUNTER_PASSES = {
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE"],
+    "req": ["TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+            "TCC_EA0_RDREQ_128B_sum"],
+    "tcc": ["TCC_BUBBLE_sum", "TCC_HIT_sum", "TCC_MISS_sum", "TCC_EA0_RDREQ_DRAM_sum"],
+    "td": ["TD_TD_BUSY_sum", "TA_TA_BUSY_sum", "GRBM_GUI_ACTIVE"],
+}
+NUM_G7_PREFIXES = ("spg::k_num_chunk_pipe", "spg::k_num_chunk_rank")
+
+
+def _read_counter_pass(folder):
+    """{dispatch id: {"name", "grid", "ns", counter: value}} of one pass."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                d = out.setdefault(int(r["Dispatch_Id"]), {
+                    "name": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                    "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+                d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def _short_name(name):
+    n = name.replace("spg::", "").replace("void ", "")
+    return n.split("(")[0]
+
+
+def summarize_counters(root, copy_mib):
+    passes = {k: _read_counter_pass(os.path.join(root, k)) for k in COUNTER_PASSES}
+    # every pass ran the same program: dispatches line up by order
+    order = {k: sorted(v) for k, v in passes.items()}
+    n = min(len(v) for v in order.values())
+    names = [passes["fetch"][order["fetch"][i]]["name"] for i in range(n)]
+    for k in passes:
+        for i in range(n):
+            if passes[k][order[k][i]]["name"] != names[i]:
+                raise SystemExit(f"pass {k} dispatch {i} is {passes[k][order[k][i]]['name']}, "
+                                 f"not {names[i]}")
+
+    def rec(i):
+        r = {"name": names[i], "ns": passes["td"][order["td"][i]]["ns"]}
+        for k in passes:
+            r.update({c: v for c, v in passes[k][order[k][i]].items()
+                      if c not in ("name", "grid", "ns")})
+        r["grid"] = passes["fetch"][order["fetch"][i]]["grid"]
+        return r
+
+    recs = [rec(i) for i in range(n)]
+    # calibration: the largest copyBuffer dispatch, then the first two
+    # elementwise copies after it (float 64-byte stride, int 128-byte stride)
+    ci = max((i for i in range(n) if "copyBuffer" in recs[i]["name"]),
+             key=lambda i: recs[i]["FETCH_SIZE"])
+    # PyTorch cuts each strided copy into launches of 32-bit offsets: merge the
+    # consecutive launches of one kernel and grid
+    strided = []
+    for i in range(ci + 1, n):
+        if "copy" not in recs[i]["name"] or "rocclr" in recs[i]["name"]:
+            continue
+        if strided and strided[-1][-1] == i - 1 and recs[i - 1]["grid"] == recs[i]["grid"] \
+                and recs[i - 1]["name"] == recs[i]["name"]:
+            strided[-1].append(i)
+        elif len(strided) < 2:
+            strided.append([i])
+        else:
+            break
+    for grp in strided:
+        merged = dict(recs[grp[0]])
+        for i in grp[1:]:
+            for c, v in recs[i].items():
+                if isinstance(v, float):
+                    merged[c] += v
+        merged["launches"] = len(grp)
+        recs.append(merged)
+    strided = [len(recs) - len(strided) + k for k in range(len(strided))]
+    copy_b = copy_mib << 20
+    gather_b = [CALIB_GATHER_BYTES, CALIB_GATHER_BYTES]
+
+    def req_bytes(r):
+        return (32 * r["TCC_EA0_RDREQ_32B_sum"] + 64 * r["TCC_EA0_RDREQ_64B_sum"]
+                + 128 * r["TCC_EA0_RDREQ_128B_sum"])
+
+    fscale = copy_b / (recs[ci]["FETCH_SIZE"] * 1024)
+    wscale = copy_b / (recs[ci]["WRITE_SIZE"] * 1024)
+    lines = ["# HBM traffic of the dominant kernel, R-MAT scale 18 self-product", "",
+             "Five counter passes, each its own run of the same program (one step of the "
+             "R-MAT 18 product after the calibration kernels):", ""]
+    for k, ctrs in COUNTER_PASSES.items():
+        lines.append(f"    cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc "
+                     f"{' '.join(ctrs)} -d <out>/{k} -o run --output-format csv -- python3 "
+                     f"/root/repo/bench.py --steps 1 --warmup 0 --no-cpu --serve-requests 0 "
+                     f"--no-configs --calib-copy-mib {copy_mib}")
+    lines += ["", "reduced by", "",
+              f"    python3 bench.py --summarize-counters <out> --calib-copy-mib {copy_mib}", "",
+              "## Calibration", "",
+              "FETCH_SIZE is defined as (128 TCC_BUBBLE + 64 (TCC_EA0_RDREQ - TCC_BUBBLE - "
+              "TCC_EA0_RDREQ_32B) + 32 TCC_EA0_RDREQ_32B) / 1024 KiB.  The request-size column "
+              "counts the read requests the L2 sends to memory by their size instead: "
+              "32 RDREQ_32B + 64 RDREQ_64B + 128 RDREQ_128B bytes.", "",
+              "| calibration kernel | known read | known write | FETCH_SIZE | request sizes "
+              "(32/64/128 B) | read by request size | TCC_BUBBLE | WRITE_SIZE |",
+              "|---|---|---|---|---|---|---|---|"]
+    cal = [("plain copy, 1 GiB", ci, copy_b, copy_b)]
+    if len(strided) == 2:
+        cal += [("4 GiB read at a 64-byte stride (float32)", strided[0], gather_b[0],
+                 CALIB_GATHER_BYTES // 16),
+                ("4 GiB read at a 128-byte stride (int32)", strided[1], None,
+                 CALIB_GATHER_BYTES // 32)]
+    for label, i, rd, wr in cal:
+        r = recs[i]
+        nl = r.get("launches", 1)
+        lines.append(
+            f"| {label} (`{_short_name(r['name'])[:48]}...`"
+            f"{', %d launches' % nl if nl > 1 else ''}) | "
+            f"{'%.2f GiB' % (rd / 2**30) if rd else '2 or 4 GiB'} | {wr / 2**20:.0f} MiB | "
+            f"{r['FETCH_SIZE'] / 2**20:.3f} GiB | {r['TCC_EA0_RDREQ_32B_sum']:.0f} / "
+            f"{r['TCC_EA0_RDREQ_64B_sum']:.0f} / {r['TCC_EA0_RDREQ_128B_sum']:.0f} | "
+            f"{req_bytes(r) / 2**30:.3f} GiB | {r['TCC_BUBBLE_sum']:.0f} | "
+            f"{r['WRITE_SIZE'] / 2**20:.3f} GiB |")
+    lines += ["", f"Copy-based scale factors: fetch {fscale:.4f}, write {wscale:.4f}.", "",
+              "Why the fetch factor is 2: on this GPU the L2 sends its reads to memory as "
+              "128-byte requests, counted by TCC_EA0_RDREQ_128B, while TCC_BUBBLE, the term "
+              "FETCH_SIZE's formula weights by 128 bytes, reads 0; every 128-byte request is "
+              "then counted as 64 bytes.  The copy and both strided reads are (nearly) all "
+              "128-byte requests, so FETCH_SIZE reads half their traffic.  The int32 read at "
+              "a 128-byte stride fetches 4 GiB for 128 MiB of data: the L2 fetches whole "
+              "128-byte lines.  The measured kernels' requests are 128-byte too (above 99.9 % "
+              "of them), so the copy-scaled FETCH_SIZE and the request-size count agree for "
+              "them (below).  WRITE_SIZE needs no scale (64-byte write requests, counted "
+              "right).  'DRAM read requests' are those sent towards memory; the 256 MB "
+              "last-level cache sits on that path, so part of them is served there.", ""]
+    # the numeric chunk group
+    g7 = [r for r in recs[:n] if r["name"].replace("void ", "").startswith(NUM_G7_PREFIXES)]
+    lines += ["## The numeric chunk group (num.g7)", "",
+              "| kernel | ms | FETCH_SIZE x scale | read by request size | WRITE_SIZE x scale | "
+              "L2 hit | DRAM read requests / all | TD busy | TA busy |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    tot = dict(fetch=0.0, req=0.0, write=0.0, ns=0)
+    for r in g7:
+        f_b = r["FETCH_SIZE"] * 1024 * fscale
+        w_b = r["WRITE_SIZE"] * 1024 * wscale
+        q_b = req_bytes(r)
+        hit = r["TCC_HIT_sum"] / max(1.0, r["TCC_HIT_sum"] + r["TCC_MISS_sum"])
+        dram = r["TCC_EA0_RDREQ_DRAM_sum"] / max(1.0, r["TCC_EA0_RDREQ_sum"])
+        cyc = r["GRBM_GUI_ACTIVE"] / 8  # summed over the 8 dies: busy clocks of one
+        td = r["TD_TD_BUSY_sum"] / max(1.0, cyc * 256)
+        ta = r["TA_TA_BUSY_sum"] / max(1.0, cyc * 256)
+        tot["fetch"] += f_b
+        tot["req"] += q_b
+        tot["write"] += w_b
+        tot["ns"] += r["ns"]
+        lines.append(f"| `{_short_name(r['name'])}` | {r['ns'] / 1e6:.3f} | {f_b / 1e9:.2f} GB | "
+                     f"{q_b / 1e9:.2f} GB | {w_b / 1e9:.2f} GB | {100 * hit:.1f} % | "
+                     f"{100 * dram:.1f} % | {100 * td:.0f} % | {100 * ta:.0f} % |")
+    lines += ["", f"Per launch of the group: {tot['fetch'] / 1e9:.2f} GB fetched (copy-scaled "
+                  f"FETCH_SIZE) or {tot['req'] / 1e9:.2f} GB (request sizes), "
+                  f"{tot['write'] / 1e9:.2f} GB written.  TD and TA busy: the counters summed "
+                  f"over the 256 compute units, divided by 256 times the dispatch's busy "
+                  f"clocks (GRBM_GUI_ACTIVE, which sums the 8 dies' clocks: it reads about "
+                  f"19 per ns, 8 x 2.4 GHz, so it is divided by 8).  For scale, the 1 GiB "
+                  f"copy keeps TD busy {100 * recs[ci]['TD_TD_BUSY_sum'] / max(1.0, recs[ci]['GRBM_GUI_ACTIVE'] / 8 * 256):.0f} % "
+                  f"of its time.  Times are the counter runs' own dispatch durations "
+                  f"(serialised, so a little longer than in the timed bench).",
+              f"Kernel sources at measurement (sha256 of {', '.join(os.path.basename(f) for f in KERNEL_SOURCES)}): "
+              f"`{kernel_source_digest()}`.", ""]
+    md = os.path.join(ROOT, "profiles", "num_chunk_rmat18_hbm_traffic.md")
+    with open(md, "w") as fh:
+        fh.write("\n".join(lines))
+    chunk_cols = None
+    m = [r for r in g7 if "k_num_chunk_pipe" in r["name"]]
+    if m:
+        chunk_cols = int(_short_name(m[0]["name"]).split(",")[1].strip(" >"))
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump({"group": "num.g7",
+                   "kernel": " + ".join(_short_name(r["name"]) for r in g7),
+                   "chunk_cols": chunk_cols, "source_sha256": kernel_source_digest(),
+                   "fetch_bytes_per_launch": int(tot["fetch"]),
+                   "write_bytes_per_launch": int(tot["write"]),
+                   "fetch_bytes_by_request_size": int(tot["req"]),
+                   "fetch_scale": fscale, "write_scale": wscale,
+                   "summary": os.path.basename(md)}, fh, indent=1)
+        fh.write("\n")
+    print("\n".join(lines))
+
+
+def summarize_kernel_stats(path):
+    """profiles/rmat18_kernel_stats.md from a rocprofv3 --stats kernel_stats.csv
+    of bench.py --steps 5 --warmup 2 --no-cpu --serve-requests 0 --no-configs."""
+    import csv
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel time, R-MAT scale 18 self-product (bench.py default workload)", "",
+             "Command (one MI355X, 5 timed + 2 warm-up steps, so 7 launches of each per-step "
+             "kernel; the symbolic-phase kernels run once more, for the group statistics):", "",
+             "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d <out> -o run "
+             "--output-format csv -- python3 /root/repo/bench.py --steps 5 --warmup 2 --no-cpu "
+             "--serve-requests 0 --no-configs", "",
+             "reduced by", "",
+             "    python3 bench.py --summarize-kernel-stats <out>/run_kernel_stats.csv", "",
+             "`rocprofv3 --stats` summary, kernels above 0.05 % of GPU time:", "",
+             "| kernel | calls | average (ms) | min (ms) | max (ms) | share |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        if float(r["Percentage"]) < 0.05:
+            continue
+        lines.append(f"| `{_short_name(r['Name'])[:140]}` | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
+                     f"{float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} % |")
+    lines += ["", "Launch groups named in bench.py's `phases_ms`: `num.g7` = `k_num_chunk_pipe` "
+                  "(dense chunks), `num.g7r` = `k_num_chunk_rank` (four launches: single light "
+                  "chunks, 8192 columns, and merged light chunks, 16384 columns, each with a "
+                  "2048- and a 1024-slot accumulator), `sym.g7` = `k_sym_chunk_pipe`, "
+                  "`num.g5`/`num.g6` = `k_num_block`, `sym.g5`/`sym.g6` = `k_sym_block`, "
+                  "`plan.ipcount` = `k_ipcount` + `k_ip_groups`, `plan.split` = `k_bsplit` + "
+                  "`k_sabs` + `k_chunk_items` + item descriptors and scans.", ""]
+    with open(os.path.join(ROOT, "profiles", "rmat18_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -640,8 +897,22 @@ def main():
                     help="comma-separated subset of rmat18, er2k, contraction, mcl, tiny, served "
                          "(a study run: the JSON line then holds only those)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="run one plain device copy of this size first (counter calibration)")
+                    help="run one plain device copy of this size, and strided reads of a 4 GiB "
+                         "buffer, first (counter calibration)")
+    ap.add_argument("--summarize-counters", default="",
+                    help="no GPU work: reduce the rocprofv3 counter passes under this folder "
+                         "(subfolders fetch, write, req, tcc, td) to the traffic summary in "
+                         "profiles/")
+    ap.add_argument("--summarize-kernel-stats", default="",
+                    help="no GPU work: write profiles/rmat18_kernel_stats.md from this "
+                         "rocprofv3 kernel_stats.csv")
     args = ap.parse_args()
+    if args.summarize_kernel_stats:
+        summarize_kernel_stats(args.summarize_kernel_stats)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.calib_copy_mib or 1024)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the row-block "
               f"sharding over several GPUs is designed but not built", file=sys.stderr)
