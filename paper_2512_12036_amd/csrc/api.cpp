@@ -38,7 +38,7 @@ struct spgemm_plan {
     // host buffer for the allocation-free entry point.
     explicit spgemm_plan(std::pmr::memory_resource *r = std::pmr::new_delete_resource())
         : A(r), B(r), hprods(r), hblks(r), hstats(r), nnz_c(r), timed(r), allocs(r),
-          dev_rpt(r) {}
+          dev_rpt(r), bs_perm(r), bs_val(r) {}
     hipStream_t stream = nullptr;
     spgemm_alloc_fn afn = nullptr;
     spgemm_free_fn ffn = nullptr;
@@ -126,6 +126,10 @@ struct spgemm_plan {
     std::pmr::vector<int64_t *> dev_rpt; // the row-pointer arrays it was captured with
     int64_t *dev_off = nullptr;
     int64_t dev_cap = -1;
+    // B sorted at plan time (unsorted B with column-chunked rows): the sort's
+    // permutation and the sorted values, gathered at every numeric call
+    std::pmr::vector<int32_t *> bs_perm;
+    std::pmr::vector<float *> bs_val;
     hipGraphExec_t num_graph = nullptr;  // the numeric launches, captured (opt.graph)
     bool num_graph_empty = false;        // captured, with nothing to launch
     std::pmr::vector<void *> allocs;
@@ -390,6 +394,51 @@ spgemm_status read_flags(spgemm_plan *p, int *out, int n) {
     return SPGEMM_OK;
 }
 
+// Sorts the rows of every B that is stored out of column order and meets
+// column-chunked rows (fewer than 2^30 entries): the sorted columns replace
+// B's in the descriptor, and the permutation gathers B's values at every
+// numeric call.
+spgemm_status sort_b_rows(spgemm_plan *p, const ProdStats *ps) {
+    size_t tmp_bytes = 0;
+    bool any = false;
+    for (int q = 0; q < p->nprod; ++q) {
+        const spgemm_csr &b = p->B[q];
+        if (ps[q].h_rows == 0 || p->hprods[q].b_sorted != 0 || b.nnz <= 0 ||
+            b.nnz >= (int64_t(1) << 30))
+            continue;
+        const size_t t = bsort_temp_bytes(b.nnz, b.nrows, b.ncols);
+        if (t == 0) return SPGEMM_EHIP;
+        tmp_bytes = std::max(tmp_bytes, t);
+        any = true;
+    }
+    if (!any) return SPGEMM_OK;
+    std::pmr::vector<int32_t *> cols(p->nprod, nullptr, p->hblks.get_allocator());
+    uint8_t *tmp = nullptr;
+    ST_TRY(alloc_stage(p, [&]() -> spgemm_status {
+        for (int q = 0; q < p->nprod; ++q) {
+            const spgemm_csr &b = p->B[q];
+            if (ps[q].h_rows == 0 || p->hprods[q].b_sorted != 0 || b.nnz <= 0 ||
+                b.nnz >= (int64_t(1) << 30))
+                continue;
+            ST_TRY(dalloc(p, &cols[q], (size_t)b.nnz));
+            ST_TRY(dalloc(p, &p->bs_perm[q], (size_t)b.nnz));
+            ST_TRY(dalloc(p, &p->bs_val[q], (size_t)b.nnz));
+        }
+        return dalloc(p, &tmp, tmp_bytes);
+    }));
+    TimeScope ts(p, "plan.bsort");
+    for (int q = 0; q < p->nprod; ++q) {
+        if (!cols[q]) continue;
+        ProdDev &P = p->hprods[q];
+        const spgemm_csr &b = p->B[q];
+        HIP_TRY(launch_bsort(b.row_ptr, b.nrows, b.ncols, b.col_idx, b.nnz, cols[q],
+                             p->bs_perm[q], tmp, tmp_bytes, p->stream));
+        P.colB = cols[q];
+        P.b_sorted = 1;
+    }
+    return upload_descriptors(p);
+}
+
 // Host side of plan creation: descriptors, row blocks, the per-row
 // workspace, the pinned staging; the descriptors and row blocks are
 // uploaded.  No kernel runs yet.
@@ -400,6 +449,8 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
     p->hprods.resize(nprod);
     p->hstats.resize(nprod);
     p->nnz_c.assign(nprod, -1);
+    p->bs_perm.assign(nprod, nullptr);
+    p->bs_val.assign(nprod, nullptr);
     int64_t row_base = 0;
     {
         size_t nb = 0;
@@ -554,8 +605,12 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         p->h_items += (int64_t)ps[q].h_items;
         p->h_tiles += (int64_t)ps[q].h_tiles;
         if (p->hprods[q].b_sorted == 2) p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
-        if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
     }
+    // B stored out of order, with column-chunked rows: sort its rows once
+    // (the chunk kernels then take each chunk's part of a B row directly)
+    ST_TRY(sort_b_rows(p, ps));
+    for (int q = 0; q < nprod; ++q)
+        if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
     if (p->nh != p->sym_start[kGroups] - p->sym_start[kGroups - 1]) return SPGEMM_EINTERNAL;
     if (p->h_items > item_limit(p->opt)) return SPGEMM_EOVERFLOW;
 
@@ -1083,6 +1138,13 @@ spgemm_status capture_numeric(spgemm_plan *p) {
 
 spgemm_status numeric_impl(spgemm_plan *p) {
     if (p->state != 2) return SPGEMM_ESTATE;
+    for (int q = 0; q < p->nprod; ++q) {  // B sorted at plan time: its values too
+        if (!p->bs_perm[q]) continue;
+        TimeScope ts(p, "num.bgather");
+        launch_gather_f32(p->hprods[q].valB, p->bs_perm[q], p->B[q].nnz, p->bs_val[q],
+                          p->stream);
+        p->hprods[q].valB = p->bs_val[q];
+    }
     ST_TRY(upload_descriptors(p));
     if (!p->opt.graph || p->opt.profile) return numeric_launch(p, p->stream);
     if (!p->num_graph && !p->num_graph_empty) ST_TRY(capture_numeric(p));

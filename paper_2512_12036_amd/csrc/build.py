@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libspgemm.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["k_plan.hip", "k_hash.hip", "k_chunk.hip", "k_apps.hip", "k_gnn.hip", "k_rowthread.hip", "api.cpp"]
+SOURCES = ["k_plan.hip", "k_hash.hip", "k_chunk.hip", "k_apps.hip", "k_gnn.hip", "k_rowthread.hip",
+           "k_bsort.hip", "api.cpp"]
 # the device input generator of the served workload: a library of its own
 GEN_SOURCES = ["k_gen.hip"]
 GEN_LIB = os.path.join(PKG, "libspgemm_gen.so")

@@ -104,6 +104,20 @@ __device__ __forceinline__ int64_t c_base(const ProdDev &P, const int64_t *rptv,
     return P.c_arena ? rptv[g] : rptv[g] - rptv[P.row_base];
 }
 
+// Launch geometry.  A dispatch packet holds each grid dimension's extent as
+// a 32-bit count of work-items, so a 1-D grid of 2^32 work-items or more is
+// laid out as rows of kGridRow workgroups over y (a wider x would wrap).
+// Kernels take their workgroup's linear index from lin_block() and bound it
+// themselves: a split grid covers its whole last row.
+constexpr int64_t kGridRow = int64_t(1) << 16;
+inline dim3 grid1d(int64_t blocks, int threads) {
+    if (blocks * (int64_t)threads <= int64_t(0xFFFFFFFF)) return dim3((unsigned)blocks);
+    return dim3((unsigned)kGridRow, (unsigned)((blocks + kGridRow - 1) / kGridRow));
+}
+__device__ __forceinline__ int64_t lin_block() {
+    return (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+}
+
 // Device-driven launches cover an upper bound of a group's rows and read the
 // group's place in the row map from the device (gstart[gsel .. gsel + 1]).
 __device__ __forceinline__ void group_range(const int64_t *gstart, int gsel,
@@ -281,6 +295,15 @@ void launch_cc_round(int64_t n, const int64_t *rpt, const int32_t *col, int64_t 
 // phases.
 void launch_rt_offsets(const ProdDev *prods, const uint64_t *items, int64_t count, int64_t *lens,
                        int64_t *off, void *scan_tmp, hipStream_t s);
+// Sorting B's rows at plan time (unsorted B with column-chunked rows): the
+// scratch bytes of the sort, the sort of (column, position) pairs per row,
+// and the numeric-time gather of B's values into the sorted order.
+size_t bsort_temp_bytes(int64_t nnz, int64_t rows, int64_t ncols);
+hipError_t launch_bsort(const int64_t *rpt, int64_t rows, int64_t ncols, const int32_t *col,
+                        int64_t nnz, int32_t *col_out, int32_t *perm, void *tmp, size_t tmp_bytes,
+                        hipStream_t s);
+void launch_gather_f32(const float *val, const int32_t *perm, int64_t n, float *out,
+                       hipStream_t s);
 void launch_rt_gather(const ProdDev *prods, const uint64_t *items, int64_t count,
                       const int64_t *off, RangeEnt *stream, bool values, hipStream_t s);
 void launch_sym_rowthread(const ProdDev *prods, const uint64_t *items, int64_t count,

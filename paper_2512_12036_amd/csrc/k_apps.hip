@@ -19,7 +19,7 @@ namespace spg {
 
 __global__ void k_label_count(const int32_t *__restrict__ labels, int64_t n, int64_t k,
                               int64_t *__restrict__ cnt, int *__restrict__ err) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = lin_block() * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int32_t l = labels[v];
     if (l < 0 || l >= k) {
@@ -32,7 +32,7 @@ __global__ void k_label_count(const int32_t *__restrict__ labels, int64_t n, int
 __global__ void k_label_scatter(const int32_t *__restrict__ labels, int64_t n, int64_t k,
                                 int64_t *__restrict__ cursor, int32_t *__restrict__ col,
                                 float *__restrict__ val) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = lin_block() * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int32_t l = labels[v];
     if (l < 0 || l >= k) return;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64) void k_mcl_count(int64_t m, const int64_t *__re
                                                   int64_t *__restrict__ keep,
                                                   int32_t *__restrict__ sel) {
     __shared__ uint32_t hist[256];
-    const int64_t r = blockIdx.x;
+    const int64_t r = lin_block();
     const int lane = threadIdx.x;
     if (r >= m) return;
     const int64_t s = rpt[r], e = rpt[r + 1];
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_mcl_write(int64_t m, const int64_t *__r
                                                    const int64_t *__restrict__ out_rpt,
                                                    int32_t *__restrict__ out_col,
                                                    float *__restrict__ out_val) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = lin_block() * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= m) return;
     const float sum = rowsum[2 * r], ksum = rowsum[2 * r + 1];
@@ -241,7 +241,7 @@ __global__ void k_mcl_change(int64_t m, const int64_t *__restrict__ rpt_a,
                              int64_t nnz_a, const int64_t *__restrict__ rpt_b,
                              const int32_t *__restrict__ col_b, const float *__restrict__ val_b,
                              int64_t nnz_b, unsigned long long *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = lin_block() * blockDim.x + threadIdx.x;
     if (t >= nnz_a + nnz_b) return;
     const bool first = t < nnz_a;
     const int64_t j = first ? t : t - nnz_a;
@@ -281,14 +281,14 @@ __device__ __forceinline__ int32_t cc_root(const int32_t *lab, int32_t x) {
 }
 
 __global__ void k_cc_init(int64_t n, int32_t *__restrict__ lab) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = lin_block() * blockDim.x + threadIdx.x;
     if (v < n) lab[v] = (int32_t)v;
 }
 
 __global__ void k_cc_hook(int64_t n, const int64_t *__restrict__ rpt,
                           const int32_t *__restrict__ col, int64_t nnz, int32_t *lab,
                           int *__restrict__ changed) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = lin_block() * blockDim.x + threadIdx.x;
     if (j >= nnz) return;
     const int32_t u = (int32_t)row_of(rpt, n, j);
     const int32_t v = col[j];
@@ -300,12 +300,12 @@ __global__ void k_cc_hook(int64_t n, const int64_t *__restrict__ rpt,
 }
 
 __global__ void k_cc_compress(int64_t n, int32_t *lab) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = lin_block() * blockDim.x + threadIdx.x;
     if (v < n) lab[v] = cc_root(lab, (int32_t)v);
 }
 
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = lin_block() * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
@@ -320,7 +320,7 @@ __global__ void k_its_sample(int64_t m, int s, const int64_t *__restrict__ rpt,
                              const int32_t *__restrict__ col, const float *__restrict__ val,
                              const float *__restrict__ u, const int32_t *__restrict__ self,
                              int32_t *__restrict__ out) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = lin_block() * blockDim.x + threadIdx.x;
     if (q >= m * s) return;
     const int64_t r = q / s;
     const int64_t a = rpt[r], b = rpt[r + 1];
@@ -347,29 +347,29 @@ void launch_its_sample(int64_t m, int s, const int64_t *rpt, const int32_t *col,
                        const float *u, const int32_t *self, int32_t *out, hipStream_t st) {
     const int64_t n = m * s;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_its_sample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, s,
+    hipLaunchKernelGGL(k_its_sample, grid1d(((n + 255) / 256), 256), dim3(256), 0, st, m, s,
                        rpt, col, val, u, self, out);
 }
 
 void launch_selector_t(const int32_t *labels, int64_t n, int64_t k, int64_t *rpt, int32_t *col,
                        float *val, int64_t *work, void *scan_tmp, int *err, hipStream_t s) {
-    const unsigned nb = (unsigned)((n + 255) / 256);
+    const int64_t nb = (n + 255) / 256;
     // work[0..k) = label counts; their exclusive scan (k + 1 entries) is rpt,
     // then work becomes the per-row write cursor
     launch_fill_i64(work, k, 0, s);
     if (n > 0)
-        hipLaunchKernelGGL(k_label_count, dim3(nb), dim3(256), 0, s, labels, n, k, work, err);
+        hipLaunchKernelGGL(k_label_count, grid1d(nb, 256), dim3(256), 0, s, labels, n, k, work, err);
     launch_scan_i64(work, rpt, k, scan_tmp, s);
     (void)hipMemcpyAsync(work, rpt, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s);
     if (n > 0)
-        hipLaunchKernelGGL(k_label_scatter, dim3(nb), dim3(256), 0, s, labels, n, k, work, col,
+        hipLaunchKernelGGL(k_label_scatter, grid1d(nb, 256), dim3(256), 0, s, labels, n, k, work, col,
                            val);
 }
 
 void launch_mcl_count(int64_t m, const int64_t *rpt, const float *val, float power, float theta,
                       int k, float *rowsum, int64_t *keep, int32_t *sel, hipStream_t s) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_mcl_count, dim3((unsigned)m), dim3(64), 0, s, m, rpt, val, power, theta,
+    hipLaunchKernelGGL(k_mcl_count, grid1d(m, 64), dim3(64), 0, s, m, rpt, val, power, theta,
                        k, rowsum, keep, sel);
 }
 
@@ -377,7 +377,7 @@ void launch_mcl_write(int64_t m, const int64_t *rpt, const int32_t *col, const f
                       float power, float theta, const float *rowsum, const int32_t *sel,
                       const int64_t *out_rpt, int32_t *out_col, float *out_val, hipStream_t s) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_mcl_write, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, rpt, col,
+    hipLaunchKernelGGL(k_mcl_write, grid1d(((m + 3) / 4), 256), dim3(256), 0, s, m, rpt, col,
                        val, power, theta, rowsum, sel, out_rpt, out_col, out_val);
 }
 
@@ -387,24 +387,24 @@ void launch_mcl_change(int64_t m, const int64_t *rpt_a, const int32_t *col_a, co
     launch_fill_i64((int64_t *)out, 1, 0, s);
     const int64_t t = nnz_a + nnz_b;
     if (m <= 0 || t <= 0) return;
-    hipLaunchKernelGGL(k_mcl_change, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, m, rpt_a,
+    hipLaunchKernelGGL(k_mcl_change, grid1d(((t + 255) / 256), 256), dim3(256), 0, s, m, rpt_a,
                        col_a, val_a, nnz_a, rpt_b, col_b, val_b, nnz_b,
                        (unsigned long long *)out);
 }
 
 void launch_cc_init(int64_t n, int32_t *lab, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_cc_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, lab);
+    hipLaunchKernelGGL(k_cc_init, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, n, lab);
 }
 
 void launch_cc_round(int64_t n, const int64_t *rpt, const int32_t *col, int64_t nnz, int32_t *lab,
                      int *changed, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t *)changed, 1, 0);
     if (nnz > 0)
-        hipLaunchKernelGGL(k_cc_hook, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, n,
+        hipLaunchKernelGGL(k_cc_hook, grid1d(((nnz + 255) / 256), 256), dim3(256), 0, s, n,
                            rpt, col, nnz, lab, changed);
     if (n > 0)
-        hipLaunchKernelGGL(k_cc_compress, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+        hipLaunchKernelGGL(k_cc_compress, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, n,
                            lab);
 }
 

@@ -32,7 +32,7 @@ namespace spg {
 __global__ __launch_bounds__(256) void k_bsplit(const int64_t *__restrict__ rptB,
                                                  const int32_t *__restrict__ colB, int64_t k_rows,
                                                  int W, int nch, int32_t *__restrict__ bsplit) {
-    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t x = lin_block() * 256 + threadIdx.x;
     const int64_t per = nch + 1;
     if (x >= k_rows * per) return;
     const int64_t k = x / per;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_bsplit(const int64_t *__restrict__ rptB
 
 // out[base[r] .. base[r+1]) = r for r < n: the row of every chunk item.
 __global__ void k_expand(const int64_t *__restrict__ base, int64_t n, int32_t *__restrict__ out) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t r = lin_block() * blockDim.x + threadIdx.x;
     if (r >= n) return;
     for (int64_t x = base[r]; x < base[r + 1]; ++x) out[x] = (int32_t)r;
 }
@@ -66,7 +66,7 @@ __global__ void k_expand(const int64_t *__restrict__ base, int64_t n, int32_t *_
 __global__ void k_row_splitlen(const ProdDev *__restrict__ prods,
                                const uint64_t *__restrict__ items, int64_t nh,
                                int64_t *__restrict__ len) {
-    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t h = lin_block() * blockDim.x + threadIdx.x;
     if (h >= nh) return;
     const uint64_t e = items[h];
     const ProdDev &P = prods[item_prod(e)];
@@ -77,7 +77,7 @@ __global__ void k_row_splitlen(const ProdDev *__restrict__ prods,
 // ntile[h] = tiles of kSabsJ A nonzeros of group-7 row h.
 __global__ void k_sabs_tiles(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                              int64_t nh, int64_t *__restrict__ ntile) {
-    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t h = lin_block() * blockDim.x + threadIdx.x;
     if (h >= nh) return;
     const uint64_t e = items[h];
     const ProdDev &P = prods[item_prod(e)];
@@ -97,6 +97,7 @@ __global__ void k_sabs_tiles(const ProdDev *__restrict__ prods, const uint64_t *
 // chunk are added to ipc[cbase[h] + c] (rows of at most kSabsC chunks).
 __global__ __launch_bounds__(256) void k_sabs(const ProdDev *__restrict__ prods,
                                                const uint64_t *__restrict__ items,
+                                               int64_t ntiles,
                                                const int32_t *__restrict__ tile_row,
                                                const int64_t *__restrict__ tbase,
                                                const int64_t *__restrict__ sbase,
@@ -106,7 +107,8 @@ __global__ __launch_bounds__(256) void k_sabs(const ProdDev *__restrict__ prods,
     __shared__ uint32_t tile[kSabsC + 1][kSabsJ + 1];  // [bound][nonzero], padded
     __shared__ int32_t kk[kSabsJ];                     // B row of each nonzero of the tile
     __shared__ uint32_t bb[kSabsJ];                    // its first position in B
-    const int64_t t = blockIdx.x;
+    const int64_t t = lin_block();
+    if (t >= ntiles) return;  // block-uniform, before any barrier
     const int64_t h = tile_row[t];
     const uint64_t e = items[h];
     const ProdDev &P = prods[item_prod(e)];
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void k_chunk_items(const ProdDev *__restrict__
                                                       int32_t *__restrict__ mstart,
                                                       int64_t *__restrict__ nitem) {
     static_assert(kSabsC <= 64, "one chunk per lane");
-    const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t h = lin_block() * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (h >= nh) return;  // wave-uniform
     const int nch = prods[item_prod(items[h])].nch;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_chunk_items(const ProdDev *__restrict__
 __global__ void k_num_nitems(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ ditems,
                              int64_t n, const int32_t *__restrict__ hslot,
                              const int64_t *__restrict__ nitem, int64_t *__restrict__ dnch) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = lin_block() * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const uint64_t e = ditems[r];
     dnch[r] = nitem[hslot[prods[item_prod(e)].row_base + item_row(e)]];
@@ -204,7 +206,7 @@ __global__ void k_num_nitems(const ProdDev *__restrict__ prods, const uint64_t *
 // nchv[r] = chunks of row r divided by div (div = 1: chunks, div = K: items).
 __global__ void k_nch_of(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                          int64_t n, int div, int64_t *__restrict__ nchv) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t r = lin_block() * blockDim.x + threadIdx.x;
     if (r < n) nchv[r] = prods[item_prod(items[r])].nch / div;
 }
 
@@ -230,7 +232,7 @@ __global__ void k_sym_desc(const ProdDev *__restrict__ prods, const uint64_t *__
                            const int64_t *__restrict__ sbase, int64_t nitems, int kper,
                            const int32_t *__restrict__ mstart, const int64_t *__restrict__ nlim,
                            ChunkDesc *__restrict__ desc) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t it = lin_block() * blockDim.x + threadIdx.x;
     if (it >= nitems || (nlim && it >= *nlim)) return;
     const int64_t h = item_of[it];
     const uint64_t e = items[h];
@@ -268,7 +270,7 @@ __global__ void k_num_desc(const ProdDev *__restrict__ prods, const uint64_t *__
                            const int64_t *__restrict__ cbase, const int64_t *__restrict__ sbase,
                            const int64_t *__restrict__ rptv, const int32_t *__restrict__ mstart,
                            const int64_t *__restrict__ nlim, ChunkDesc *__restrict__ desc) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t it = lin_block() * blockDim.x + threadIdx.x;
     if (it >= nitems || (nlim && it >= *nlim)) return;
     const int64_t dr = item_of[it];
     const uint64_t e = ditems[dr];
@@ -409,6 +411,7 @@ __device__ __forceinline__ void resident_bounds(const ProdDev &P, int64_t alen, 
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ prods,
                                                    const ChunkDesc *__restrict__ desc,
+                                                   int64_t nitems,
                                                    const uint32_t *__restrict__ sabs, int kper,
                                                    int64_t *__restrict__ chunk_cnt,
                                                    int64_t *__restrict__ row_nnz,
@@ -417,7 +420,9 @@ __global__ __launch_bounds__(WG) void k_sym_chunk(const ProdDev *__restrict__ pr
     __shared__ int64_t st_s[WG];
     __shared__ int64_t st_e[WG + 1];
     __shared__ int64_t wsum[WG / 64];
-    const ChunkDesc d = desc[blockIdx.x];
+    const int64_t item = lin_block();
+    if (item >= nitems) return;  // block-uniform, before any barrier
+    const ChunkDesc d = desc[item];
     const ProdDev &P = prods[d.prod];
     const int Q = P.nch / kper;
     const bool resident = !FAST && d.alen <= WG;
@@ -478,6 +483,7 @@ constexpr int kRankWaves = SPG_RANK_WAVES;  // independent waves (items) per wor
 template <int WG, int WMAX, bool FAST>
 __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ prods,
                                                    const ChunkDesc *__restrict__ desc,
+                                                   int64_t nitems,
                                                    const uint32_t *__restrict__ sabs, int kper,
                                                    const int64_t *__restrict__ chunk_cnt,
                                                    const int64_t *__restrict__ chunk_pos,
@@ -488,7 +494,9 @@ __global__ __launch_bounds__(WG) void k_num_chunk(const ProdDev *__restrict__ pr
     __shared__ int64_t st_e[WG + 1];
     __shared__ float st_a[WG];
     __shared__ int64_t wsum[WG / 64];
-    const ChunkDesc d = desc[blockIdx.x];
+    const int64_t item = lin_block();
+    if (item >= nitems) return;  // block-uniform, before any barrier
+    const ChunkDesc d = desc[item];
     const ProdDev &P = prods[d.prod];
     const int Q = P.nch / kper;
     const bool resident = !FAST && d.alen <= WG;
@@ -1002,7 +1010,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
     uint32_t *st_s = st_s_all[wave];
     int *st_e = st_e_all[wave];
     float *st_a = st_a_all[wave];
-    const int64_t first = ((int64_t)blockIdx.x * WAVES + wave) * IPW;
+    const int64_t first = (lin_block() * WAVES + wave) * IPW;
     if (first >= nitems) return;  // wave-uniform
     const int64_t last = first + IPW < nitems ? first + IPW : nitems;
     RankIn<KMAX> cur = rank_load<WMAX, CAP>(prods, desc_word(desc, first), sabs, chunk_cnt,
@@ -1124,9 +1132,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
 
 // Workgroups of a pipelined launch: wgs_per_cu per compute unit (a multiple
 // of 8 in total, so that the grid covers the eight dies evenly), or one per
-// item when wgs_per_cu is 0; never more than there are items.
-static unsigned pipe_grid(int wgs_per_cu, int64_t nitems) {
-    if (wgs_per_cu <= 0) return (unsigned)nitems;
+// item when wgs_per_cu is 0; never more than there are items, nor more than a
+// 1-D grid holds (the workgroups walk the items with a stride of the grid).
+static unsigned pipe_grid(int wgs_per_cu, int64_t nitems, int threads) {
+    const int64_t limit = int64_t(0xFFFFFFFF) / threads;
+    if (wgs_per_cu <= 0) return (unsigned)(nitems < limit ? nitems : limit);
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1153,7 +1163,7 @@ __global__ void k_desc_flag(const ChunkDesc *__restrict__ desc, int64_t nitems,
                             const int64_t *__restrict__ chunk_cnt, int64_t cap,
                             const int64_t *__restrict__ nlim, int64_t *__restrict__ fa,
                             int64_t *__restrict__ fb) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t it = lin_block() * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
     int64_t a = 0, b = 0;
     if (!(nlim && it >= *nlim)) {
@@ -1177,7 +1187,7 @@ __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
                              const int64_t *__restrict__ chunk_cnt,
                              const int64_t *__restrict__ chunk_pos,
                              const int64_t *__restrict__ nlim, ChunkDesc *__restrict__ out) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t it = lin_block() * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
     const int64_t n = nlim ? *nlim : nitems;
     if (it >= n) return;
@@ -1203,7 +1213,7 @@ __global__ void k_desc_split(const ChunkDesc *__restrict__ desc, int64_t nitems,
 void launch_desc_flag(const ChunkDesc *desc, int64_t nitems, const int64_t *chunk_cnt,
                       int64_t cap, const int64_t *nlim, int64_t *fa, int64_t *fb, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_desc_flag, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, desc,
+    hipLaunchKernelGGL(k_desc_flag, grid1d(((nitems + 255) / 256), 256), dim3(256), 0, s, desc,
                        nitems, chunk_cnt, cap, nlim, fa, fb);
 }
 
@@ -1212,7 +1222,7 @@ void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *fa,
                        const int64_t *chunk_cnt, const int64_t *chunk_pos, const int64_t *nlim,
                        ChunkDesc *out, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_desc_split, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_desc_split, grid1d(((nitems + 255) / 256), 256), dim3(256), 0, s,
                        desc, nitems, fa, fapos, fb, fbpos, chunk_cnt, chunk_pos, nlim, out);
 }
 
@@ -1220,20 +1230,20 @@ void launch_bsplit(const int64_t *rptB, const int32_t *colB, int64_t k_rows, int
                    int32_t *bsplit, hipStream_t s) {
     const int64_t n = k_rows * (nch + 1);
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_bsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rptB, colB,
+    hipLaunchKernelGGL(k_bsplit, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, rptB, colB,
                        k_rows, W, nch, bsplit);
 }
 
 void launch_nch_of(const ProdDev *prods, const uint64_t *items, int64_t n, int div,
                    int64_t *nchv, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_nch_of, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_nch_of, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, prods,
                        items, n, div, nchv);
 }
 
 void launch_expand(const int64_t *base, int64_t n, int32_t *out, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n, out);
+    hipLaunchKernelGGL(k_expand, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, base, n, out);
 }
 
 void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t *item_of,
@@ -1241,21 +1251,21 @@ void launch_sym_desc(const ProdDev *prods, const uint64_t *items, const int32_t 
                      int64_t nitems, int kper, const int32_t *mstart, const int64_t *nlim,
                      ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_sym_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_sym_desc, grid1d(((nitems + 255) / 256), 256), dim3(256), 0, s, prods,
                        items, item_of, ibase, cbase, sbase, nitems, kper, mstart, nlim, desc);
 }
 
 void launch_row_splitlen(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *len,
                          hipStream_t s) {
     if (nh <= 0) return;
-    hipLaunchKernelGGL(k_row_splitlen, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_row_splitlen, grid1d(((nh + 255) / 256), 256), dim3(256), 0, s, prods,
                        items, nh, len);
 }
 
 void launch_sabs_tiles(const ProdDev *prods, const uint64_t *items, int64_t nh, int64_t *ntile,
                        hipStream_t s) {
     if (nh <= 0) return;
-    hipLaunchKernelGGL(k_sabs_tiles, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_sabs_tiles, grid1d(((nh + 255) / 256), 256), dim3(256), 0, s, prods,
                        items, nh, ntile);
 }
 
@@ -1263,7 +1273,7 @@ void launch_sabs(const ProdDev *prods, const uint64_t *items, int64_t ntiles,
                  const int32_t *tile_row, const int64_t *tbase, const int64_t *sbase,
                  uint32_t *sabs, const int64_t *cbase, unsigned long long *ipc, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_sabs, dim3((unsigned)ntiles), dim3(256), 0, s, prods, items, tile_row,
+    hipLaunchKernelGGL(k_sabs, grid1d(ntiles, 256), dim3(256), 0, s, prods, items, ntiles, tile_row,
                        tbase, sbase, sabs, cbase, ipc);
 }
 
@@ -1271,14 +1281,14 @@ void launch_chunk_items(const ProdDev *prods, const uint64_t *items, int64_t nh,
                         int64_t cap, const int64_t *cbase, const unsigned long long *ipc,
                         int32_t *mstart, int64_t *nitem, hipStream_t s) {
     if (nh <= 0) return;
-    hipLaunchKernelGGL(k_chunk_items, dim3((unsigned)((nh + 3) / 4)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_chunk_items, grid1d(((nh + 3) / 4), 256), dim3(256), 0, s, prods,
                        items, nh, merge, cap, cbase, ipc, mstart, nitem);
 }
 
 void launch_num_nitems(const ProdDev *prods, const uint64_t *ditems, int64_t n,
                        const int32_t *hslot, const int64_t *nitem, int64_t *dnch, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_num_nitems, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_num_nitems, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, prods,
                        ditems, n, hslot, nitem, dnch);
 }
 
@@ -1287,7 +1297,7 @@ void launch_num_desc(const ProdDev *prods, const uint64_t *ditems, const int32_t
                      const int64_t *cbase, const int64_t *sbase, const int64_t *rptv,
                      const int32_t *mstart, const int64_t *nlim, ChunkDesc *desc, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_num_desc, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_num_desc, grid1d(((nitems + 255) / 256), 256), dim3(256), 0, s, prods,
                        ditems, item_of, dbase, nitems, kper, hslot, cbase, sbase, rptv, mstart,
                        nlim, desc);
 }
@@ -1296,26 +1306,25 @@ template <bool FAST>
 static void sym_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *desc,
                              const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
                              int64_t *row_nnz, uint32_t *sbits, int wpc, hipStream_t s) {
-    const dim3 grid((unsigned)nitems);
     if (wmax <= 2048)
-        hipLaunchKernelGGL((k_sym_chunk<64, 2048, FAST>), grid, dim3(64), 0, s, prods, desc,
-                           sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
+        hipLaunchKernelGGL((k_sym_chunk<64, 2048, FAST>), grid1d(nitems, 64), dim3(64), 0, s, prods,
+                           desc, nitems, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
     else if (wmax <= 4096)
-        hipLaunchKernelGGL((k_sym_chunk<128, 4096, FAST>), grid, dim3(128), 0, s, prods, desc,
-                           sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
+        hipLaunchKernelGGL((k_sym_chunk<128, 4096, FAST>), grid1d(nitems, 128), dim3(128), 0, s, prods,
+                           desc, nitems, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
     else if (wmax <= 8192)
-        hipLaunchKernelGGL((k_sym_chunk<256, 8192, FAST>), grid, dim3(256), 0, s, prods, desc,
-                           sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
+        hipLaunchKernelGGL((k_sym_chunk<256, 8192, FAST>), grid1d(nitems, 256), dim3(256), 0, s, prods,
+                           desc, nitems, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
     else
-        hipLaunchKernelGGL((k_sym_chunk<256, kMaxChunkCols, FAST>), grid, dim3(256), 0, s, prods,
-                           desc, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
+        hipLaunchKernelGGL((k_sym_chunk<256, kMaxChunkCols, FAST>), grid1d(nitems, 256), dim3(256), 0, s,
+                           prods, desc, nitems, sabs, kper, chunk_cnt, row_nnz, sbits, wpc);
 }
 
 template <int WG, int WMAX>
 static void sym_pipe_launch(const ProdDev *prods, const ChunkDesc *desc, const uint32_t *sabs,
                             int64_t nitems, int64_t *chunk_cnt, int64_t *row_nnz,
                             uint32_t *sbits, int wpc, int wgs_per_cu, int *err, hipStream_t s) {
-    const unsigned g = pipe_grid(wgs_per_cu, nitems);
+    const unsigned g = pipe_grid(wgs_per_cu, nitems, WG);
     hipLaunchKernelGGL((k_sym_chunk_pipe<WG, WMAX>), dim3(g), dim3(WG), 0, s, prods, desc, nitems,
                        sabs, chunk_cnt, row_nnz, sbits, wpc, err);
 }
@@ -1384,19 +1393,18 @@ static void num_chunk_launch(int wmax, const ProdDev *prods, const ChunkDesc *de
                              const uint32_t *sabs, int64_t nitems, int kper,
                              const int64_t *chunk_cnt, const int64_t *chunk_pos,
                              const uint32_t *sbits, int wpc, int *err, hipStream_t s) {
-    const dim3 grid((unsigned)nitems);
     if (wmax <= 2048)
-        hipLaunchKernelGGL((k_num_chunk<64, 2048, FAST>), grid, dim3(64), 0, s, prods, desc,
-                           sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
+        hipLaunchKernelGGL((k_num_chunk<64, 2048, FAST>), grid1d(nitems, 64), dim3(64), 0, s, prods,
+                           desc, nitems, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
     else if (wmax <= 4096)
-        hipLaunchKernelGGL((k_num_chunk<128, 4096, FAST>), grid, dim3(128), 0, s, prods, desc,
-                           sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
+        hipLaunchKernelGGL((k_num_chunk<128, 4096, FAST>), grid1d(nitems, 128), dim3(128), 0, s, prods,
+                           desc, nitems, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
     else if (wmax <= 8192)
-        hipLaunchKernelGGL((k_num_chunk<256, 8192, FAST>), grid, dim3(256), 0, s, prods, desc,
-                           sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
+        hipLaunchKernelGGL((k_num_chunk<256, 8192, FAST>), grid1d(nitems, 256), dim3(256), 0, s, prods,
+                           desc, nitems, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
     else
-        hipLaunchKernelGGL((k_num_chunk<512, kMaxChunkCols, FAST>), grid, dim3(512), 0, s,
-                           prods, desc, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
+        hipLaunchKernelGGL((k_num_chunk<512, kMaxChunkCols, FAST>), grid1d(nitems, 512), dim3(512), 0, s,
+                           prods, desc, nitems, sabs, kper, chunk_cnt, chunk_pos, sbits, wpc, err);
 }
 
 template <int WG, int WMAX>
@@ -1404,7 +1412,7 @@ static void num_pipe_launch(const ProdDev *prods, const ChunkDesc *desc, const u
                             int64_t nitems, const int64_t *chunk_cnt, const int64_t *chunk_pos,
                             const uint32_t *sbits, int wpc, int wgs_per_cu, int rank_cap,
                             bool resolved, int *err, hipStream_t s) {
-    const unsigned g = pipe_grid(wgs_per_cu, nitems);
+    const unsigned g = pipe_grid(wgs_per_cu, nitems, WG);
     hipLaunchKernelGGL((k_num_chunk_pipe<WG, WMAX>), dim3(g), dim3(WG), 0, s, prods, desc, nitems,
                        sabs, chunk_cnt, chunk_pos, sbits, wpc, (int64_t)rank_cap,
                        resolved ? 1 : 0, err);
@@ -1418,7 +1426,7 @@ static void num_rank_launch(const ProdDev *prods, const ChunkDesc *desc, const u
     const int res = resolved ? 1 : 0;
     constexpr int IPW = kRankItems, WV = kRankWaves;
     const int64_t per_wg = (int64_t)IPW * WV;
-    const dim3 grid((unsigned)((nitems + per_wg - 1) / per_wg)), block(64 * WV);
+    const dim3 grid = grid1d((nitems + per_wg - 1) / per_wg, 64 * WV), block(64 * WV);
     if (rank_cap <= 256)
         hipLaunchKernelGGL((k_num_chunk_rank<RW, 256, IPW, WV>), grid, block, 0, s, prods, desc,
                            nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(64) void k_topk_rows(int64_t n, int64_t f, const fl
                                                   int32_t *__restrict__ col,
                                                   float *__restrict__ val) {
     __shared__ uint32_t hist[256];
-    const int64_t i = blockIdx.x;
+    const int64_t i = lin_block();
     const int lane = threadIdx.x;
     if (i >= n) return;
     const float *row = x + i * ldx;
@@ -122,12 +122,12 @@ __global__ __launch_bounds__(64) void k_topk_rows(int64_t n, int64_t f, const fl
 // ---------------------------------------------------------------------------
 __global__ void k_fill_f32(float *__restrict__ p, int64_t n, float v) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+    for (int64_t i = lin_block() * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 __global__ __launch_bounds__(256) void k_fill_rows(int64_t m, int64_t n, float *__restrict__ c,
                                                    int64_t ldc) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = lin_block() * 4 + (threadIdx.x >> 6);
     if (r >= m) return;
     for (int64_t j = threadIdx.x & 63; j < n; j += 64) c[r * ldc + j] = 0.f;
 }
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_csr_to_dense(int64_t m, const int64_t *
                                                       const int32_t *__restrict__ col,
                                                       const float *__restrict__ val,
                                                       float *__restrict__ d, int64_t ldd) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = lin_block() * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= m) return;
     for (int64_t j = rpt[r] + lane; j < rpt[r + 1]; j += 64) d[r * ldd + col[j]] = val[j];
@@ -149,6 +149,11 @@ __global__ __launch_bounds__(256) void k_csr_to_dense(int64_t m, const int64_t *
 // v_mfma_f32_16x16x4f32 (one wave): D[16 x 16] += A[16 x 4] B[4 x 16]; lane
 // l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
 // D[4 (l / 16) + r][l % 16] in its r-th accumulator, r = 0..3.
+//
+// Split k: when the output has too few tiles to fill the chip (the weight
+// gradient H^T G is 512 x 256 over k = the graph's rows), blockIdx.z takes
+// its own range of k and adds its partial tile into C (zeroed first) with
+// FP32 atomics; the sum's order is then not fixed, its error bound the same.
 // ---------------------------------------------------------------------------
 constexpr int GT = 64;   // output tile edge per workgroup
 constexpr int GK = 16;   // k depth staged per step
@@ -159,7 +164,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32(int64_t M, int64_t N, int64_t 
                                                   const float *__restrict__ A, int64_t sar,
                                                   int64_t sac, const float *__restrict__ B,
                                                   int64_t sbr, int64_t sbc,
-                                                  float *__restrict__ C, int64_t ldc) {
+                                                  float *__restrict__ C, int64_t ldc,
+                                                  int64_t kslice) {
     __shared__ float sA[GK][GT + 4];  // [k][i]
     __shared__ float sB[GK][GT + 4];  // [k][j]
     const int t = threadIdx.x;
@@ -175,18 +181,20 @@ __global__ __launch_bounds__(256) void k_gemm_f32(int64_t M, int64_t N, int64_t 
     // along whichever index is contiguous in memory so the loads coalesce
     const bool a_kfast = sac == 1;
     const bool b_jfast = sbc == 1;
-    for (int64_t k0 = 0; k0 < K; k0 += GK) {
+    const int64_t kbeg = (int64_t)blockIdx.z * kslice;
+    const int64_t kend = kbeg + kslice < K ? kbeg + kslice : K;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = t + 256 * q;  // 0..1023
             int ii, kk;
             if (a_kfast) { kk = e & 15; ii = e >> 4; } else { ii = e & 63; kk = e >> 6; }
             const int64_t gi = i0 + ii, gk = k0 + kk;
-            sA[kk][ii] = (gi < M && gk < K) ? A[gi * sar + gk * sac] : 0.f;
+            sA[kk][ii] = (gi < M && gk < kend) ? A[gi * sar + gk * sac] : 0.f;
             int jj, kb;
             if (b_jfast) { jj = e & 63; kb = e >> 6; } else { kb = e & 15; jj = e >> 4; }
             const int64_t gj = j0 + jj, gkb = k0 + kb;
-            sB[kb][jj] = (gj < N && gkb < K) ? B[gkb * sbr + gj * sbc] : 0.f;
+            sB[kb][jj] = (gj < N && gkb < kend) ? B[gkb * sbr + gj * sbc] : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -214,7 +222,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32(int64_t M, int64_t N, int64_t 
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = i0 + wr + 16 * a + 4 * (lane >> 4) + r;
                 const int64_t gj = j0 + wc + 16 * b + (lane & 15);
-                if (gi < M && gj < N) C[gi * ldc + gj] = acc[a][b][r];
+                if (gi < M && gj < N) {
+                    if (gridDim.z > 1)
+                        atomicAdd(&C[gi * ldc + gj], acc[a][b][r]);
+                    else
+                        C[gi * ldc + gj] = acc[a][b][r];
+                }
             }
 }
 
@@ -231,7 +244,7 @@ __global__ __launch_bounds__(256) void k_masked_spmm(int64_t m, const int64_t *_
                                                      const int64_t *__restrict__ rpt_m,
                                                      const int32_t *__restrict__ col_m,
                                                      float *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = lin_block() * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= m) return;
     const int64_t m0 = rpt_m[i], m1 = rpt_m[i + 1];
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(256) void k_masked_spmm(int64_t m, const int64_t *_
 // ---------------------------------------------------------------------------
 __global__ void k_col_count(const int32_t *__restrict__ col, int64_t nnz,
                             unsigned long long *__restrict__ cnt) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = lin_block() * blockDim.x + threadIdx.x;
     if (j < nnz) atomicAdd(&cnt[col[j]], 1ull);
 }
 
@@ -265,7 +278,7 @@ __global__ __launch_bounds__(256) void k_transpose_scatter(int64_t m, const int6
                                                            unsigned long long *__restrict__ cursor,
                                                            int32_t *__restrict__ col_t,
                                                            float *__restrict__ val_t) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = lin_block() * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= m) return;
     for (int64_t j = rpt[r] + lane; j < rpt[r + 1]; j += 64) {
@@ -276,7 +289,7 @@ __global__ __launch_bounds__(256) void k_transpose_scatter(int64_t m, const int6
 }
 
 __global__ void k_rows_uniform(int64_t *__restrict__ rpt, int64_t n, int64_t k) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = lin_block() * blockDim.x + threadIdx.x;
     if (i <= n) rpt[i] = i * k;
 }
 
@@ -284,14 +297,14 @@ __global__ void k_rows_uniform(int64_t *__restrict__ rpt, int64_t n, int64_t k) 
 // launchers
 // ---------------------------------------------------------------------------
 void launch_rows_uniform(int64_t *rpt, int64_t n, int64_t k, hipStream_t s) {
-    hipLaunchKernelGGL(k_rows_uniform, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, rpt, n,
+    hipLaunchKernelGGL(k_rows_uniform, grid1d(((n + 256) / 256), 256), dim3(256), 0, s, rpt, n,
                        k);
 }
 
 void launch_topk_rows(int64_t n, int64_t f, const float *x, int64_t ldx, int k, int32_t *col,
                       float *val, hipStream_t s) {
     if (n <= 0 || f <= 0 || k <= 0) return;
-    hipLaunchKernelGGL(k_topk_rows, dim3((unsigned)n), dim3(64), 0, s, n, f, x, ldx, k, col, val);
+    hipLaunchKernelGGL(k_topk_rows, grid1d(n, 64), dim3(64), 0, s, n, f, x, ldx, k, col, val);
 }
 
 void launch_csr_to_dense(int64_t m, int64_t n, const int64_t *rpt, const int32_t *col,
@@ -301,7 +314,7 @@ void launch_csr_to_dense(int64_t m, int64_t n, const int64_t *rpt, const int32_t
     int64_t nb = (total + 255) / 256;
     if (nb > 65536) nb = 65536;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)nb), dim3(256), 0, s, d, total, 0.f);
-    hipLaunchKernelGGL(k_csr_to_dense, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, rpt, col,
+    hipLaunchKernelGGL(k_csr_to_dense, grid1d(((m + 3) / 4), 256), dim3(256), 0, s, m, rpt, col,
                        val, d, ldd);
 }
 
@@ -310,20 +323,30 @@ void launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float *A, int64_t sa
                      hipStream_t s) {
     if (M <= 0 || N <= 0) return;
     if (K <= 0) {  // empty sum: C = 0
-        hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, M, N, C,
+        hipLaunchKernelGGL(k_fill_rows, grid1d(((M + 3) / 4), 256), dim3(256), 0, s, M, N, C,
                            ldc);
         return;
     }
-    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
+    // split k until the grid has about four workgroups per compute unit,
+    // keeping at least 256 of k per slice
+    const int64_t tiles = ((N + GT - 1) / GT) * ((M + GT - 1) / GT);
+    int64_t split = 1;
+    while (tiles * split < 1024 && K / (2 * split) >= 256 && split < 64) split *= 2;
+    const int64_t kslice = ((K + split - 1) / split + GK - 1) / GK * GK;
+    split = (K + kslice - 1) / kslice;
+    if (split > 1)
+        hipLaunchKernelGGL(k_fill_rows, grid1d(((M + 3) / 4), 256), dim3(256), 0, s, M, N, C,
+                           ldc);
+    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)split);
     hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, s, M, N, K, A, sar, sac, B, sbr, sbc, C,
-                       ldc);
+                       ldc, kslice);
 }
 
 void launch_masked_spmm(int64_t m, const int64_t *rpt_t, const int32_t *col_t, const float *val_t,
                         const float *d, int64_t ldd, const int64_t *rpt_m, const int32_t *col_m,
                         float *out, hipStream_t s) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_masked_spmm, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, rpt_t,
+    hipLaunchKernelGGL(k_masked_spmm, grid1d(((m + 3) / 4), 256), dim3(256), 0, s, m, rpt_t,
                        col_t, val_t, d, ldd, rpt_m, col_m, out);
 }
 
@@ -332,12 +355,12 @@ void launch_transpose(int64_t m, int64_t n, const int64_t *rpt, const int32_t *c
                       float *val_t, int64_t *work, void *scan_tmp, hipStream_t s) {
     launch_fill_i64(work, n, 0, s);
     if (nnz > 0)
-        hipLaunchKernelGGL(k_col_count, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, col,
+        hipLaunchKernelGGL(k_col_count, grid1d(((nnz + 255) / 256), 256), dim3(256), 0, s, col,
                            nnz, (unsigned long long *)work);
     launch_scan_i64(work, rpt_t, n, scan_tmp, s);
     (void)hipMemcpyAsync(work, rpt_t, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s);
     if (m > 0 && nnz > 0)
-        hipLaunchKernelGGL(k_transpose_scatter, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m,
+        hipLaunchKernelGGL(k_transpose_scatter, grid1d(((m + 3) / 4), 256), dim3(256), 0, s, m,
                            rpt, col, val, (unsigned long long *)work, col_t, val_t);
 }
 

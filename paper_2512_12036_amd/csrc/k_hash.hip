@@ -274,11 +274,12 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
                                                     int *__restrict__ err,
                                                     const int64_t *__restrict__ gstart, int gsel) {
     constexpr int R = 256 / G;
+    const int64_t blk = lin_block();
     if constexpr (DEV) {
         group_range(gstart, gsel, items, count);
-        if ((int64_t)blockIdx.x * R >= count) return;  // block-uniform
+        if (blk * R >= count) return;  // block-uniform
     }
-    sym_group_rows<G>(prods, items, count, row_nnz, err, blockIdx.x);
+    sym_group_rows<G>(prods, items, count, row_nnz, err, blk);
 }
 
 template <int G>
@@ -386,12 +387,13 @@ __global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ p
                                                     int *__restrict__ err,
                                                     const int64_t *__restrict__ gstart, int gsel) {
     constexpr int R = 256 / G;
+    const int64_t blk = lin_block();
     if constexpr (DEV) {
         group_range(gstart, gsel, items, count);
-        if ((int64_t)blockIdx.x * R >= count) return;  // block-uniform
+        if (blk * R >= count) return;  // block-uniform
         if (*err & kErrCapacity) return;  // C does not fit its arena (block-uniform)
     }
-    num_group_rows<G>(prods, items, count, rptv, err, blockIdx.x);
+    num_group_rows<G>(prods, items, count, rptv, err, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -476,7 +478,9 @@ __global__ __launch_bounds__(WG) void k_sym_block(const ProdDev *__restrict__ pr
                                                    int *__restrict__ err, int64_t count,
                                                    const int64_t *__restrict__ gstart, int gsel) {
     if constexpr (!DEV) {
-        sym_block_row<WG, TMAX>(prods, items, ipv, row_nnz, err, blockIdx.x);
+        const int64_t it = lin_block();
+        if (it >= count) return;  // a split grid covers its whole last row
+        sym_block_row<WG, TMAX>(prods, items, ipv, row_nnz, err, it);
     } else {
         group_range(gstart, gsel, items, count);
         __shared__ int64_t next;
@@ -615,7 +619,9 @@ __global__ __launch_bounds__(WG) void k_num_block(const ProdDev *__restrict__ pr
                                                    int *__restrict__ err, int64_t count,
                                                    const int64_t *__restrict__ gstart, int gsel) {
     if constexpr (!DEV) {
-        num_block_row<WG, TMAX>(prods, items, rptv, err, blockIdx.x);
+        const int64_t it = lin_block();
+        if (it >= count) return;  // a split grid covers its whole last row
+        num_block_row<WG, TMAX>(prods, items, rptv, err, it);
     } else {
         group_range(gstart, gsel, items, count);
         if (*err & kErrCapacity) return;  // C does not fit its arena (block-uniform)
@@ -645,9 +651,9 @@ template <typename K, typename... Args>
 static void launch_rows(K host, K dev, int64_t blocks, int64_t dev_blocks, int threads,
                         hipStream_t s, const int64_t *gstart, Args... args) {
     if (gstart)
-        hipLaunchKernelGGL(dev, dim3((unsigned)dev_blocks), dim3(threads), 0, s, args...);
+        hipLaunchKernelGGL(dev, grid1d(dev_blocks, threads), dim3(threads), 0, s, args...);
     else
-        hipLaunchKernelGGL(host, dim3((unsigned)blocks), dim3(threads), 0, s, args...);
+        hipLaunchKernelGGL(host, grid1d(blocks, threads), dim3(threads), 0, s, args...);
 }
 
 template <int G>

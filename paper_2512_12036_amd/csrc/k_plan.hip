@@ -378,13 +378,13 @@ __global__ void k_group_starts(const int64_t *__restrict__ off, int nblk, int64_
 }
 
 __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = lin_block() * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
 __global__ void k_rows_local(const int64_t *__restrict__ rptv, int64_t row_base, int64_t m,
                              int64_t *__restrict__ dst) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = lin_block() * blockDim.x + threadIdx.x;
     if (i <= m) dst[i] = rptv[row_base + i] - rptv[row_base];
 }
 
@@ -393,7 +393,8 @@ __global__ __launch_bounds__(256) void k_detect_sorted(const int64_t *__restrict
                                                         const int32_t *__restrict__ col,
                                                         int64_t nrows, int *__restrict__ unsorted) {
     __shared__ int64_t rp[257];
-    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    const int64_t i0 = lin_block() * 256;
+    if (i0 >= nrows) return;  // block-uniform, before the barrier
     const int nr = (int)((nrows - i0) < 256 ? (nrows - i0) : 256);
     for (int t = threadIdx.x; t <= nr; t += 256) rp[t] = rpt[i0 + t];
     __syncthreads();
@@ -415,8 +416,8 @@ void launch_detect_sorted(ProdDev *prods, int nprod, const ProdDev *hp, int *fla
                           hipStream_t s) {
     for (int p = 0; p < nprod; ++p) {
         if (hp[p].b_sorted != 2 || hp[p].k == 0) continue;
-        unsigned nb = (unsigned)((hp[p].k + 255) / 256);
-        hipLaunchKernelGGL(k_detect_sorted, dim3(nb), dim3(256), 0, s, hp[p].rptB, hp[p].colB,
+        const int64_t nb = (hp[p].k + 255) / 256;
+        hipLaunchKernelGGL(k_detect_sorted, grid1d(nb, 256), dim3(256), 0, s, hp[p].rptB, hp[p].colB,
                            hp[p].k, flags + p);
     }
     hipLaunchKernelGGL(k_set_sorted, dim3((nprod + 255) / 256), dim3(256), 0, s, prods, nprod,
@@ -427,7 +428,7 @@ void launch_detect_sorted(ProdDev *prods, int nprod, const ProdDev *hp, int *fla
 // every column in [0, ncols).
 __global__ void k_validate_rows(const int64_t *__restrict__ rpt, int64_t m, int64_t nnz,
                                 int *__restrict__ bad) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = lin_block() * blockDim.x + threadIdx.x;
     if (i > m) return;
     int b = 0;
     if (i == 0 && rpt[0] != 0) b = 1;
@@ -438,7 +439,7 @@ __global__ void k_validate_rows(const int64_t *__restrict__ rpt, int64_t m, int6
 
 __global__ void k_validate_cols(const int32_t *__restrict__ col, int64_t nnz, int64_t ncols,
                                 int *__restrict__ bad) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = lin_block() * blockDim.x + threadIdx.x;
     if (i < nnz) {
         int c = col[i];
         if (c < 0 || c >= ncols) atomicOr(bad, 2);
@@ -448,13 +449,13 @@ __global__ void k_validate_cols(const int32_t *__restrict__ col, int64_t nnz, in
 // Row pointers are checked first; columns only when the pointers are sound
 // (the host reads the flag in between), so no kernel reads out of bounds.
 void launch_validate_rows(const CsrCheck &c, int *bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_rows, dim3((unsigned)((c.m + 256) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_validate_rows, grid1d(((c.m + 256) / 256), 256), dim3(256), 0, s,
                        c.rpt, c.m, c.nnz, bad);
 }
 
 void launch_validate_cols(const CsrCheck &c, int *bad, hipStream_t s) {
     if (c.nnz <= 0) return;
-    hipLaunchKernelGGL(k_validate_cols, dim3((unsigned)((c.nnz + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_validate_cols, grid1d(((c.nnz + 255) / 256), 256), dim3(256), 0, s,
                        c.col, c.nnz, c.ncols, bad);
 }
 
@@ -490,7 +491,7 @@ void launch_group_starts(const int64_t *off, int nblk, int64_t *starts, hipStrea
 
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(k_fill_i64, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, p, n, v);
 }
 
 // Row-size estimation alone (Algorithm 1), aggregated: 16 lanes per row sum
@@ -506,7 +507,7 @@ __global__ __launch_bounds__(256) void k_ip_estimate(const int64_t *__restrict__
     if (threadIdx.x < 3) acc[threadIdx.x] = 0;
     __syncthreads();
     const int seg = threadIdx.x & 15;
-    const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int64_t i = lin_block() * 16 + (threadIdx.x >> 4);
     int64_t ip = 0;
     if (i < m) {
         const int64_t a0 = rptA[i], a1 = rptA[i + 1];
@@ -534,7 +535,7 @@ void launch_ip_estimate(const int64_t *rptA, const int32_t *colA, const int64_t 
                         int64_t ncols, int64_t *out, hipStream_t s) {
     launch_fill_i64(out, 3, 0, s);
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_ip_estimate, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s, rptA,
+    hipLaunchKernelGGL(k_ip_estimate, grid1d(((m + 15) / 16), 256), dim3(256), 0, s, rptA,
                        colA, rptB, m, ncols, (unsigned long long *)out);
 }
 
@@ -555,7 +556,7 @@ void launch_arena_check(const int64_t *rptv, int64_t mtot, int64_t capacity, int
 
 void launch_rows_local(const int64_t *rptv, int64_t row_base, int64_t m, int64_t *dst,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_rows_local, dim3((unsigned)((m + 256) / 256)), dim3(256), 0, s, rptv,
+    hipLaunchKernelGGL(k_rows_local, grid1d(((m + 256) / 256), 256), dim3(256), 0, s, rptv,
                        row_base, m, dst);
 }
 

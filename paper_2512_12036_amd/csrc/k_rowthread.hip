@@ -22,7 +22,7 @@ constexpr int kRtStage = 512;   // staged stream entries per 64-row workgroup
 
 __global__ void k_rt_lens(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                           int64_t count, int64_t *__restrict__ lens) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = lin_block() * blockDim.x + threadIdx.x;
     if (t >= count) return;
     const uint64_t e = items[t];
     const ProdDev &P = prods[item_prod(e)];
@@ -35,7 +35,7 @@ __global__ void k_rt_lens(const ProdDev *__restrict__ prods, const uint64_t *__r
 __global__ void k_rt_gather(const ProdDev *__restrict__ prods, const uint64_t *__restrict__ items,
                             int64_t count, const int64_t *__restrict__ off,
                             RangeEnt *__restrict__ stream, int values) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = lin_block() * blockDim.x + threadIdx.x;
     if (t >= count) return;
     const uint64_t e = items[t];
     const ProdDev &P = prods[item_prod(e)];
@@ -58,7 +58,7 @@ __global__ void k_rt_gather(const ProdDev *__restrict__ prods, const uint64_t *_
 __device__ __forceinline__ bool rt_stage(const RangeEnt *__restrict__ stream,
                                          const int64_t *__restrict__ off, int64_t count,
                                          RangeEnt *stage, int64_t &s0) {
-    const int64_t t0 = (int64_t)blockIdx.x * 64;
+    const int64_t t0 = lin_block() * 64;
     const int64_t tl = t0 + 64 < count ? t0 + 64 : count;
     s0 = off[t0];
     const int64_t n = off[tl] - s0;
@@ -78,12 +78,13 @@ __global__ __launch_bounds__(64) void k_sym_rowthread(const ProdDev *__restrict_
     constexpr int LOG2T = __builtin_ctz(T);
     __shared__ int keys[T * 64];
     __shared__ RangeEnt stage[kRtStage];
+    if (lin_block() * 64 >= count) return;  // block-uniform, before the barrier
     const int lane = threadIdx.x;
     for (int h = 0; h < T; ++h) keys[h * 64 + lane] = kEmptyKey;
     int64_t s0 = 0;
     const bool staged = rt_stage(stream, off, count, stage, s0);
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t t = lin_block() * 64 + lane;
     if (t >= count) return;
     const uint64_t e = items[t];
     const ProdDev &P = prods[item_prod(e)];
@@ -122,6 +123,7 @@ __global__ __launch_bounds__(64) void k_num_rowthread(const ProdDev *__restrict_
     __shared__ int keys[T * 64];
     __shared__ float vals[T * 64];
     __shared__ RangeEnt stage[kRtStage];
+    if (lin_block() * 64 >= count) return;  // block-uniform, before the barrier
     const int lane = threadIdx.x;
     for (int h = 0; h < T; ++h) {
         keys[h * 64 + lane] = kEmptyKey;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(64) void k_num_rowthread(const ProdDev *__restrict_
     int64_t s0 = 0;
     const bool staged = rt_stage(stream, off, count, stage, s0);
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t t = lin_block() * 64 + lane;
     if (t >= count) return;
     const uint64_t e = items[t];
     const ProdDev &P = prods[item_prod(e)];
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(64) void k_num_rowthread(const ProdDev *__restrict_
 void launch_rt_offsets(const ProdDev *prods, const uint64_t *items, int64_t count, int64_t *lens,
                        int64_t *off, void *scan_tmp, hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_rt_lens, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_rt_lens, grid1d(((count + 255) / 256), 256), dim3(256), 0, s, prods,
                        items, count, lens);
     launch_scan_i64(lens, off, count, scan_tmp, s);
 }
@@ -194,7 +196,7 @@ void launch_rt_offsets(const ProdDev *prods, const uint64_t *items, int64_t coun
 void launch_rt_gather(const ProdDev *prods, const uint64_t *items, int64_t count,
                       const int64_t *off, RangeEnt *stream, bool values, hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_rt_gather, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, prods,
+    hipLaunchKernelGGL(k_rt_gather, grid1d(((count + 255) / 256), 256), dim3(256), 0, s, prods,
                        items, count, off, stream, values ? 1 : 0);
 }
 
@@ -202,7 +204,7 @@ void launch_sym_rowthread(const ProdDev *prods, const uint64_t *items, int64_t c
                           const int64_t *off, const RangeEnt *stream, int64_t *row_nnz, int *err,
                           hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_sym_rowthread<kRtSlots>, dim3((unsigned)((count + 63) / 64)), dim3(64), 0,
+    hipLaunchKernelGGL(k_sym_rowthread<kRtSlots>, grid1d(((count + 63) / 64), 64), dim3(64), 0,
                        s, prods, items, count, off, stream, row_nnz, err);
 }
 
@@ -210,7 +212,7 @@ void launch_num_rowthread(const ProdDev *prods, const uint64_t *items, int64_t c
                           const int64_t *off, const RangeEnt *stream, const int64_t *rptv,
                           int *err, hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_num_rowthread<kRtSlots>, dim3((unsigned)((count + 63) / 64)), dim3(64), 0,
+    hipLaunchKernelGGL(k_num_rowthread<kRtSlots>, grid1d(((count + 63) / 64), 64), dim3(64), 0,
                        s, prods, items, count, off, stream, rptv, err);
 }
 

@@ -96,3 +96,36 @@ def test_rmat16_full_size_every_row(values):
     torch.cuda.synchronize()
     structure_invariants(c)
     compare_all_rows(a, a, c, exact=(values != "float"), label=f"R-MAT 16 {values}")
+
+
+@pytest.mark.parametrize("m,kper", [(70_000, 1), (140_000, 2)])
+def test_chunk_items_beyond_one_grid(m, kper):
+    """More column-chunk work than one 1-D grid holds (the dispatch packet
+    counts work-items in 32 bits): rows of about 1,800 products each against
+    a B of 2^21 columns, 256 chunks per row.  B's rows are stored out of
+    order, so the plan sorts them first.  With one chunk per item the
+    pipelined kernels take the 17.9 million items with a capped grid; with
+    two chunks per item (140,000 rows) the one-workgroup-per-item kernels
+    take 17.9 million 256-lane workgroups, a grid split over two dimensions.
+    Every row against the oracle, exactly (integer values)."""
+    import torch
+    rng = np.random.default_rng(2024)
+    nb, ncols, blen = 16, 1 << 21, 900
+    b_col = np.concatenate([rng.choice(ncols, blen, replace=False) for _ in range(nb)])
+    b = gen.Csr(nb, ncols, np.arange(nb + 1, dtype=np.int64) * blen, b_col.astype(np.int32),
+                rng.integers(1, 4, nb * blen).astype(np.float32))
+    a_col = np.sort(np.stack([rng.choice(nb, 2, replace=False) for _ in range(m)]), axis=1)
+    a = gen.Csr(m, nb, np.arange(m + 1, dtype=np.int64) * 2, a_col.reshape(-1).astype(np.int32),
+                rng.integers(1, 4, 2 * m).astype(np.float32))
+    da, db = spgemm.to_device(a), spgemm.to_device(b, sorted_rows=False)
+    opt = spgemm.make_options(chunks_per_item=kper)
+    plan = spgemm.Plan(da, db, opt)
+    info = plan.info()
+    items = info.chunks_per_row * m // kper
+    assert info.sym_group_rows[7] == m and items * 256 >= 1 << 32
+    plan.free()
+    c = spgemm.matmul(da, db, opt)
+    torch.cuda.synchronize()
+    log(f"[gpu] beyond one grid (kper {kper}): nnz(C) = {c.nnz}, {items} chunk items")
+    structure_invariants(c)
+    compare_all_rows(a, b, c, exact=True, label=f"beyond one grid, kper {kper}")

@@ -44,7 +44,9 @@ def test_topk_rows_bit_exact(n, f, k):
 
 @pytest.mark.parametrize("M,N,K,ta,tb", [(300, 77, 129, False, False), (64, 64, 16, False, False),
                                          (1, 5, 3, False, False), (513, 200, 257, True, False),
-                                         (129, 300, 70, False, True), (97, 65, 33, True, True)])
+                                         (129, 300, 70, False, True), (97, 65, 33, True, True),
+                                         # few output tiles over a long k: split k
+                                         (64, 48, 5000, True, False), (130, 70, 3001, False, False)])
 def test_gemm_f32(M, N, K, ta, tb):
     import torch
     rng = np.random.default_rng(M * N + K)
