@@ -345,6 +345,28 @@ def run_rmat18(args):
     return out
 
 
+def run_unsorted(args):
+    """The R-MAT 18 self-product with every row of B stored in a random
+    order (A unchanged): the plan sorts B's rows on the device first (a
+    segmented radix sort) and gathers B's values into that order at the
+    numeric call, so the column-chunked rows keep the tabulated chunk bounds.
+    Compared with the sorted input's step."""
+    import torch
+    from paper_2512_12036_amd import gen, spgemm
+    a = rmat18()
+    b = gen.shuffle_rows(a, seed=5)
+    da = spgemm.to_device(a)
+    db = spgemm.to_device(b, sorted_rows=False)
+    r = measure_product(da, db, args.steps, args.warmup, "R-MAT 18, B unsorted")
+    out = {"workload": "C = A*B, A R-MAT scale 18, B = A with every row stored in a random order",
+           "ms_per_step": round(r["ms"], 3),
+           "gflops": round(r["info"].flops / (r["ms"] * 1e-3) / 1e9, 2),
+           "phases_ms": {k: round(v, 4) for k, v in sorted(r["avg"].items())}}
+    del da, db
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_er2k(args):
     """Erdos-Renyi 2,000 x 2,000 with 16,000 nonzeros, C = A*A: the latency
     floor of one whole pass."""
@@ -385,6 +407,124 @@ def run_tiny(args):
             "ms_per_step": round(r["ms"], 3),
             "gflops": round(r["info"].flops / (r["ms"] * 1e-3) / 1e9, 2),
             "phases_ms": {k: round(v, 4) for k, v in sorted(r["avg"].items())}}
+    return out
+
+
+def _cuda_timed(fn, steps, warmup):
+    """Median ms of fn() between HIP events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def run_gnn(args):
+    """One GNN layer with a pruning layer (paper Section V-C, Eq. 1-3),
+    forward and backward, at the largest served graph size: A_hat of the
+    served generator with n = 200,000 nodes (mean degree about 28 with the
+    self loop), X dense n x 512 with ReLU-like rows (half zero), TopK k = 64
+    per row, W 512 x 256.  Forward: TopK, the SpGEMM A_hat TopK(X), dense H,
+    H W on the matrix cores; backward: G W^T, the masked SpMM on TopK's
+    pattern, H^T G.  Each step is timed on its own (median of the steps)."""
+    import torch
+    from paper_2512_12036_amd import gen, gnn, spgemm
+    n, f, fo, k = 200_000, 512, 256, 64
+    log("[bench] generating the GNN layer problem ...")
+    g_ = gen.gnn_graph_t(4242, "cuda", n=n, d=27.0)
+    a = spgemm.DeviceCsr(g_.nrows, g_.ncols, g_.rpt, g_.col, g_.val, True)
+    gen_t = torch.Generator(device="cuda").manual_seed(4242)
+    x = torch.relu(torch.randn(n, f, device="cuda", generator=gen_t))
+    w = torch.randn(f, fo, device="cuda", generator=gen_t) / f ** 0.5
+    g = torch.randn(n, fo, device="cuda", generator=gen_t)
+    torch.cuda.synchronize()
+    steps, warm = max(10, args.steps), max(3, args.warmup)
+    st = {}
+    xk = spgemm.topk_rows(x, k)
+    st["topk"] = _cuda_timed(lambda: spgemm.topk_rows(x, k), steps, warm)
+    h = spgemm.matmul(a, xk)
+    st["spgemm"] = _cuda_timed(lambda: spgemm.matmul(a, xk), steps, warm)
+    hd = spgemm.to_dense(h)
+    st["to_dense"] = _cuda_timed(lambda: spgemm.to_dense(h), steps, warm)
+    st["gemm_hw"] = _cuda_timed(lambda: spgemm.gemm(hd, w), steps, warm)
+    d = spgemm.gemm(g, w.t())
+    st["gemm_gwt"] = _cuda_timed(lambda: spgemm.gemm(g, w.t()), steps, warm)
+    st["masked_spmm"] = _cuda_timed(lambda: spgemm.masked_spmm(a, d, xk), steps, warm)
+    st["gemm_htg"] = _cuda_timed(lambda: spgemm.gemm(hd.t(), g), steps, warm)
+    fwd = _cuda_timed(lambda: gnn.layer_forward(a, x, w, k), steps, warm)
+    _, cache = gnn.layer_forward(a, x, w, k)
+    bwd = _cuda_timed(lambda: gnn.layer_backward(a, g, w, cache), steps, warm)
+    deg = (a.rpt[1:] - a.rpt[:-1]).to(torch.int64)
+    # every A nonzero (i, j) meets TopK row j, which holds k entries
+    ip = int(deg.sum()) * k
+    gemm_flops = 2.0 * n * f * fo
+    mask_flops = 2.0 * int(deg.sum()) * k  # one multiply-add per (mask entry, A^T entry)
+    best_gemm = min(st["gemm_hw"], st["gemm_gwt"], st["gemm_htg"])
+    out = {
+        "workload": f"GNN layer, A_hat of the served generator n = {n}, nnz = {int(deg.sum())}; "
+                    f"X {n} x {f} ReLU(N(0,1)); TopK k = {k}; W {f} x {fo}; FP32",
+        "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
+        "steps_ms": {k_: round(v, 4) for k_, v in st.items()},
+        "spgemm_gflops": round(2.0 * ip / (st["spgemm"] * 1e-3) / 1e9, 2),
+        "masked_spmm_gflops": round(mask_flops / (st["masked_spmm"] * 1e-3) / 1e9, 2),
+        "gemm_tflops": {k_: round(gemm_flops / (st[k_] * 1e-3) / 1e12, 2)
+                        for k_ in ("gemm_hw", "gemm_gwt", "gemm_htg")},
+        "roofline": {"bound": "mfma", "kernel": "spgemm_gemm_f32 (v_mfma_f32_16x16x4_f32)",
+                     "achieved": round(gemm_flops / (best_gemm * 1e-3) / 1e12, 2),
+                     "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": round(gemm_flops / (best_gemm * 1e-3) / 1e12 / 157.3, 4),
+                     "traffic": None},
+    }
+    del a, x, w, g, xk, h, hd, d, cache
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_sampling(args):
+    """Matrix-based bulk sampling (paper Section V-C, GraphSAGE form): 8
+    stacked minibatches of 1,024 vertices of a graph of 2^20 vertices (the
+    served generator's normalised adjacency, mean degree about 16), fanouts
+    25 then 10, every layer's P = Q A, NORM, SAMPLE and EXTRACT on the
+    device; uniforms drawn beforehand.  Reports draws and extracted entries
+    per second."""
+    import torch
+    from paper_2512_12036_amd import gen, sampling, spgemm
+    log("[bench] generating the sampling graph ...")
+    g_ = gen.gnn_graph_t(90, "cuda", n=1 << 20, d=15.0)
+    da = spgemm.DeviceCsr(g_.nrows, g_.ncols, g_.rpt, g_.col, g_.val, True)
+    a = da
+    rng = np.random.default_rng(90)
+    batch = np.concatenate([rng.choice(a.nrows, 1024, replace=False) for _ in range(8)])
+    fanouts = [25, 10]
+    sizes = [len(batch)]
+    for s_ in fanouts[:-1]:
+        sizes.append(sizes[-1] * s_)
+    uniforms = [torch.from_numpy(rng.random(m * s_).astype(np.float32)).cuda()
+                for m, s_ in zip(sizes, fanouts)]
+    bt = torch.from_numpy(batch.astype(np.int32)).cuda()
+    torch.cuda.synchronize()
+    layers = sampling.graphsage_bulk(da, bt, fanouts, uniforms)
+    torch.cuda.synchronize()
+    draws = sum(int(l["sampled"].numel()) for l in layers)
+    extracted = sum(int(l["a_l"].nnz) for l in layers)
+    del layers
+    ms = _cuda_timed(lambda: sampling.graphsage_bulk(da, bt, fanouts, uniforms),
+                     max(10, args.steps), max(3, args.warmup))
+    out = {"workload": "GraphSAGE bulk sampling, 2^20-vertex graph of the served generator (mean "
+                       "degree about 16, + self loops), 8 x 1,024 batch vertices, fanouts 25, 10",
+           "ms": round(ms, 3), "draws": draws, "extracted_entries": extracted,
+           "draws_per_s": round(draws / (ms * 1e-3), 1),
+           "extracted_per_s": round(extracted / (ms * 1e-3), 1)}
+    del da, a, g_, uniforms, bt
+    torch.cuda.empty_cache()
     return out
 
 
@@ -894,7 +1034,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the ER, contraction and MCL workloads")
     ap.add_argument("--only", default="",
-                    help="comma-separated subset of rmat18, er2k, contraction, mcl, tiny, served "
+                    help="comma-separated subset of rmat18, er2k, contraction, mcl, tiny, gnn, "
+                         "sampling, unsorted, served "
                          "(a study run: the JSON line then holds only those)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size, and strided reads of a 4 GiB "
@@ -919,7 +1060,8 @@ def main():
         sys.exit(2)
     if args.only:
         runs = {"rmat18": run_rmat18, "er2k": run_er2k, "contraction": run_contraction,
-                "mcl": run_mcl, "tiny": run_tiny,
+                "mcl": run_mcl, "tiny": run_tiny, "gnn": run_gnn, "sampling": run_sampling,
+                "unsorted": run_unsorted,
                 "served": lambda a: run_served(a.serve_requests,
                                                SERVE_CONFIGS)}
         out = {}
@@ -930,7 +1072,8 @@ def main():
     out = run_rmat18(args)
     if not args.no_configs:
         out["configs"] = {"er2k": run_er2k(args), "contraction": run_contraction(args),
-                          "mcl": run_mcl(args)}
+                          "mcl": run_mcl(args), "tiny_rows": run_tiny(args),
+                          "gnn_layer": run_gnn(args), "bulk_sampling": run_sampling(args)}
     if args.serve_requests > 0:
         # small batches (latency, throughput) and large ones (the HBM budget
         # binds: batches are closed by it)
