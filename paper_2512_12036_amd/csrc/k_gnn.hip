@@ -181,22 +181,36 @@ __global__ __launch_bounds__(256) void k_gemm_f32(int64_t M, int64_t N, int64_t 
     // along whichever index is contiguous in memory so the loads coalesce
     const bool a_kfast = sac == 1;
     const bool b_jfast = sbc == 1;
+    int ai[4], ak[4], bj[4], bk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = t + 256 * q;  // 0..1023
+        if (a_kfast) { ak[q] = e & 15; ai[q] = e >> 4; } else { ai[q] = e & 63; ak[q] = e >> 6; }
+        if (b_jfast) { bj[q] = e & 63; bk[q] = e >> 6; } else { bk[q] = e & 15; bj[q] = e >> 4; }
+    }
     const int64_t kbeg = (int64_t)blockIdx.z * kslice;
     const int64_t kend = kbeg + kslice < K ? kbeg + kslice : K;
+    // the next k step's elements are loaded into registers while the MFMAs
+    // of the current one run
+    float ra[4], rb[4];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t gi = i0 + ai[q], gk = k0 + ak[q];
+            ra[q] = (gi < M && gk < kend) ? A[gi * sar + gk * sac] : 0.f;
+            const int64_t gj = j0 + bj[q], gkb = k0 + bk[q];
+            rb[q] = (gj < N && gkb < kend) ? B[gkb * sbr + gj * sbc] : 0.f;
+        }
+    };
+    fetch(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int e = t + 256 * q;  // 0..1023
-            int ii, kk;
-            if (a_kfast) { kk = e & 15; ii = e >> 4; } else { ii = e & 63; kk = e >> 6; }
-            const int64_t gi = i0 + ii, gk = k0 + kk;
-            sA[kk][ii] = (gi < M && gk < kend) ? A[gi * sar + gk * sac] : 0.f;
-            int jj, kb;
-            if (b_jfast) { jj = e & 63; kb = e >> 6; } else { kb = e & 15; jj = e >> 4; }
-            const int64_t gj = j0 + jj, gkb = k0 + kb;
-            sB[kb][jj] = (gj < N && gkb < kend) ? B[gkb * sbr + gj * sbc] : 0.f;
+            sA[ak[q]][ai[q]] = ra[q];
+            sB[bk[q]][bj[q]] = rb[q];
         }
         __syncthreads();
+        if (k0 + GK < kend) fetch(k0 + GK);
 #pragma unroll
         for (int ks = 0; ks < GK; ks += 4) {
             const int kr = ks + (lane >> 4);
