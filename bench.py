@@ -383,6 +383,20 @@ def run_er2k(args):
            "intermediate_products": r["info"].ip_total, "nnz_c": r["info"].nnz_c,
            "roofline": dominant_roofline(r["per_launch"], r["avg"], units),
            "phases_ms": {k: round(v, 4) for k, v in sorted(r["avg"].items())}}
+    # the same product through the one-call allocation-free entry point (plan,
+    # symbolic and numeric in one C call, C into arrays sized by the IP bound)
+    cap = int(r["info"].ip_total)
+    c_rpt = torch.empty(a.nrows + 1, dtype=torch.int64, device="cuda")
+    c_col = torch.empty(cap, dtype=torch.int32, device="cuda")
+    c_val = torch.empty(cap, dtype=torch.float32, device="cuda")
+    per = []
+    for k in range(steps + 5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, _ = spgemm.multiply_noalloc(da, da, c_rpt, c_col, c_val)
+        per.append((time.perf_counter() - t0) * 1e3)
+        assert code == 0, code
+    out["one_call_ms"] = round(float(np.median(per[5:])), 4)
     if not args.no_cpu:
         rows = np.arange(a.nrows, dtype=np.int64)
         out["cpu_baseline"] = cpu_baseline_of(a, a, rows, float(r["info"].flops),
@@ -639,10 +653,11 @@ def run_mcl(args):
 
     def loop(record):
         t = t0
-        it_ms, tl, ips, units = [], [], [], []
+        it_ms, tl, ips, units, pr_ms = [], [], [], [], []
         for it in range(5):
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
+            evp = torch.cuda.Event(enable_timing=True)
             ev0.record()
             plan = spgemm.Plan(t, t, opt)
             plan.symbolic()
@@ -657,29 +672,43 @@ def run_mcl(args):
             del cols, vals
             if record:
                 units.append(plan_units(t, t))
+            evp.record()
             nt = spgemm.mcl_prune(e, 2.0, 1e-4)
             ev1.record()
             del e
             t = nt
             torch.cuda.synchronize()
             it_ms.append(ev0.elapsed_time(ev1))
-        return it_ms, tl, ips, units, t
+            pr_ms.append(evp.elapsed_time(ev1))
+        return it_ms, tl, ips, units, t, pr_ms
 
     loop(False)
     torch.cuda.empty_cache()
     log("[bench] mcl: warmup loop done")
     steps = 2
-    all_ms, all_tl = [], []
+    all_ms, all_tl, all_pr = [], [], []
     torch.cuda.synchronize()
     tt = time.perf_counter()
     for _ in range(steps):
-        it_ms, tl, ips, _, tfin = loop(False)
+        it_ms, tl, ips, _, tfin, pr_ms = loop(False)
         all_ms.append(it_ms)
         all_tl.append(tl)
+        all_pr.append(pr_ms)
         torch.cuda.empty_cache()
     ms = (time.perf_counter() - tt) * 1e3 / steps
     log(f"[bench] mcl: {steps} timed loops done")
-    _, _, _, units, _ = loop(True)
+    _, _, _, units, _, _ = loop(True)
+    torch.cuda.empty_cache()
+    # the whole of Algorithm 6: iterations until the change between iterates
+    # reaches 1e-6 (at most 40), then the clusters as connected components
+    from paper_2512_12036_amd import apps
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    labels, tcl, iters, changes = apps.mcl_cluster(t0, 2.0, 1e-4, 0, 1e-6, 40)
+    torch.cuda.synchronize()
+    cl_ms = (time.perf_counter() - tc) * 1e3
+    n_clusters = int(torch.unique(labels).numel())
+    del tcl
     torch.cuda.empty_cache()
     flops = 2 * sum(ips)
     # dominant launch group over the iterations
@@ -697,8 +726,14 @@ def run_mcl(args):
            "steps": steps, "ms_per_step": round(ms, 2),
            "ms_per_iteration": [round(float(np.mean([m[i] for m in all_ms])), 3)
                                 for i in range(5)],
+           "prune_ms_per_iteration": [round(float(np.mean([m[i] for m in all_pr])), 3)
+                                      for i in range(5)],
            "gflops": round(flops / (ms * 1e-3) / 1e9, 2),
-           "intermediate_products": ips, "nnz_final": tfin.nnz, "roofline": best}
+           "intermediate_products": ips, "nnz_final": tfin.nnz, "roofline": best,
+           "clustering": {"iterations": iters, "ms": round(cl_ms, 2), "clusters": n_clusters,
+                          "last_change": changes[-1] if changes else None,
+                          "what": "iterations until the largest entry change <= 1e-6 (at most "
+                                  "40), then connected components of the final pattern"}}
     if not args.no_cpu:
         import oracle
         ip1 = oracle.ip(t0h, t0h)
