@@ -524,8 +524,11 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
         for (int s = 0; s < kDescSlots; ++s)
             HIP_TRY(hipEventCreateWithFlags(&p->desc_ev[s], hipEventDisableTiming));
     }
-    HIP_TRY(hipMemsetAsync(p->stats, 0, sizeof(ProdStats) * nprod, p->stream));
-    HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int) * (3 + nprod), p->stream));
+    // cleared by fill kernels, not memsets, so that a caller may capture the
+    // plan's work in a graph (device allocations are padded to 256 bytes, so
+    // the flags' last 8-byte word is in bounds)
+    launch_fill_i64((int64_t *)p->stats, (int64_t)(sizeof(ProdStats) / 8) * nprod, 0, p->stream);
+    launch_fill_i64((int64_t *)p->flags, (3 + nprod + 1) / 2, 0, p->stream);
     ST_TRY(upload_descriptors(p));
     if (!p->hblks.empty())
         HIP_TRY(hipMemcpyAsync(p->dblks, p->hblks.data(), sizeof(RowBlk) * p->hblks.size(),

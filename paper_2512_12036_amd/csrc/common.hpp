@@ -98,6 +98,7 @@ struct ProdStats {
     unsigned long long h_tiles;   // sum of ceil(alen / kSabsJ) over symbolic group-7 rows
     unsigned long long pad[5];
 };
+static_assert(sizeof(ProdStats) % 8 == 0, "ProdStats is cleared in 8-byte words");
 
 // First output slot of batch row g in its product's C arrays.
 __device__ __forceinline__ int64_t c_base(const ProdDev &P, const int64_t *rptv, int64_t g) {

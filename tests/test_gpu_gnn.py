@@ -132,3 +132,70 @@ def test_layer_teacher_forced(n, f, fo, k):
     gw = dw_d.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(gw - dw) <= n * U * dwb + 1e-30)
     log(f"[gpu] GNN layer n={n} f={f} fo={fo} k={k}: forward and backward match the oracle")
+
+
+def test_layer_full_size_sampled_rows():
+    """The benchmarked layer size (A_hat of the served generator with n =
+    200,000 and mean degree 27, X 200,000 x 512, k = 64, W 512 x 256),
+    checked on sampled outputs the oracle computes one by one: TopK on 2,000
+    rows (bit for bit), H = A_hat TopK(X) on 2,000 rows including the densest
+    (teacher-forced on the GPU's TopK, within the SpGEMM tolerance), X_l = H W
+    and D = G W^T on those rows, the masked gradient on those rows, and 16
+    columns of the weight gradient H^T G (within the FP32 summation bounds)."""
+    import torch
+    n, f, fo, k = 200_000, 512, 256, 64
+    g_ = gen.gnn_graph_t(4242, "cpu", n=n, d=27.0)
+    a = gen.Csr(g_.nrows, g_.ncols, g_.rpt.numpy(), g_.col.numpy(), g_.val.numpy())
+    rng = np.random.default_rng(4242)
+    x = np.maximum(rng.standard_normal((n, f), dtype=np.float32), 0.0)
+    w = (rng.standard_normal((f, fo), dtype=np.float32) / np.float32(np.sqrt(f)))
+    gr = rng.standard_normal((n, fo), dtype=np.float32)
+    da = spgemm.to_device(a)
+    xt, wt, gt = (torch.from_numpy(v).cuda() for v in (x, w, gr))
+    out, cache = gnn.layer_forward(da, xt, wt, k)
+    dx_d, dw_d = gnn.layer_backward(da, gt, wt, cache)
+    torch.cuda.synchronize()
+    xk_d, hd_d = cache
+    deg = np.diff(a.rpt)
+    rows = np.unique(np.concatenate([rng.choice(n, 1990, replace=False),
+                                     np.argsort(deg)[-10:]])).astype(np.int64)
+    # TopK, bit for bit
+    xk = csr_host(xk_d)
+    rpt, col, val = oracle.topk_rows(x[rows], k)
+    sel = (xk.rpt[rows][:, None] + np.arange(k)[None, :]).reshape(-1)
+    assert np.array_equal(xk.col[sel], col) and np.array_equal(xk.val[sel], val)
+    # H on the sampled rows against the oracle's product with the GPU's TopK
+    ref = oracle.product(a, xk, rows)
+    h = hd_d[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    rid = np.repeat(np.arange(len(rows)), np.diff(ref.rpt))
+    hr = np.zeros_like(h)
+    hr[rid, ref.col] = ref.val
+    hb = np.zeros_like(h)
+    hb[rid, ref.col] = ref.absb
+    assert np.all(np.abs(h - hr) <= 1e-5 * hb + 1e-30)
+    # X_l = H W and the masked gradient on those rows
+    w64 = w.astype(np.float64)
+    o = out[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(o - h @ w64) <= f * U * (np.abs(h) @ np.abs(w64)) + 1e-30)
+    at = a  # A_hat is symmetric
+    gx = dx_d.val.cpu().numpy().astype(np.float64)
+    maxdeg = int(deg.max())
+    for r in rows[:400]:
+        nb = at.col[at.rpt[r]:at.rpt[r + 1]].astype(np.int64)
+        av = at.val[at.rpt[r]:at.rpt[r + 1]].astype(np.float64)
+        d_rows = gr[nb].astype(np.float64) @ w64.T          # D = G W^T on the neighbours
+        d_abs = np.abs(gr[nb].astype(np.float64)) @ np.abs(w64.T)
+        cs = xk.col[xk.rpt[r]:xk.rpt[r + 1]]
+        want = av @ d_rows[:, cs]
+        bound = np.abs(av) @ d_abs[:, cs]
+        got = gx[xk.rpt[r]:xk.rpt[r + 1]]
+        assert np.all(np.abs(got - want) <= (fo + maxdeg + 2) * U * bound + 1e-30), r
+    # 16 columns of dW = H^T G, with the GPU's H
+    cols = rng.choice(fo, 16, replace=False)
+    hfull = hd_d.cpu().numpy().astype(np.float64)
+    g64 = gr[:, cols].astype(np.float64)
+    want = hfull.T @ g64
+    bound = np.abs(hfull).T @ np.abs(g64)
+    got = dw_d[:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= n * U * bound + 1e-30)
+    log(f"[gpu] GNN layer at n={n}: sampled rows and weight-gradient columns match the oracle")
