@@ -27,6 +27,86 @@ namespace {
 
 constexpr int kDescSlots = 4;  // pinned descriptor staging buffers (ring)
 
+// Process-wide pools of pinned host buffers and of events, per device.
+// Pinned allocation and event creation are driver calls of tens of
+// microseconds (a pinned free can wait on the device), which a stream of
+// plans (a server, a benchmark loop) would otherwise pay per plan.  Plans
+// take from the pools and give back in spgemm_free, after synchronising
+// their stream; the pools keep everything until the process ends.
+constexpr int kPoolDevices = 64;
+
+class HostPools {
+  public:
+    // a pinned buffer of at least `bytes` (a power of two from 4 KB);
+    // *got = its size; null if the allocation fails
+    void *pinned(size_t bytes, size_t *got) {
+        const int d = device();
+        std::lock_guard<std::mutex> g(mu_);
+        auto &fl = pinned_[d];
+        size_t best = SIZE_MAX;
+        for (size_t i = 0; i < fl.size(); ++i)
+            if (fl[i].first >= bytes && (best == SIZE_MAX || fl[i].first < fl[best].first))
+                best = i;
+        if (best != SIZE_MAX) {
+            const auto e = fl[best];
+            fl.erase(fl.begin() + (std::ptrdiff_t)best);
+            *got = e.first;
+            return e.second;
+        }
+        size_t cap = 4096;
+        while (cap < bytes) cap <<= 1;
+        void *h = nullptr;
+        if (hipHostMalloc(&h, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        *got = cap;
+        return h;
+    }
+    void give_pinned(void *h, size_t bytes) {
+        if (!h) return;
+        const int d = device();
+        std::lock_guard<std::mutex> g(mu_);
+        pinned_[d].emplace_back(bytes, h);
+    }
+    // an event; timing: false -> created with hipEventDisableTiming
+    hipError_t event(hipEvent_t *e, bool timing) {
+        const int d = device();
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto &fl = events_[timing][d];
+            if (!fl.empty()) {
+                *e = fl.back();
+                fl.pop_back();
+                return hipSuccess;
+            }
+        }
+        return timing ? hipEventCreate(e) : hipEventCreateWithFlags(e, hipEventDisableTiming);
+    }
+    void give_event(hipEvent_t e, bool timing) {
+        if (!e) return;
+        const int d = device();
+        std::lock_guard<std::mutex> g(mu_);
+        events_[timing][d].push_back(e);
+    }
+
+  private:
+    static int device() {
+        int d = 0;
+        if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kPoolDevices) d = 0;
+        return d;
+    }
+    std::mutex mu_;
+    std::vector<std::pair<size_t, void *>> pinned_[kPoolDevices];
+    std::vector<hipEvent_t> events_[2][kPoolDevices];
+};
+
+// never destroyed: it may be used until the runtime shuts down
+HostPools &pools() {
+    static HostPools *p = new HostPools;
+    return *p;
+}
+
 struct HostStats {
     int64_t ip_sum = 0, ip_max = 0, nnz_sum = 0, nnz_max = 0;
 };
@@ -50,6 +130,7 @@ struct spgemm_plan {
     std::pmr::vector<ProdDev> hprods;
     ProdDev *dprods = nullptr;
     ProdDev *pinned = nullptr;  // kDescSlots * nprod descriptors
+    size_t pinned_bytes = 0;
     hipEvent_t desc_ev[kDescSlots] = {};
     bool desc_ev_used[kDescSlots] = {};
     int desc_next = 0;
@@ -190,7 +271,11 @@ struct TimeScope {
     TimeScope(spgemm_plan *plan, const char *name) : p(plan) {
         if (!p->opt.profile) return;
         spgemm_plan::Timed t{name, nullptr, nullptr};
-        if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return;
+        if (pools().event(&t.a, true) != hipSuccess) return;
+        if (pools().event(&t.b, true) != hipSuccess) {
+            pools().give_event(t.a, true);
+            return;
+        }
         (void)hipEventRecord(t.a, p->stream);
         idx = p->timed.size();
         p->timed.push_back(t);
@@ -301,13 +386,16 @@ spgemm_status ensure_hread(spgemm_plan *p, size_t bytes) {
         p->hread_bytes = p->host_read_bytes;
         return SPGEMM_OK;
     }
-    if (p->hread) (void)hipHostFree(p->hread);
+    // the old buffer holds nothing still in flight: every read into it was
+    // waited for
+    pools().give_pinned(p->hread, p->hread_bytes);
     p->hread = nullptr;
     p->hread_bytes = 0;
-    void *h = nullptr;
-    HIP_TRY(hipHostMalloc(&h, bytes, hipHostMallocDefault));
+    size_t got = 0;
+    void *h = pools().pinned(bytes, &got);
+    if (!h) return SPGEMM_EHIP;
     p->hread = (int64_t *)h;
-    p->hread_bytes = bytes;
+    p->hread_bytes = got;
     return SPGEMM_OK;
 }
 
@@ -518,11 +606,12 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
         return ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk));
     }));
     if (!p->noalloc) {
-        void *h = nullptr;
-        HIP_TRY(hipHostMalloc(&h, sizeof(ProdDev) * nprod * kDescSlots, hipHostMallocDefault));
+        size_t got = 0;
+        void *h = pools().pinned(sizeof(ProdDev) * nprod * kDescSlots, &got);
+        if (!h) return SPGEMM_EHIP;
         p->pinned = (ProdDev *)h;
-        for (int s = 0; s < kDescSlots; ++s)
-            HIP_TRY(hipEventCreateWithFlags(&p->desc_ev[s], hipEventDisableTiming));
+        p->pinned_bytes = got;
+        for (int s = 0; s < kDescSlots; ++s) HIP_TRY(pools().event(&p->desc_ev[s], false));
     }
     // cleared by fill kernels, not memsets, so that a caller may capture the
     // plan's work in a graph (device allocations are padded to 256 bytes, so
@@ -1445,14 +1534,16 @@ void spgemm_free(spgemm_plan *p) {
         else (void)hipFree(ptr);
     }
     p->allocs.clear();
+    // the stream is idle: the pinned buffers and events go back to the pools
     for (auto &t : p->timed) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
+        pools().give_event(t.a, true);
+        pools().give_event(t.b, true);
     }
-    if (p->pinned) (void)hipHostFree(p->pinned);
-    if (p->hread) (void)hipHostFree(p->hread);
-    for (int s = 0; s < kDescSlots; ++s)
-        if (p->desc_ev[s]) (void)hipEventDestroy(p->desc_ev[s]);
+    if (!p->noalloc) {
+        pools().give_pinned(p->pinned, p->pinned_bytes);
+        pools().give_pinned(p->hread, p->hread_bytes);
+    }
+    for (int s = 0; s < kDescSlots; ++s) pools().give_event(p->desc_ev[s], false);
     delete p;
 }
 
