@@ -573,6 +573,7 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
         P.W = (int32_t)w;
         p->wmax = std::max<int>(p->wmax, P.W);
         P.b_sorted = (b.flags & SPGEMM_ROWS_SORTED) ? 1 : 2;
+        P.b_unique = (b.flags & SPGEMM_ROWS_SORTED) ? 1 : 0;
         for (int64_t i0 = 0; i0 < a.nrows; i0 += kRowBlock) {
             RowBlk rb;
             rb.p = q;
@@ -696,7 +697,10 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
         p->h_split += (int64_t)ps[q].h_split;
         p->h_items += (int64_t)ps[q].h_items;
         p->h_tiles += (int64_t)ps[q].h_tiles;
-        if (p->hprods[q].b_sorted == 2) p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
+        if (p->hprods[q].b_sorted == 2) {
+            p->hprods[q].b_sorted = unsorted[q] ? 0 : 1;
+            p->hprods[q].b_unique = unsorted[q] ? 0 : 1;
+        }
     }
     // B stored out of order, with column-chunked rows: sort its rows once
     // (the chunk kernels then take each chunk's part of a B row directly)

@@ -50,6 +50,9 @@ struct ProdDev {
     int32_t b_sorted;   // rows of B strictly ascending: 1 yes, 0 no, 2 detect
     int32_t c_arena;    // 1: colC / valC are one arena shared by the batch, indexed by
                         // the batch-wide row pointers (device-driven plans)
+    int32_t b_unique;   // 1: B's rows strictly ascending, so no duplicate columns (B
+                        // rows sorted by the plan may hold duplicates: 0)
+    int32_t pad_;
 };
 
 // One work item of group 7: the chunks q, q + Q, ... (K of them) of one row,

@@ -442,6 +442,16 @@ __device__ __forceinline__ void sym_block_row(const ProdDev *__restrict__ prods,
     const ProdDev &P = prods[item_prod(e)];
     const int64_t i = item_row(e);
     const int64_t g = P.row_base + i;
+    const int64_t a0 = P.rptA[i];
+    if (P.rptA[i + 1] - a0 == 1 && P.b_unique == 1) {
+        // one A nonzero and strictly ascending B rows: the row's structure is
+        // that B row's (block-uniform; no barrier has been reached)
+        if (threadIdx.x == 0) {
+            const int k = P.colA[a0];
+            row_nnz[g] = P.rptB[k + 1] - P.rptB[k];
+        }
+        return;
+    }
     int64_t bound = ipv[g] < P.n ? ipv[g] : P.n;
     // direct-mapped (slot = column) when B's columns fit the table
     const bool direct = P.n <= TMAX;
@@ -512,6 +522,25 @@ __device__ __forceinline__ void num_block_row(const ProdDev *__restrict__ prods,
     const int64_t i = item_row(e);
     const int64_t g = P.row_base + i;
     const int64_t expect = rptv[g + 1] - rptv[g];
+    const int64_t a0 = P.rptA[i];
+    if (P.rptA[i + 1] - a0 == 1 && P.b_unique == 1) {
+        // one A nonzero and strictly ascending B rows: the row is that B row
+        // scaled, already in column order; copied with coalesced accesses
+        // (each value a single FP32 product, as the table would hold it)
+        const int k = P.colA[a0];
+        const float av = P.valA[a0];
+        const int64_t b0 = P.rptB[k], len = P.rptB[k + 1] - b0;
+        if (len != expect) {
+            if (threadIdx.x == 0) atomicOr(err, kErrCount);
+            return;
+        }
+        const int64_t base = c_base(P, rptv, g);
+        for (int64_t q = threadIdx.x; q < len; q += WG) {
+            gst(P.colC + base + q, gld(P.colB + b0 + q));
+            gst(P.valC + base + q, av * gld(P.valB + b0 + q));
+        }
+        return;
+    }
     // direct-mapped (slot = column) when B's columns fit the table
     const bool direct = P.n <= TMAX;
     int log2T = ceil_log2(direct ? P.n : 2 * expect);

@@ -408,7 +408,10 @@ __global__ __launch_bounds__(256) void k_detect_sorted(const int64_t *__restrict
 
 __global__ void k_set_sorted(ProdDev *prods, int nprod, const int *__restrict__ unsorted) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nprod && prods[p].b_sorted == 2) prods[p].b_sorted = unsorted[p] ? 0 : 1;
+    if (p < nprod && prods[p].b_sorted == 2) {
+        prods[p].b_sorted = unsorted[p] ? 0 : 1;
+        prods[p].b_unique = unsorted[p] ? 0 : 1;  // ascending pairs only: no duplicates
+    }
 }
 
 // hp: host copy of the descriptors; b_sorted == 2 there means "detect".
