@@ -174,10 +174,16 @@ def bin_of(key: np.ndarray, upper: list[int]) -> np.ndarray:
     return bins
 
 
-def bins_reference(key: np.ndarray, upper: list[int]):
+def bins_reference(key: np.ndarray, upper: list[int], single=None, copy_group: int = 5):
     """(bins, map, offsets): map lists rows group by group, ascending row
-    order inside a group; offsets[b] is where group b starts."""
+    order inside a group; offsets[b] is where group b starts.  single: rows
+    that hold one A nonzero against strictly ascending B rows; those the
+    bounds would put past copy_group go to copy_group (a scaled copy of one B
+    row needs no table, so the smallest block group's kernel takes it)."""
     bins = bin_of(key, upper)
+    if single is not None:
+        move = np.asarray(single, dtype=bool) & (bins > copy_group)
+        bins[move] = copy_group
     nb = len(upper) + 1
     order = np.argsort(bins, kind="stable").astype(np.int64)
     offsets = np.zeros(nb + 1, dtype=np.int64)

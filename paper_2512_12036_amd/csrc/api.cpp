@@ -467,10 +467,13 @@ int64_t item_limit(const spgemm_options &o) {
     return (o.item_limit > 0 && o.item_limit < cap) ? o.item_limit : cap;
 }
 
-GroupBounds bounds_of(const int64_t *up) {
+// copy_group: the block group whose kernels copy single-nonzero rows (0:
+// none, for device-driven plans that do not launch it)
+GroupBounds bounds_of(const int64_t *up, int copy_group = 5) {
     GroupBounds gb{};
     for (int g = 0; g < kGroups - 1; ++g) gb.up[g] = up[g];
     gb.up[kGroups - 1] = INT64_MAX;
+    gb.copy_group = copy_group;
     return gb;
 }
 
@@ -860,7 +863,7 @@ spgemm_status device_launch_all(spgemm_plan *p, hipStream_t st, int64_t *const *
     launch_fill_i64((int64_t *)p->flags, (3 + nprod + 1) / 2, 0, st);
     launch_fill_i64(p->starts + kWorkCtr, 2 * (kGroups + 1), 0, st);
     // Algorithm 1 and the symbolic grouping
-    const GroupBounds gs = bounds_of(p->opt.sym_upper);
+    const GroupBounds gs = bounds_of(p->opt.sym_upper, p->sym_hi >= 5 ? 5 : 0);
     launch_ipcount(p->dprods, p->dblks, p->nblk, gs, p->ip, p->blkcnt, p->stats, M, st);
     launch_scan_i64(p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk, p->scan_tmp, st);
     launch_scatter(p->dprods, p->dblks, p->nblk, gs, p->ip, p->blkoff, p->map_sym, p->hslot,
@@ -875,7 +878,7 @@ spgemm_status device_launch_all(spgemm_plan *p, hipStream_t st, int64_t *const *
                          p->flags, st, p->starts, g);
     launch_scan_i64(p->row_nnz, p->rptv, M, p->scan_tmp, st);
     // numeric grouping by output length
-    const GroupBounds gn = bounds_of(p->opt.num_upper);
+    const GroupBounds gn = bounds_of(p->opt.num_upper, p->num_hi >= 5 ? 5 : 0);
     launch_count_groups(p->dprods, p->dblks, p->nblk, gn, p->row_nnz, p->ip, p->blkcnt, p->stats,
                         st);
     launch_scan_i64(p->blkcnt, p->blkoff, (int64_t)kGroups * p->nblk, p->scan_tmp, st);

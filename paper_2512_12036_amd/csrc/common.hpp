@@ -158,7 +158,13 @@ __device__ __forceinline__ uint32_t hash_slot(int c, int log2T) {
 // ---------------------------------------------------------------------------
 // Host launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
-struct GroupBounds { int64_t up[kGroups]; };  // up[0] = 0, up[7] unused
+// up[0] = 0, up[7] unused.  copy_group > 0: rows of a single A nonzero with
+// strictly ascending B rows that would go past that group go to it instead
+// (its kernels copy such rows); 0: no such rule.
+struct GroupBounds {
+    int64_t up[kGroups];
+    int64_t copy_group;
+};
 
 size_t scan_temp_bytes(int64_t n);
 // out[0..n] = exclusive prefix of in[0..n) (out[n] = total).  out != in.

@@ -136,6 +136,15 @@ __device__ __forceinline__ int group_of(int64_t key, const GroupBounds &gb, int6
     return kGroups - 1;
 }
 
+// group_of, then the copy rule: a row of one A nonzero whose B rows are
+// strictly ascending (`single`) that would take a later group than
+// gb.copy_group takes that one (its block kernels copy the scaled B row).
+__device__ __forceinline__ int group_of_row(int64_t key, const GroupBounds &gb, int64_t ncols,
+                                            bool single) {
+    const int g = group_of(key, gb, ncols);
+    return (single && gb.copy_group > 0 && g > gb.copy_group) ? (int)gb.copy_group : g;
+}
+
 // Largest r in [0, n) with rp[r] <= j (rp non-decreasing, rp[0] <= j).
 __device__ __forceinline__ int lds_upper_row(const int64_t *rp, int n, int64_t j) {
     int lo = 0, hi = n;
@@ -166,7 +175,7 @@ __device__ __forceinline__ int64_t num_key(int64_t nnz, int64_t ip, int64_t ncol
 // thread, valid < nrows) plus per-product sums of `key`: total, max, and the
 // group-7 (chunked) rows with their A nonzeros, split-table size and chunk
 // count (nch per row).
-__device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64_t alen,
+__device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64_t alen, bool single,
                                                 bool valid, const GroupBounds &gb, int nblk,
                                                 int64_t *blkcnt, ProdStats *st, int nch,
                                                 bool ip_stats, int64_t ncols) {
@@ -174,7 +183,7 @@ __device__ __forceinline__ void block_histogram(int64_t key, int64_t gkey, int64
     __shared__ unsigned long long red[kRowBlock / 64][5];
     if (threadIdx.x < kGroups) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int g = valid ? group_of(gkey, gb, ncols) : -1;
+    const int g = valid ? group_of_row(gkey, gb, ncols, single) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int b = 0; b < kGroups; ++b) {
@@ -312,8 +321,9 @@ __global__ __launch_bounds__(kRowBlock) void k_ip_groups(const ProdDev *__restri
     const int64_t row = blk.i0 + threadIdx.x;
     const int64_t key = valid ? ip[P.row_base + row] : 0;
     const int64_t alen = valid ? P.rptA[row + 1] - P.rptA[row] : 0;
-    block_histogram(key, sym_key(key, P.n), alen, valid, gb, nblk, blkcnt, stats + blk.p, P.nch,
-                    true, P.n);
+    const bool single = alen == 1 && P.b_unique == 1;
+    block_histogram(key, sym_key(key, P.n), alen, single, valid, gb, nblk, blkcnt, stats + blk.p,
+                    P.nch, true, P.n);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__restrict__ prods,
@@ -329,7 +339,9 @@ __global__ __launch_bounds__(kRowBlock) void k_count_groups(const ProdDev *__res
     const int64_t r = P.row_base + blk.i0 + threadIdx.x;
     const int64_t k = valid ? key[r] : 0;
     const int64_t gk = valid ? num_key(k, ip[r], P.n) : 0;
-    block_histogram(k, gk, 0, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false, P.n);
+    const int64_t row = blk.i0 + threadIdx.x;
+    const bool single = valid && P.b_unique == 1 && P.rptA[row + 1] - P.rptA[row] == 1;
+    block_histogram(k, gk, 0, single, valid, gb, nblk, blkcnt, stats + blk.p, P.nch, false, P.n);
 }
 
 __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict__ prods,
@@ -351,7 +363,8 @@ __global__ __launch_bounds__(kRowBlock) void k_scatter(const ProdDev *__restrict
         k = key[P.row_base + row];
         k = ip ? num_key(k, ip[P.row_base + row], P.n) : sym_key(k, P.n);
     }
-    const int g = valid ? group_of(k, gb, P.n) : -1;
+    const bool single = valid && P.b_unique == 1 && P.rptA[row + 1] - P.rptA[row] == 1;
+    const int g = valid ? group_of_row(k, gb, P.n, single) : -1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int rank = 0;

@@ -224,7 +224,7 @@ def test_identity_exact():
 
 def test_ip_and_maps_bit_exact():
     import torch
-    a = gen.rmat(12, 16, seed=21)
+    a = gen.rmat(13, 16, seed=21)
     da, db = spgemm.to_device(a), spgemm.to_device(a)
     opt = spgemm.default_options()
     plan = spgemm.Plan(da, db, opt)
@@ -234,7 +234,11 @@ def test_ip_and_maps_bit_exact():
         m, gs = plan.export(1)
         # symbolic key: intermediate products capped at B's column count
         key = np.minimum(oracle.ip(a, a), a.ncols)
-        _, order, offs = oracle.bins_reference(key, list(opt.sym_upper))
+        # rows of one A nonzero (B's rows strictly ascending) go no further
+        # than the first block group
+        single = np.diff(a.rpt) == 1
+        assert np.any(single & (key > opt.sym_upper[5]))
+        _, order, offs = oracle.bins_reference(key, list(opt.sym_upper), single)
         mm = m.cpu().numpy()
         assert np.all((mm >> 32) == 0)
         assert np.array_equal(mm & 0xffffffff, order)
@@ -244,7 +248,7 @@ def test_ip_and_maps_bit_exact():
         counts = oracle.row_counts(a, a)
         # numeric key: output length, raised to ceil(IP / 16) capped at B's columns
         key2 = np.maximum(counts, np.minimum((oracle.ip(a, a) + 15) // 16, a.ncols))
-        _, order2, offs2 = oracle.bins_reference(key2, list(opt.num_upper))
+        _, order2, offs2 = oracle.bins_reference(key2, list(opt.num_upper), single)
         assert np.array_equal(m2.cpu().numpy() & 0xffffffff, order2)
         assert gs2 == offs2.tolist()
         assert np.array_equal(np.diff(plan.rpts[0].cpu().numpy()), counts)
@@ -267,7 +271,7 @@ def test_symbolic_key_capped_at_columns():
     try:
         m, gs = plan.export(1)
         key = np.minimum(oracle.ip(a, b), b.ncols)
-        _, order, offs = oracle.bins_reference(key, list(opt.sym_upper))
+        _, order, offs = oracle.bins_reference(key, list(opt.sym_upper), np.diff(a.rpt) == 1)
         assert np.array_equal(m.cpu().numpy() & 0xffffffff, order)
         assert gs == offs.tolist()
         assert gs[7] == gs[8]      # no chunked rows although IP reaches ~10^4

@@ -45,6 +45,25 @@ def test_bins_brute_force_and_boundaries():
     assert offsets[-1] == keys.shape[0]
 
 
+def test_bins_copy_rule_brute_force():
+    """Single-nonzero rows past the copy group take the copy group; every
+    other row keeps its bound-derived group (brute force over all rows)."""
+    upper = [0, 16, 64, 64, 256, 1024, 1024]
+    rng = np.random.default_rng(3)
+    keys = rng.integers(0, 5000, 400)
+    keys[:20] = 0
+    single = rng.random(400) < 0.4
+    bins, order, offsets = oracle.bins_reference(keys, upper, single, 5)
+    plain, _, _ = oracle.bins_reference(keys, upper)
+    for i in range(400):
+        want = 5 if (single[i] and plain[i] > 5) else plain[i]
+        assert bins[i] == want, (i, keys[i], single[i], bins[i])
+    assert np.any(single & (plain > 5)) and np.any(~single & (plain > 5))
+    for b in range(len(upper) + 1):
+        seg = order[offsets[b]:offsets[b + 1]]
+        assert np.all(bins[seg] == b) and np.all(np.diff(seg) > 0)
+
+
 def test_mcl_step_hand_example():
     rpt = np.array([0, 3, 3, 4])
     col = np.array([0, 1, 2, 5], dtype=np.int32)
