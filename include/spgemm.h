@@ -173,7 +173,17 @@ typedef struct {
      * table.  Requires sym_upper[1] and num_upper[1] <= 32.  0 = off (the
      * lane-group kernels). */
     int32_t row_thread;
-    int32_t reserved;        /* must be 0 */
+    /* Accumulation precision of the column-chunked rows (group 7, the rows
+     * with the longest outputs): 0 = FP32, as the paper's atomic adds of
+     * valA x valB (Algorithm 4); 1 = FP64: each product a * b is formed
+     * exactly in FP64, the sums are kept in FP64 and every output is rounded
+     * to FP32 once.  With 1 the plan uses chunks of at most 2048 columns
+     * (chunk_cols is lowered to 2048), num_rank_cap 2048, chunk_merge 1 and
+     * chunks_per_item 1, and B must hold fewer than 2^30 nonzeros when such
+     * rows exist (else SPGEMM_EINVAL).  The other groups accumulate in FP32;
+     * lower the group bounds to send more rows to group 7 (every row whose
+     * key exceeds num_upper[6]).  Device-driven plans have no group 7. */
+    int32_t accumulate;
 } spgemm_options;
 
 typedef struct spgemm_plan spgemm_plan;

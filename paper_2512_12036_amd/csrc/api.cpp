@@ -117,8 +117,8 @@ struct spgemm_plan {
     // Host containers draw from `mr`: the heap for ordinary plans, a static
     // host buffer for the allocation-free entry point.
     explicit spgemm_plan(std::pmr::memory_resource *r = std::pmr::new_delete_resource())
-        : A(r), B(r), hprods(r), hblks(r), hstats(r), nnz_c(r), timed(r), allocs(r),
-          dev_rpt(r), bs_perm(r), bs_val(r) {}
+        : A(r), B(r), hprods(r), hblks(r), hstats(r), nnz_c(r), timed(r), dev_rpt(r),
+          bs_perm(r), bs_val(r), allocs(r) {}
     hipStream_t stream = nullptr;
     spgemm_alloc_fn afn = nullptr;
     spgemm_free_fn ffn = nullptr;
@@ -433,7 +433,8 @@ spgemm_status check_options(const spgemm_options &o) {
         return SPGEMM_EINVAL;
     if (o.validate < 0 || o.validate > 2) return SPGEMM_EINVAL;
     if (o.item_limit < 0) return SPGEMM_EINVAL;
-    if (o.row_thread < 0 || o.row_thread > 1 || o.reserved != 0) return SPGEMM_EINVAL;
+    if (o.row_thread < 0 || o.row_thread > 1) return SPGEMM_EINVAL;
+    if (o.accumulate < 0 || o.accumulate > 1) return SPGEMM_EINVAL;
     if (o.row_thread && (o.sym_upper[1] > kRtSlots / 2 || o.num_upper[1] > kRtSlots / 2))
         return SPGEMM_EINVAL;
     if (o.profile < 0 || o.profile > 1) return SPGEMM_EINVAL;
@@ -451,6 +452,17 @@ spgemm_status check_options(const spgemm_options &o) {
         return SPGEMM_EINVAL;
     if (o.graph < 0 || o.graph > 1) return SPGEMM_EINVAL;
     return SPGEMM_OK;
+}
+
+// FP64 accumulation (accumulate = 1) takes every column chunk through the
+// rank kernel's FP64 form: chunks of at most 2048 columns, a rank cap of
+// 2048 (so no chunk is dense), no merging, one chunk per item.
+void apply_accumulate(spgemm_options &o) {
+    if (o.accumulate != 1) return;
+    if (o.chunk_cols > 2048) o.chunk_cols = 2048;
+    o.num_rank_cap = 2048;
+    o.chunk_merge = 1;
+    o.chunks_per_item = 1;
 }
 
 spgemm_status check_csr(const spgemm_csr &m, bool need_values) {
@@ -710,6 +722,8 @@ spgemm_status plan_create_impl(spgemm_plan *p, int nprod, const spgemm_csr *A,
     ST_TRY(sort_b_rows(p, ps));
     for (int q = 0; q < nprod; ++q)
         if (p->hprods[q].b_sorted != 1 || p->B[q].nnz >= (int64_t(1) << 30)) p->fast = false;
+    // FP64 accumulation runs on the rank kernel, which needs the fast path
+    if (p->opt.accumulate == 1 && p->nh > 0 && !p->fast) return SPGEMM_EINVAL;
     if (p->nh != p->sym_start[kGroups] - p->sym_start[kGroups - 1]) return SPGEMM_EINTERNAL;
     if (p->h_items > item_limit(p->opt)) return SPGEMM_EOVERFLOW;
 
@@ -939,6 +953,7 @@ spgemm_status create_common(spgemm_plan **out, int32_t nprod, const spgemm_csr *
     spgemm_options o;
     if (opt) o = *opt; else spgemm_default_options(&o);
     ST_TRY(check_options(o));
+    apply_accumulate(o);
     spgemm_plan *p = new (std::nothrow) spgemm_plan();
     if (!p) return SPGEMM_ENOMEM;
     p->stream = (hipStream_t)stream;
@@ -1179,10 +1194,12 @@ spgemm_status numeric_launch(spgemm_plan *p, hipStream_t st) {
             // accumulator)
             TimeScope ts(p, "num.g7r");
             const int cap = p->opt.num_rank_cap;
+            const bool f64 = p->opt.accumulate == 1;
             if (!split) {
-                launch_num_chunk_rank(p->wmax, p->dprods, p->ndesc, p->sabs, p->d_items,
-                                      p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc, cap, false,
-                                      p->flags, st);
+                if (!launch_num_chunk_rank(p->wmax, p->dprods, p->ndesc, p->sabs, p->d_items,
+                                           p->chunk_cnt, p->chunk_pos, p->sbits, p->wpc, cap,
+                                           false, p->flags, st, f64))
+                    return SPGEMM_EINTERNAL;
             } else {
                 const ChunkDesc *r = p->ndesc_split + p->n_dense;
                 const struct { int64_t n; int w, cap; } parts[4] = {
@@ -1191,10 +1208,11 @@ spgemm_status numeric_launch(spgemm_plan *p, hipStream_t st) {
                     {p->n_m1, p->wmax_item, cap},
                     {p->n_m0, p->wmax_item, cap / 2}};
                 for (const auto &q : parts) {
-                    if (q.n > 0)
-                        launch_num_chunk_rank(q.w, p->dprods, r, p->sabs, q.n, p->chunk_cnt,
-                                              p->chunk_pos, p->sbits, p->wpc, q.cap, true,
-                                              p->flags, st);
+                    if (q.n > 0 &&
+                        !launch_num_chunk_rank(q.w, p->dprods, r, p->sabs, q.n, p->chunk_cnt,
+                                               p->chunk_pos, p->sbits, p->wpc, q.cap, true,
+                                               p->flags, st, f64))
+                        return SPGEMM_EINTERNAL;
                     r += q.n;
                 }
             }
@@ -1433,6 +1451,7 @@ spgemm_status spgemm_plan_create_device(spgemm_plan **out, int32_t nprod, const 
     spgemm_options o;
     if (opt) o = *opt; else spgemm_default_options(&o);
     ST_TRY(check_options(o));
+    apply_accumulate(o);
     spgemm_plan *p = new (std::nothrow) spgemm_plan();
     if (!p) return SPGEMM_ENOMEM;
     p->stream = (hipStream_t)stream;
@@ -1771,6 +1790,7 @@ spgemm_status spgemm_multiply_noalloc(const spgemm_csr *A, const spgemm_csr *B,
     spgemm_options o;
     if (opt) o = *opt; else spgemm_default_options(&o);
     ST_TRY(check_options(o));
+    apply_accumulate(o);
     o.profile = 0;  // no timing events
     o.graph = 0;    // no graph objects
     std::lock_guard<std::mutex> lock(g_noalloc_mu);

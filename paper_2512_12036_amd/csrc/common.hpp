@@ -122,6 +122,26 @@ __device__ __forceinline__ int64_t lin_block() {
     return (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
 }
 
+// Work order over the eight dies (XCDs) of the chip.  Workgroups go to the
+// dies round-robin in order of their linear index, so work unit w of a
+// walk (a workgroup's index, or index + k * grid for a grid walking its
+// units) runs on die w % 8, and consecutive units would land on eight
+// different L2 caches.  xcd_unit(w, n) renumbers [0, n) so that every die
+// takes runs of kXcdRun consecutive units: the column chunks of one row then
+// share that die's L2 (the row's A nonzeros and sub-range bounds, and the
+// cache lines of B that straddle two chunks).  A bijection on [0, n): whole
+// groups of 8 * kXcdRun units are interleaved, the tail keeps its order.
+#ifndef SPG_XCD_RUN
+#define SPG_XCD_RUN 4
+#endif
+constexpr int64_t kXcds = 8, kXcdRun = SPG_XCD_RUN;
+__host__ __device__ __forceinline__ int64_t xcd_unit(int64_t w, int64_t n) {
+    constexpr int64_t span = kXcds * kXcdRun;
+    if (w >= n / span * span) return w;
+    const int64_t r = w / kXcds;
+    return r / kXcdRun * span + (w % kXcds) * kXcdRun + r % kXcdRun;
+}
+
 // Device-driven launches cover an upper bound of a group's rows and read the
 // group's place in the row map from the device (gstart[gsel .. gsel + 1]).
 __device__ __forceinline__ void group_range(const int64_t *gstart, int gsel,
@@ -265,11 +285,13 @@ void launch_desc_split(const ChunkDesc *desc, int64_t nitems, const int64_t *fa,
                        const int64_t *chunk_cnt, const int64_t *chunk_pos, const int64_t *nlim,
                        ChunkDesc *out, hipStream_t s);
 // Chunks with at most rank_cap outputs (fast path, one chunk per item only).
+// f64: FP64 accumulation, for items of at most 2048 columns and a rank cap
+// of 1024 or 2048; false (nothing launched) for any other shape.
 bool num_chunk_rank_used(bool fast, int kper, int rank_cap);
-void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+bool launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
                            const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
                            const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
-                           bool resolved, int *err, hipStream_t s);
+                           bool resolved, int *err, hipStream_t s, bool f64 = false);
 
 // Algorithm 1 alone, aggregated into out[3] (device): sum of intermediate
 // products, sum of min(ip, ncols), largest row.

@@ -701,22 +701,22 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
     __shared__ uint32_t st_s[WG];
     __shared__ int st_e[WG + 1];
     __shared__ int64_t wsum[WG / 64];
-    int64_t it = blockIdx.x;
+    int64_t w = blockIdx.x;  // walk index; the item is xcd_unit(w, nitems)
     const int64_t stride = gridDim.x;
-    if (it >= nitems) return;
+    if (w >= nitems) return;
     int clean = 0;  // bitmap words [0, clean) are zero (each item re-zeroes what it used)
-    ChunkDesc d = desc_unpack(desc_word(desc, it));
+    ChunkDesc d = desc_unpack(desc_word(desc, xcd_unit(w, nitems)));
     ItemIn in = item_load<false>(prods, d, sabs, nullptr, nullptr, nullptr, 0);
-    uint64_t wnext = it + stride < nitems ? desc_word(desc, it + stride) : 0ull;
+    uint64_t wnext = w + stride < nitems ? desc_word(desc, xcd_unit(w + stride, nitems)) : 0ull;
     for (;;) {
-        const int64_t itn = it + stride;
-        const bool more = itn < nitems;
+        const int64_t wn = w + stride;
+        const bool more = wn < nitems;
         ChunkDesc dn;
         ItemIn inn;
         if (more) {
             dn = desc_unpack(wnext);
             inn = item_load<false>(prods, dn, sabs, nullptr, nullptr, nullptr, 0);
-            wnext = itn + stride < nitems ? desc_word(desc, itn + stride) : 0ull;
+            wnext = wn + stride < nitems ? desc_word(desc, xcd_unit(wn + stride, nitems)) : 0ull;
         }
         const ProdDev &P = prods[d.prod];
         const int c = d.q;
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
             chunk_cnt[d.slot0 + c + threadIdx.x] = 0;  // chunks merged into this item
         }
         if (!more) break;
-        it = itn;
+        w = wn;
         d = dn;
         in = inn;
     }
@@ -789,22 +789,22 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ int st_e[WG + 1];
     __shared__ float st_a[WG];
     __shared__ int wsum[WG / 64];
-    int64_t it = blockIdx.x;
+    int64_t w = blockIdx.x;  // walk index; the item is xcd_unit(w, nitems)
     const int64_t stride = gridDim.x;
-    if (it >= nitems) return;
+    if (w >= nitems) return;
     bool cleared = false;  // the accumulator is cleared before the first item taken
-    ChunkDesc d = desc_unpack(desc_word(desc, it));
+    ChunkDesc d = desc_unpack(desc_word(desc, xcd_unit(w, nitems)));
     ItemIn in = item_load<true>(prods, d, sabs, chunk_cnt, chunk_pos, sbits, wpc, resolved);
-    uint64_t wnext = it + stride < nitems ? desc_word(desc, it + stride) : 0ull;
+    uint64_t wnext = w + stride < nitems ? desc_word(desc, xcd_unit(w + stride, nitems)) : 0ull;
     for (;;) {
-        const int64_t itn = it + stride;
-        const bool more = itn < nitems;
+        const int64_t wn = w + stride;
+        const bool more = wn < nitems;
         ChunkDesc dn;
         ItemIn inn;
         if (more) {
             dn = desc_unpack(wnext);
             inn = item_load<true>(prods, dn, sabs, chunk_cnt, chunk_pos, sbits, wpc, resolved);
-            wnext = itn + stride < nitems ? desc_word(desc, itn + stride) : 0ull;
+            wnext = wn + stride < nitems ? desc_word(desc, xcd_unit(wn + stride, nitems)) : 0ull;
         }
         const ProdDev &P = prods[d.prod];
         const int c = d.q;
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if (threadIdx.x == 0 && base != expect) atomicOr(err, kErrChunk);
         }
         if (!more) break;
-        it = itn;
+        w = wn;
         d = dn;
         in = inn;
     }
@@ -984,7 +984,11 @@ __device__ __forceinline__ RankIn<WMAX / 2048> rank_load(const ProdDev *prods, u
     return in;
 }
 
-template <int WMAX, int CAP, int IPW, int WAVES>
+// Acc: the accumulator type.  double (the FP64-accumulation option): every
+// product a * b is formed exactly in FP64 (two FP32 significands fit in
+// FP64's), the sums are FP64 LDS atomics, and each output is rounded to FP32
+// once, on its way out.
+template <int WMAX, int CAP, int IPW, int WAVES, typename Acc = float>
 __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__restrict__ prods,
                                                        const ChunkDesc *__restrict__ desc,
                                                        int64_t nitems,
@@ -1000,17 +1004,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
     // each wave of the workgroup takes its own items, with its own LDS
     // slices; the waves never meet at a barrier
     __shared__ uint2 sw_all[WAVES][NWD];         // {word, outputs before the word}
-    __shared__ float cacc_all[WAVES][CAP + 64];  // + one dummy slot per lane
+    __shared__ Acc cacc_all[WAVES][CAP + 64];  // + one dummy slot per lane
     __shared__ uint32_t st_s_all[WAVES][64];
     __shared__ int st_e_all[WAVES][65];
     __shared__ float st_a_all[WAVES][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint2 *sw = sw_all[wave];
-    float *cacc = cacc_all[wave];
+    Acc *cacc = cacc_all[wave];
     uint32_t *st_s = st_s_all[wave];
     int *st_e = st_e_all[wave];
     float *st_a = st_a_all[wave];
-    const int64_t first = (lin_block() * WAVES + wave) * IPW;
+    const int64_t first = (xcd_unit(lin_block(), (nitems + WAVES * IPW - 1) / (WAVES * IPW)) *
+                               WAVES + wave) * IPW;
     if (first >= nitems) return;  // wave-uniform
     const int64_t last = first + IPW < nitems ? first + IPW : nitems;
     RankIn<KMAX> cur = rank_load<WMAX, CAP>(prods, desc_word(desc, first), sabs, chunk_cnt,
@@ -1055,8 +1060,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
                     sw[lane * K + k] = make_uint2(cur.wv[k], (uint32_t)pre);
                     pre += __popc(cur.wv[k]);
                 }
-            for (int r = lane; r < expect; r += 64) cacc[r] = 0.f;
-            cacc[CAP + lane] = 0.f;
+            for (int r = lane; r < expect; r += 64) cacc[r] = Acc(0);
+            cacc[CAP + lane] = Acc(0);
             if (lane == 0 && total != expect) atomicOr(err, kErrChunk);
             wave_lds_sync();
             const int dummy = CAP + lane;
@@ -1070,7 +1075,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
                 P, d, in, sabs, st_s, st_e, st_a, nullptr,
                 [&](const int *cc, const float *aa, const float *vv, const bool *ok) {
                     int idx[NVT];
-                    float add[NVT];
+                    Acc add[NVT];
 #pragma unroll
                     for (int v = 0; v < NVT; ++v) {
                         const int rel = cc[v] - lo;
@@ -1080,9 +1085,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
                         stray |= ok[v] && !in_structure;
                         const bool take = ok[v] && in_structure;
                         idx[v] = take ? (int)e.y + __popc(e.x & (bit - 1u)) : dummy;
-                        add[v] = take ? aa[v] * vv[v] : 0.f;
+                        add[v] = take ? Acc(aa[v]) * Acc(vv[v]) : Acc(0);
                     }
-                    lds_fadd_many<NVT>(cacc, idx, add);
+                    if constexpr (std::is_same<Acc, float>::value) {
+                        lds_fadd_many<NVT>(cacc, idx, add);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < NVT; ++v)
+                            __hip_atomic_fetch_add(cacc + idx[v], add[v], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 },
                 lane);
             wave_lds_sync();
@@ -1098,7 +1110,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             constexpr bool kColsInTable = 2 * NWD >= CAP;
             int *ccol = kColsInTable ? reinterpret_cast<int *>(sw) : reinterpret_cast<int *>(cacc);
             if (!kColsInTable) {
-                for (int r = lane; r < ex; r += 64) gst(valC + r, cacc[r]);
+                for (int r = lane; r < ex; r += 64) gst(valC + r, (float)cacc[r]);
                 wave_lds_sync();
             }
             {
@@ -1119,7 +1131,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             }
             wave_lds_sync();
             for (int r = lane; r < ex; r += 64) {
-                if (kColsInTable) gst(valC + r, cacc[r]);
+                if (kColsInTable) gst(valC + r, (float)cacc[r]);
                 gst(colC + r, ccol[r]);
             }
             wave_lds_sync();  // the accumulator and structure are reused by the next item
@@ -1445,12 +1457,34 @@ bool num_chunk_rank_used(bool fast, int kper, int rank_cap) {
     return fast && kper == 1 && rank_cap > 0;
 }
 
-// wmax: widest item of the launch.
-void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+// FP64 accumulation: the plan keeps every item within 2048 columns (chunks
+// of at most 2048 columns, not merged), so only that width is instantiated.
+static bool num_rank_launch_f64(int wmax, const ProdDev *prods, const ChunkDesc *desc,
+                                const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
+                                const int64_t *chunk_pos, const uint32_t *sbits, int wpc,
+                                int rank_cap, bool resolved, int *err, hipStream_t s) {
+    if (wmax > 2048 || rank_cap < 1024) return false;
+    const int res = resolved ? 1 : 0;
+    const dim3 grid = grid1d(nitems, 64), block(64);
+    if (rank_cap <= 1024)
+        hipLaunchKernelGGL((k_num_chunk_rank<2048, 1024, 1, 1, double>), grid, block, 0, s,
+                           prods, desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+    else
+        hipLaunchKernelGGL((k_num_chunk_rank<2048, 2048, 1, 1, double>), grid, block, 0, s,
+                           prods, desc, nitems, sabs, chunk_cnt, chunk_pos, sbits, wpc, res, err);
+    return true;
+}
+
+// wmax: widest item of the launch.  f64: accumulate in FP64 (returns false,
+// launching nothing, for a shape the FP64 kernel does not cover).
+bool launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc,
                            const uint32_t *sabs, int64_t nitems, const int64_t *chunk_cnt,
                            const int64_t *chunk_pos, const uint32_t *sbits, int wpc, int rank_cap,
-                           bool resolved, int *err, hipStream_t s) {
-    if (nitems <= 0 || rank_cap <= 0) return;
+                           bool resolved, int *err, hipStream_t s, bool f64) {
+    if (nitems <= 0 || rank_cap <= 0) return true;
+    if (f64)
+        return num_rank_launch_f64(wmax, prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits,
+                                   wpc, rank_cap, resolved, err, s);
     if (wmax <= 2048)
         num_rank_launch<2048>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits, wpc,
                               rank_cap, resolved, err, s);
@@ -1469,6 +1503,7 @@ void launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc
     else
         num_rank_launch<kMaxItemCols>(prods, desc, sabs, nitems, chunk_cnt, chunk_pos, sbits,
                                       wpc, rank_cap, resolved, err, s);
+    return true;
 }
 
 template <int WMAX>

@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
                 ("sym_chunk_threads", ctypes.c_int32), ("num_rank_cap", ctypes.c_int32),
                 ("chunk_merge", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("item_limit", _I64), ("row_thread", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("accumulate", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -172,7 +172,8 @@ def default_options() -> Options:
 def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
                  profile=None, chunks_per_item=None, chunk_wgs_per_cu=None,
                  chunk_threads=None, sym_chunk_threads=None, num_rank_cap=None,
-                 chunk_merge=None, graph=None, item_limit=None, row_thread=None) -> Options:
+                 chunk_merge=None, graph=None, item_limit=None, row_thread=None,
+                 accumulate=None) -> Options:
     o = default_options()
     if sym_upper is not None:
         for g, v in enumerate(sym_upper):
@@ -204,6 +205,8 @@ def make_options(sym_upper=None, num_upper=None, chunk_cols=None, validate=None,
         o.item_limit = int(item_limit)
     if row_thread is not None:
         o.row_thread = int(row_thread)
+    if accumulate is not None:
+        o.accumulate = int(accumulate)
     return o
 
 

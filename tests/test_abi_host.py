@@ -79,7 +79,7 @@ def _create(a, b, o):
                                          ("chunk_merge", 3), ("chunk_merge", 16),
                                          ("graph", 2), ("graph", -1), ("validate", 3),
                                          ("item_limit", -1), ("row_thread", 2),
-                                         ("reserved", 1)])
+                                         ("accumulate", 2), ("accumulate", -1)])
 def test_bad_options_rejected(field, value):
     o = spgemm.default_options()
     setattr(o, field, value)
