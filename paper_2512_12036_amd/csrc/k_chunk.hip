@@ -1101,39 +1101,67 @@ __global__ __launch_bounds__(64 * WAVES) void k_num_chunk_rank(const ProdDev *__
             const int ex = (int)expect;
             float *valC = P.valC + out0;
             int32_t *colC = P.colC + out0;
-            // The columns: every lane expands the set bits of its structure
-            // words (still in registers) at their ranks, then coalesced
-            // copies.  They go into the rank table, which is no longer read,
-            // when it has room for the item's outputs (values and columns then
-            // leave together); else into the accumulator once the values have
-            // left.
-            constexpr bool kColsInTable = 2 * NWD >= CAP;
-            int *ccol = kColsInTable ? reinterpret_cast<int *>(sw) : reinterpret_cast<int *>(cacc);
-            if (!kColsInTable) {
-                for (int r = lane; r < ex; r += 64) gst(valC + r, (float)cacc[r]);
-                wave_lds_sync();
-            }
-            {
-                int r = pre0;
+            // The values leave first, coalesced and already in column order.
+            for (int r = lane; r < ex; r += 64) gst(valC + r, (float)cacc[r]);
+            // The columns, balanced over the lanes.  The structure's non-empty
+            // words are listed in column order in the rank table's space (no
+            // longer read), each as {word, (word index << 16) | rank of its
+            // first output}; lane l then emits the ranks [l S, l S + S),
+            // S = ceil(ex / 64): a binary search for the word that holds its
+            // first rank, then a walk through the set bits of that word and
+            // the next ones.  (A lane expanding its own words would take as
+            // many steps as the densest lane's words hold bits: about six
+            // times as many on R-MAT chunks.)  The columns are staged in the
+            // accumulator, whose values have left, and copied out coalesced.
+            int nzc = 0;
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
+            for (int k = 0; k < KMAX; ++k) nzc += (k < K && cur.wv[k] != 0u) ? 1 : 0;
+            int m;
+            int pos = wg_excl_scan<64, int>(nzc, nullptr, m);
+            {
+                int pre = pre0;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
                     if (k < K) {
-                        uint32_t w = cur.wv[k];
-                        const int base = lo + ((lane * K + k) << 5);
-                        while (w) {
-                            const int b = __builtin_ctz(w);
-                            w &= w - 1u;
-                            if (r < ex) ccol[r] = base + b;
-                            ++r;
+                        const uint32_t w = cur.wv[k];
+                        if (w) {
+                            sw[pos] = make_uint2(w, ((uint32_t)(lane * K + k) << 16) | (uint32_t)pre);
+                            ++pos;
                         }
+                        pre += __popc(w);
                     }
+            }
+            wave_lds_sync();  // the list is written; the values have been read
+            int *ccol = reinterpret_cast<int *>(cacc);
+            const int S = (ex + 63) >> 6;
+            const int t0 = lane * S;
+            const int t1 = t0 + S < ex ? t0 + S : ex;
+            if (t0 < t1 && m > 0) {
+                int jl = 0, jh = m - 1;  // the last listed word whose first rank is <= t0
+                while (jl < jh) {
+                    const int mid = (jl + jh + 1) >> 1;
+                    if ((int)(sw[mid].y & 0xffffu) <= t0) jl = mid;
+                    else jh = mid - 1;
+                }
+                uint2 e = sw[jl];
+                uint32_t w = e.x;
+                for (int q = t0 - (int)(e.y & 0xffffu); q > 0 && w; --q) w &= w - 1u;
+                int xb = lo + (int)((e.y >> 16) << 5);
+                int j = jl;
+                for (int t = t0; t < t1; ++t) {
+                    while (w == 0u && j + 1 < m) {
+                        ++j;
+                        e = sw[j];
+                        w = e.x;
+                        xb = lo + (int)((e.y >> 16) << 5);
+                    }
+                    if (w == 0u) break;  // fewer set bits than outputs (flagged above)
+                    ccol[t] = xb + __builtin_ctz(w);
+                    w &= w - 1u;
                 }
             }
             wave_lds_sync();
-            for (int r = lane; r < ex; r += 64) {
-                if (kColsInTable) gst(valC + r, (float)cacc[r]);
-                gst(colC + r, ccol[r]);
-            }
+            for (int r = lane; r < ex; r += 64) gst(colC + r, ccol[r]);
             wave_lds_sync();  // the accumulator and structure are reused by the next item
         }
         if (IPW == 1 || !more) break;
