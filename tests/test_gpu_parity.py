@@ -393,3 +393,23 @@ def test_row_thread_batch_and_graph():
                                           exact_values=True) is None, (graph, rep, q)
         finally:
             plan.free()
+
+
+@pytest.mark.parametrize("group,nk", [(1, 5), (1, 40), (2, 9), (2, 100), (3, 70), (4, 20),
+                                      (4, 64), (4, 100), (4, 300)])
+def test_direct_mapped_shared_columns(group, nk):
+    # every B row holds the same columns (the layout of the served GNN
+    # features): one lane's products of a round name the same column when
+    # they come from different B rows
+    ncols = 8 * (8, 16, 32, 64)[group - 1]   # the group's table size
+    rng = np.random.default_rng(70 + group)
+    n = 700
+    kept = np.sort(rng.choice(ncols, min(nk, ncols), replace=False)).astype(np.int32)
+    k = kept.size
+    b = gen.Csr(n, ncols, np.arange(n + 1, dtype=np.int64) * k, np.tile(kept, n),
+                rng.integers(1, 4, n * k).astype(np.float32))
+    a = gen.int_valued(gen.skewed_csr(1100, n, seed=80 + group, max_len=40, heavy_rows=0), 5)
+    run_and_compare(a, b, options=forced_options(group), exact=True,
+                    label=f"shared g{group} nk{k}")
+    af = a.with_values(rng.uniform(-1, 1, a.nnz).astype(np.float32))
+    run_and_compare(af, b, options=forced_options(group), label=f"shared f32 g{group} nk{k}")
