@@ -108,3 +108,19 @@ def test_integer_exact_fp64():
     a = gen.int_valued(gen.rmat(12, 16, seed=45), 6)
     o = with_accumulate(forced_options(7, 1024), 1)
     run_and_compare(a, a, options=o, exact=True, label="f64 integer")
+
+
+def test_batch_plan_fp64():
+    # three products of different widths in one batched plan
+    mats = [signed(gen.rmat(11, 16, seed=46), 7), signed(gen.rmat(12, 16, seed=47), 8),
+            signed(gen.skewed_csr(900, 900, seed=48, max_len=300, heavy_rows=4,
+                                  heavy_len=800), 9)]
+    o = with_accumulate(forced_options(7, 512), 1)
+    log("[gpu] f64 batch of 3")
+    cs = spgemm.matmul_batch([spgemm.to_device(m) for m in mats],
+                             [spgemm.to_device(m) for m in mats], o)
+    for m, c in zip(mats, cs):
+        ref = oracle.product(m, m)
+        msg = oracle.compare(ref, c.rpt.cpu().numpy(), c.col.cpu().numpy(), c.val.cpu().numpy())
+        assert msg is None, msg
+        assert excess(m, m, c, ref) <= TIGHT
