@@ -589,6 +589,10 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
         p->wmax = std::max<int>(p->wmax, P.W);
         P.b_sorted = (b.flags & SPGEMM_ROWS_SORTED) ? 1 : 2;
         P.b_unique = (b.flags & SPGEMM_ROWS_SORTED) ? 1 : 0;
+        // a B of few columns is also kept as row bitmaps, from which the
+        // symbolic phase of direct-mapped rows takes its counts
+        if (b.ncols > 0 && b.ncols <= kBitmapCols && b.nnz > 0 && b.nrows > 0)
+            P.bmw = (int32_t)((b.ncols + 31) / 32);
         for (int64_t i0 = 0; i0 < a.nrows; i0 += kRowBlock) {
             RowBlk rb;
             rb.p = q;
@@ -619,8 +623,21 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
         ST_TRY(dalloc(p, &p->starts, 4 * (kGroups + 1)));
         ST_TRY(dalloc(p, &p->stats, nprod));
         ST_TRY(dalloc(p, &p->flags, 3 + nprod));
+        for (int q = 0; q < nprod; ++q) {
+            ProdDev &P = p->hprods[q];
+            if (P.bmw == 0) continue;
+            uint32_t *bm = nullptr;
+            ST_TRY(dalloc(p, &bm, (size_t)B[q].nrows * P.bmw));
+            P.bmB = bm;
+        }
         return ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk));
     }));
+    for (int q = 0; q < nprod; ++q) {
+        const ProdDev &P = p->hprods[q];
+        if (P.bmw > 0)
+            launch_brow_bitmap(B[q].row_ptr, B[q].col_idx, B[q].nrows, B[q].ncols, P.bmw,
+                               const_cast<uint32_t *>(P.bmB), p->stream);
+    }
     if (!p->noalloc) {
         size_t got = 0;
         void *h = pools().pinned(sizeof(ProdDev) * nprod * kDescSlots, &got);

@@ -12,6 +12,7 @@ constexpr int kGroups = 8;           // row groups, see spgemm.h
 constexpr int kChunkGroup = 7;       // column-chunked group
 constexpr int64_t kIpPerLane = 16;   // numeric grouping: target products per lane
 constexpr int64_t kDirectG4 = 512;   // table slots of group 4 (64 lanes x 8)
+constexpr int64_t kBitmapCols = kDirectG4;  // B kept as row bitmaps up to this many columns
 constexpr int kMaxChunkCols = 16384; // LDS: 64 KiB FP32 dense accumulator
 constexpr int kMaxItemCols = 65536;  // widest merged item (8 KiB LDS bitmap)
 constexpr int kSabsJ = 64;           // A nonzeros per workgroup of the sub-range tables
@@ -52,7 +53,9 @@ struct ProdDev {
                         // the batch-wide row pointers (device-driven plans)
     int32_t b_unique;   // 1: B's rows strictly ascending, so no duplicate columns (B
                         // rows sorted by the plan may hold duplicates: 0)
-    int32_t pad_;
+    int32_t bmw;        // words per row of bmB (0: no bitmaps)
+    const uint32_t *bmB;  // B's rows as column bitmaps (B with at most kBitmapCols
+                          // columns), row k at bmB + k * bmw
 };
 
 // One work item of group 7: the chunks q, q + Q, ... (K of them) of one row,
@@ -295,6 +298,12 @@ bool launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc
 
 // Algorithm 1 alone, aggregated into out[3] (device): sum of intermediate
 // products, sum of min(ip, ncols), largest row.
+// B's rows as column bitmaps (bmw = ceil(ncols / 32) words per row, at most
+// kBitmapCols / 32): out[k * bmw + w] bit b set iff column 32 w + b is in row
+// k.  Columns outside [0, ncols) are ignored.
+void launch_brow_bitmap(const int64_t *rptB, const int32_t *colB, int64_t nrows, int64_t ncols,
+                        int bmw, uint32_t *out, hipStream_t s);
+
 void launch_ip_estimate(const int64_t *rptA, const int32_t *colA, const int64_t *rptB, int64_t m,
                         int64_t ncols, int64_t *out, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);

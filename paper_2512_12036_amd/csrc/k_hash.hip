@@ -163,6 +163,28 @@ __device__ __forceinline__ int ceil_log2(int64_t x) {
 // ---------------------------------------------------------------------------
 // Group kernels: G lanes per row.
 // ---------------------------------------------------------------------------
+// The output columns of row i of a direct-mapped product (P.n <= 8 G) from
+// B's row bitmaps: the OR of the bitmaps of the B rows that the row's A
+// nonzeros name, without visiting a product.  ws lanes per stride (a power
+// of two >= P.bmw, at most G / 4), one word each, G / ws A nonzeros at a
+// time; returns in every lane word (lane & (ws - 1)) of the row's bitmap
+// (zero past P.bmw).
+template <int G>
+__device__ __forceinline__ uint32_t row_bitmap_word(const ProdDev &P, int64_t i, int lane,
+                                                    int &ws) {
+    const int bmw = P.bmw;
+    ws = 1;
+    while (ws < bmw) ws <<= 1;
+    const int w = lane & (ws - 1), r = lane / ws, R = G / ws;
+    const int64_t a0 = gld(P.rptA + i), a1 = gld(P.rptA + i + 1);
+    uint32_t acc = 0u;
+    if (w < bmw)
+        for (int64_t j = a0 + r; j < a1; j += R)
+            acc |= gld(P.bmB + (int64_t)gld(P.colA + j) * bmw + w);
+    for (int off = ws; off < G; off <<= 1) acc |= __shfl_xor(acc, off, G);
+    return acc;
+}
+
 // Walks every intermediate product of row i of P with the G lanes of a group
 // and calls f(col_b, a_value, b_value) for each.  The row's A nonzeros are
 // staged G at a time in the group's LDS slice (B-row start, exclusive prefix
@@ -252,12 +274,19 @@ __device__ __forceinline__ void sym_group_rows(const ProdDev *__restrict__ prods
     int *tab = keys + gi * T;
     int cnt = 0;
     const bool direct = P.n <= T;
-    group_products<G, 4, false>(P, i, lane, st_s + gi * G, st_e + gi * (G + 1), nullptr,
-                                [&](const int *cc, const float *, const float *, const bool *ok) {
-                                    cnt += direct ? lds_mark_many<4>(tab, cc, ok)
-                                                  : lds_insert_many<4>(tab, T - 1, LOG2T, cc,
-                                                                       ok, err);
-                                });
+    if (direct && P.bmw > 0) {
+        // the count from B's row bitmaps: each word once (lanes < ws)
+        int ws;
+        const uint32_t word = row_bitmap_word<G>(P, i, lane, ws);
+        cnt = lane < ws ? __popc(word) : 0;
+    } else {
+        group_products<G, 4, false>(
+            P, i, lane, st_s + gi * G, st_e + gi * (G + 1), nullptr,
+            [&](const int *cc, const float *, const float *, const bool *ok) {
+                cnt += direct ? lds_mark_many<4>(tab, cc, ok)
+                              : lds_insert_many<4>(tab, T - 1, LOG2T, cc, ok, err);
+            });
+    }
     cnt = seg_last<G>(seg_incl_scan<G>(cnt));
     if (lane == 0) row_nnz[P.row_base + i] = cnt;
 }

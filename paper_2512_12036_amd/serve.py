@@ -71,6 +71,7 @@ def _collector_paused(fn):
 
 WS_BYTES_FIXED = 1 << 20      # per-plan descriptors, statistics, scan tiles, rounding
 SYM_CHUNK_MIN = 1024          # default sym_upper[6]: rows above it are column-chunked
+BITMAP_COLS = 512             # B of at most this many columns is also kept as row bitmaps
 
 
 @dataclasses.dataclass
@@ -107,9 +108,12 @@ def workspace_bound(m: int, nnz_a: int, k: int, ncols: int, ip_total: int,
     for the column-chunked rows (more than SYM_CHUNK_MIN possible outputs,
     so at most ip_total / (SYM_CHUNK_MIN + 1) of them) the chunk bounds of
     B's rows, the sub-range tables, the per-chunk counts, bitmaps and the
-    item descriptors of both phases."""
+    item descriptors of both phases; for a B of at most BITMAP_COLS columns,
+    its rows as column bitmaps."""
     per_row = 8 * 3 + 8 * 2 + 4 + 8
     total = WS_BYTES_FIXED + per_row * (m + 1) + 16 * (m // 256 + 1) * 8
+    if 0 < ncols <= BITMAP_COLS:
+        total += 4 * (-(-ncols // 32)) * k + 256          # B's rows as column bitmaps
     if ncols > SYM_CHUNK_MIN and ip_total > SYM_CHUNK_MIN:
         nch = 8 * max(1, -(-ncols // (8 * chunk_cols)))
         w = max(64, -(-(-(-ncols // nch)) // 64) * 64)

@@ -413,3 +413,26 @@ def test_direct_mapped_shared_columns(group, nk):
                     label=f"shared g{group} nk{k}")
     af = a.with_values(rng.uniform(-1, 1, a.nnz).astype(np.float32))
     run_and_compare(af, b, options=forced_options(group), label=f"shared f32 g{group} nk{k}")
+
+
+@pytest.mark.parametrize("group,ncols", [(1, 64), (2, 100), (3, 256), (4, 300), (4, 512),
+                                         (None, 512), (None, 513)])
+def test_row_bitmap_counts(group, ncols):
+    """B of at most 512 columns is also kept as row bitmaps, from which the
+    symbolic phase of direct-mapped rows counts the row's columns (the OR of
+    the bitmaps of the B rows named).  B with duplicate entries, rows stored
+    out of order and empty rows; 513 columns: no bitmaps (the ordinary
+    walk).  Integer values: compared exactly."""
+    rng = np.random.default_rng(ncols)
+    b = gen.random_csr(800, ncols, min(0.5, 30.0 / ncols), 90 + ncols)
+    b = gen.shuffle_rows(with_duplicates(gen.int_valued(b, 91), 92), 93)
+    cnt = np.diff(b.rpt)
+    empty = rng.random(b.nrows) < 0.1                # some B rows emptied
+    keep = ~np.repeat(empty, cnt)
+    rpt = np.zeros(b.nrows + 1, dtype=np.int64)
+    np.cumsum(np.where(empty, 0, cnt), out=rpt[1:])
+    b = gen.Csr(b.nrows, ncols, rpt, b.col[keep], b.val[keep])
+    a = gen.int_valued(gen.skewed_csr(1500, b.nrows, seed=94, max_len=40, heavy_rows=0), 95)
+    opt = None if group is None else forced_options(group)
+    run_and_compare(a, b, options=opt, exact=True, b_sorted=False,
+                    label=f"bitmap g{group} n{ncols}")
