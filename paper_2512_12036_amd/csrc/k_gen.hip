@@ -25,10 +25,17 @@ __global__ __launch_bounds__(256) void k_gnn_features(int64_t n, int nk,
                                                       float *__restrict__ val) {
     const int64_t total = n * nk;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the column slot e % nk, kept up to date by adding the stride's
+    // remainder instead of a 64-bit division per entry
+    const int sr = (int)(stride % nk);
+    int r = (int)(e0 % nk);
+    for (int64_t e = e0; e < total; e += stride) {
         const uint64_t h = splitmix64((uint64_t)e * 4u + off);
-        col[e] = kept[e % nk];
+        col[e] = kept[r];
         val[e] = (float)((h >> 40) + 1) * (1.0f / 16777216.0f);
+        r += sr;
+        if (r >= nk) r -= nk;
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride)
         rpt[i] = i * nk;
