@@ -74,6 +74,21 @@ SYM_CHUNK_MIN = 1024          # default sym_upper[6]: rows above it are column-c
 BITMAP_COLS = 512             # B of at most this many columns is also kept as row bitmaps
 
 
+_STREAMS: dict = {}
+
+
+def _server_streams(device, n: int):
+    """The first n of the process's server streams on `device`.  Servers
+    share them: PyTorch's caching allocator keeps one pool of cached
+    segments per stream, so servers on fresh streams could not reuse what
+    earlier ones cached, and reserved memory would grow with every server."""
+    import torch
+    pool = _STREAMS.setdefault(str(device), [])
+    while len(pool) < n:
+        pool.append(torch.cuda.Stream(device))
+    return pool[:n]
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
@@ -160,7 +175,7 @@ class Server:
         self.options = options
         self.keep = keep_results
         self.device = torch.device(device)
-        self.streams = [torch.cuda.Stream(self.device) for _ in range(n_streams)]
+        self.streams = _server_streams(self.device, n_streams)
 
     @_collector_paused
     def run(self, requests: list[Request], keep_rids=None):
