@@ -510,33 +510,36 @@ void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_i64, grid1d(((n + 255) / 256), 256), dim3(256), 0, s, p, n, v);
 }
 
-// B's rows as column bitmaps, one wave per row: the lanes OR the bits of the
-// row's columns into the row's words in LDS (at most 16 of them), then write
-// them out.  Four rows per 256-thread workgroup.
+// B's rows as column bitmaps, 16 lanes per row (16 rows per 256-thread
+// workgroup): the lanes OR the bits of the row's columns into the row's
+// words in LDS (at most 16 of them), then write them out.  A row's lanes lie
+// in one wave, so their LDS traffic is ordered without a barrier.
 __global__ __launch_bounds__(256) void k_brow_bitmap(const int64_t *__restrict__ rptB,
                                                      const int32_t *__restrict__ colB,
                                                      int64_t nrows, int64_t ncols, int bmw,
                                                      uint32_t *__restrict__ out) {
     constexpr int kWords = (int)(kBitmapCols / 32);
-    __shared__ uint32_t words[4][kWords];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t k = lin_block() * 4 + wave;
-    if (k >= nrows) return;  // wave-uniform; no workgroup barrier follows
-    if (lane < kWords) words[wave][lane] = 0u;
+    constexpr int kLanes = 16;
+    static_assert(kLanes == kWords, "one word per lane of a row");
+    __shared__ uint32_t words[256 / kLanes][kWords];
+    const int sub = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
+    const int64_t k = lin_block() * (256 / kLanes) + sub;
+    if (k >= nrows) return;  // uniform over the row's lanes; no workgroup barrier follows
+    words[sub][lane] = 0u;
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     const int64_t b0 = rptB[k], b1 = rptB[k + 1];
-    for (int64_t t = b0 + lane; t < b1; t += 64) {
+    for (int64_t t = b0 + lane; t < b1; t += kLanes) {
         const int c = colB[t];
-        if (c >= 0 && c < ncols) atomicOr(&words[wave][c >> 5], 1u << (c & 31));
+        if (c >= 0 && c < ncols) atomicOr(&words[sub][c >> 5], 1u << (c & 31));
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    if (lane < bmw) out[k * bmw + lane] = words[wave][lane];
+    if (lane < bmw) out[k * bmw + lane] = words[sub][lane];
 }
 
 void launch_brow_bitmap(const int64_t *rptB, const int32_t *colB, int64_t nrows, int64_t ncols,
                         int bmw, uint32_t *out, hipStream_t s) {
     if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_brow_bitmap, grid1d((nrows + 3) / 4, 256), dim3(256), 0, s, rptB, colB,
+    hipLaunchKernelGGL(k_brow_bitmap, grid1d((nrows + 15) / 16, 256), dim3(256), 0, s, rptB, colB,
                        nrows, ncols, bmw, out);
 }
 
