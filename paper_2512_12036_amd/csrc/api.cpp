@@ -632,12 +632,6 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
         }
         return ensure_scan_tmp(p, std::max<int64_t>(M, (int64_t)kGroups * p->nblk));
     }));
-    for (int q = 0; q < nprod; ++q) {
-        const ProdDev &P = p->hprods[q];
-        if (P.bmw > 0)
-            launch_brow_bitmap(B[q].row_ptr, B[q].col_idx, B[q].nrows, B[q].ncols, P.bmw,
-                               const_cast<uint32_t *>(P.bmB), p->stream);
-    }
     if (!p->noalloc) {
         size_t got = 0;
         void *h = pools().pinned(sizeof(ProdDev) * nprod * kDescSlots, &got);
@@ -655,6 +649,30 @@ spgemm_status plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A, const s
     if (!p->hblks.empty())
         HIP_TRY(hipMemcpyAsync(p->dblks, p->hblks.data(), sizeof(RowBlk) * p->hblks.size(),
                                hipMemcpyHostToDevice, p->stream));
+    // B's row bitmaps: one launch for the batch (its workgroup rows are the
+    // products), as wide as the mean product needs
+    {
+        int64_t rows = 0;
+        int nbm = 0;
+        for (int q = 0; q < nprod; ++q)
+            if (p->hprods[q].bmw > 0) {
+                rows += B[q].nrows;
+                ++nbm;
+            }
+        if (nbm > 0) {
+            const int64_t blocks = std::max<int64_t>(1, (rows / nbm + 15) / 16);
+            if (nprod <= 65535) {
+                launch_brow_bitmap_batch(p->dprods, nprod, blocks, p->stream);
+            } else {
+                for (int q = 0; q < nprod; ++q) {
+                    const ProdDev &P = p->hprods[q];
+                    if (P.bmw > 0)
+                        launch_brow_bitmap(B[q].row_ptr, B[q].col_idx, B[q].nrows, B[q].ncols,
+                                           P.bmw, const_cast<uint32_t *>(P.bmB), p->stream);
+                }
+            }
+        }
+    }
 
     return SPGEMM_OK;
 }
@@ -919,8 +937,15 @@ spgemm_status device_launch_all(spgemm_plan *p, hipStream_t st, int64_t *const *
     // the arena: capacity check (kErrCapacity stops the numeric kernels),
     // each product's offset and its own row pointers
     launch_arena_check(p->rptv, M, capacity, p->flags, p->dprods, nprod, c_offsets, st);
-    for (int q = 0; q < nprod; ++q)
-        launch_rows_local(p->rptv, p->hprods[q].row_base, p->hprods[q].m, c_row_ptr[q], st);
+    // every product's own row pointers (the descriptors carry c_row_ptr),
+    // one launch for the batch
+    if (nprod <= 65535) {
+        launch_rows_local_batch(p->dprods, nprod, std::max<int64_t>(1, (M / nprod + 256) / 256),
+                                p->rptv, st);
+    } else {
+        for (int q = 0; q < nprod; ++q)
+            launch_rows_local(p->rptv, p->hprods[q].row_base, p->hprods[q].m, c_row_ptr[q], st);
+    }
     // accumulation phase
     const int64_t *ns = p->starts + (kGroups + 1);
     for (int g = 1; g <= std::min(p->num_hi, 4); ++g)
@@ -1507,6 +1532,7 @@ spgemm_status spgemm_execute_arena(spgemm_plan *p, const float *const *a_values,
         p->hprods[q].valB = b_values[q];
         p->hprods[q].colC = c_col;
         p->hprods[q].valC = c_val;
+        p->hprods[q].rptC = c_row_ptr[q];
         p->hprods[q].c_arena = 1;
     }
     ST_TRY(upload_descriptors(p));

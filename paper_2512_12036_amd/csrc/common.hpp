@@ -56,6 +56,7 @@ struct ProdDev {
     int32_t bmw;        // words per row of bmB (0: no bitmaps)
     const uint32_t *bmB;  // B's rows as column bitmaps (B with at most kBitmapCols
                           // columns), row k at bmB + k * bmw
+    int64_t *rptC;        // device-driven plans: C's row pointers of this product
 };
 
 // One work item of group 7: the chunks q, q + Q, ... (K of them) of one row,
@@ -303,6 +304,17 @@ bool launch_num_chunk_rank(int wmax, const ProdDev *prods, const ChunkDesc *desc
 // k.  Columns outside [0, ncols) are ignored.
 void launch_brow_bitmap(const int64_t *rptB, const int32_t *colB, int64_t nrows, int64_t ncols,
                         int bmw, uint32_t *out, hipStream_t s);
+
+// The same for every product of a batch whose descriptor has bitmaps, in
+// one launch of row_blocks x nprod workgroups (each a stride over its
+// product's B rows, 16 rows at a time); nprod <= 65535.
+void launch_brow_bitmap_batch(const ProdDev *prods, int nprod, int64_t row_blocks,
+                              hipStream_t s);
+// Every product's own row pointers (prods[q].rptC, m + 1 entries) from the
+// batch's (rptv), in one launch of row_blocks x nprod workgroups of 256
+// threads; nprod <= 65535.
+void launch_rows_local_batch(const ProdDev *prods, int nprod, int64_t row_blocks,
+                             const int64_t *rptv, hipStream_t s);
 
 void launch_ip_estimate(const int64_t *rptA, const int32_t *colA, const int64_t *rptB, int64_t m,
                         int64_t ncols, int64_t *out, hipStream_t s);

@@ -543,6 +543,59 @@ void launch_brow_bitmap(const int64_t *rptB, const int32_t *colB, int64_t nrows,
                        nrows, ncols, bmw, out);
 }
 
+// The same for every product of a batch in one launch: workgroup row y is
+// product y (products without bitmaps leave at once), and its workgroups
+// walk the product's B rows with a stride of the grid's width.
+__global__ __launch_bounds__(256) void k_brow_bitmap_batch(const ProdDev *__restrict__ prods) {
+    constexpr int kWords = (int)(kBitmapCols / 32);
+    constexpr int kLanes = 16;
+    static_assert(kLanes == kWords, "one word per lane of a row");
+    __shared__ uint32_t words[256 / kLanes][kWords];
+    const ProdDev &P = prods[blockIdx.y];
+    const int bmw = P.bmw;
+    if (bmw == 0) return;  // workgroup-uniform
+    const int sub = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
+    uint32_t *out = const_cast<uint32_t *>(P.bmB);
+    for (int64_t k = (int64_t)blockIdx.x * (256 / kLanes) + sub; k < P.k;
+         k += (int64_t)gridDim.x * (256 / kLanes)) {
+        words[sub][lane] = 0u;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        const int64_t b0 = P.rptB[k], b1 = P.rptB[k + 1];
+        for (int64_t t = b0 + lane; t < b1; t += kLanes) {
+            const int c = P.colB[t];
+            if (c >= 0 && c < P.n) atomicOr(&words[sub][c >> 5], 1u << (c & 31));
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (lane < bmw) out[k * bmw + lane] = words[sub][lane];
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // words read before the next row
+    }
+}
+
+void launch_brow_bitmap_batch(const ProdDev *prods, int nprod, int64_t row_blocks,
+                              hipStream_t s) {
+    if (nprod <= 0 || row_blocks <= 0) return;
+    hipLaunchKernelGGL(k_brow_bitmap_batch, dim3((unsigned)row_blocks, (unsigned)nprod),
+                       dim3(256), 0, s, prods);
+}
+
+// Every product's own row pointers (prods[q].rptC, m + 1 entries) from the
+// batch's: workgroup row y is product y, its workgroups stride its rows.
+__global__ __launch_bounds__(256) void k_rows_local_batch(const ProdDev *__restrict__ prods,
+                                                          const int64_t *__restrict__ rptv) {
+    const ProdDev &P = prods[blockIdx.y];
+    const int64_t r0 = rptv[P.row_base];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i <= P.m;
+         i += (int64_t)gridDim.x * 256)
+        P.rptC[i] = rptv[P.row_base + i] - r0;
+}
+
+void launch_rows_local_batch(const ProdDev *prods, int nprod, int64_t row_blocks,
+                             const int64_t *rptv, hipStream_t s) {
+    if (nprod <= 0 || row_blocks <= 0) return;
+    hipLaunchKernelGGL(k_rows_local_batch, dim3((unsigned)row_blocks, (unsigned)nprod),
+                       dim3(256), 0, s, prods, rptv);
+}
+
 // Row-size estimation alone (Algorithm 1), aggregated: 16 lanes per row sum
 // the lengths of the B rows the row's A nonzeros name; out[0] += sum of the
 // rows' intermediate products, out[1] += sum of min(ip, ncols) (a bound of
