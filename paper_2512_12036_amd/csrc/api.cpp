@@ -1431,10 +1431,20 @@ spgemm_status spgemm_symbolic_batch(spgemm_plan *p, int64_t *const *c_row_ptr, i
     spgemm_status s;
     try { s = symbolic_impl(p); } catch (...) { s = SPGEMM_ENOMEM; }
     if (s != SPGEMM_OK) return s;
-    for (int q = 0; q < p->nprod; ++q) {
-        launch_rows_local(p->rptv, p->hprods[q].row_base, p->hprods[q].m, c_row_ptr[q], p->stream);
-        nnz_c[q] = p->nnz_c[q];
+    if (p->nprod > 1 && p->nprod <= 65535) {
+        // every product's row pointers in one launch (the descriptors carry
+        // c_row_ptr)
+        for (int q = 0; q < p->nprod; ++q) p->hprods[q].rptC = c_row_ptr[q];
+        ST_TRY(upload_descriptors(p));
+        launch_rows_local_batch(p->dprods, p->nprod,
+                                std::max<int64_t>(1, (p->Mtot / p->nprod + 256) / 256), p->rptv,
+                                p->stream);
+    } else {
+        for (int q = 0; q < p->nprod; ++q)
+            launch_rows_local(p->rptv, p->hprods[q].row_base, p->hprods[q].m, c_row_ptr[q],
+                              p->stream);
     }
+    for (int q = 0; q < p->nprod; ++q) nnz_c[q] = p->nnz_c[q];
     return launch_check();
 }
 
