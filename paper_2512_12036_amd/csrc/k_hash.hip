@@ -311,19 +311,20 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     sym_group_rows<G>(prods, items, count, row_nnz, err, blk);
 }
 
-template <int G>
+// TB threads per workgroup: TB / G rows, each a group of G lanes.
+template <int G, int TB>
 __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods,
                                                const uint64_t *__restrict__ items, int64_t count,
                                                const int64_t *__restrict__ rptv,
                                                int *__restrict__ err, int64_t blk) {
-    constexpr int T = 8 * G, R = 256 / G, LOG2T = Log2<T>::v, PER = T / G;
+    constexpr int T = 8 * G, R = TB / G, LOG2T = Log2<T>::v, PER = T / G;
     __shared__ int keys[R * T];
     __shared__ float vals[R * (T + G)];  // per group: T slots + G dummy slots
-    __shared__ int64_t st_s[256];
+    __shared__ int64_t st_s[TB];
     __shared__ int st_e[R * (G + 1)];
-    __shared__ float st_a[256];
-    for (int s = threadIdx.x; s < R * T; s += 256) keys[s] = kEmptyKey;
-    for (int s = threadIdx.x; s < R * (T + G); s += 256) vals[s] = 0.f;
+    __shared__ float st_a[TB];
+    for (int s = threadIdx.x; s < R * T; s += TB) keys[s] = kEmptyKey;
+    for (int s = threadIdx.x; s < R * (T + G); s += TB) vals[s] = 0.f;
     __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t it = blk * R + gi;
@@ -409,20 +410,20 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
     }
 }
 
-template <int G, bool DEV>
-__global__ __launch_bounds__(256) void k_num_group(const ProdDev *__restrict__ prods,
-                                                    const uint64_t *__restrict__ items,
-                                                    int64_t count, const int64_t *__restrict__ rptv,
-                                                    int *__restrict__ err,
-                                                    const int64_t *__restrict__ gstart, int gsel) {
-    constexpr int R = 256 / G;
+template <int G, bool DEV, int TB>
+__global__ __launch_bounds__(TB) void k_num_group(const ProdDev *__restrict__ prods,
+                                                   const uint64_t *__restrict__ items,
+                                                   int64_t count, const int64_t *__restrict__ rptv,
+                                                   int *__restrict__ err,
+                                                   const int64_t *__restrict__ gstart, int gsel) {
+    constexpr int R = TB / G;
     const int64_t blk = lin_block();
     if constexpr (DEV) {
         group_range(gstart, gsel, items, count);
         if (blk * R >= count) return;  // block-uniform
         if (*err & kErrCapacity) return;  // C does not fit its arena (block-uniform)
     }
-    num_group_rows<G>(prods, items, count, rptv, err, blk);
+    num_group_rows<G, TB>(prods, items, count, rptv, err, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,13 +738,16 @@ void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items, int64_
     }
 }
 
+// The 64-lane group runs one row per workgroup: its rows vary in length, and
+// a workgroup of several rows waits at its barriers for the longest.
 template <int G>
 static void num_group_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
                              const int64_t *rptv, int *err, hipStream_t s, const int64_t *gstart,
                              int gsel) {
-    constexpr int R = 256 / G;
+    constexpr int TB = G == 64 ? 64 : 256;
+    constexpr int R = TB / G;
     const int64_t nb = (count + R - 1) / R;
-    launch_rows(k_num_group<G, false>, k_num_group<G, true>, nb, nb, 256, s, gstart,
+    launch_rows(k_num_group<G, false, TB>, k_num_group<G, true, TB>, nb, nb, TB, s, gstart,
                 prods, items, count, rptv, err, gstart, gsel);
 }
 
