@@ -881,6 +881,14 @@ int last_group(const int64_t *upper, int64_t max_ncols) {
     return hi;
 }
 
+// The most columns of any product's B in the plan (the group kernels hold no
+// key table when every B fits their direct-mapped table).
+int64_t max_b_cols(const spgemm_plan *p) {
+    int64_t m = 0;
+    for (int q = 0; q < p->nprod; ++q) m = std::max(m, p->hprods[q].n);
+    return m;
+}
+
 spgemm_status device_plan_setup(spgemm_plan *p, int nprod, const spgemm_csr *A,
                                 const spgemm_csr *B) {
     if (p->opt.validate || p->opt.row_thread) return SPGEMM_EINVAL;
@@ -949,7 +957,8 @@ spgemm_status device_launch_all(spgemm_plan *p, hipStream_t st, int64_t *const *
     // accumulation phase
     const int64_t *ns = p->starts + (kGroups + 1);
     for (int g = 1; g <= std::min(p->num_hi, 4); ++g)
-        launch_num_group(g, p->dprods, p->map_num, M, p->rptv, p->flags, st, ns, g);
+        launch_num_group(g, p->dprods, p->map_num, M, p->rptv, p->flags, st, ns, g,
+                         max_b_cols(p));
     for (int g = 5; g <= p->num_hi; ++g)
         launch_num_block(g, p->opt.num_upper[g], p->dprods, p->map_num, M, p->rptv, p->flags, st,
                          ns, g);
@@ -1209,7 +1218,8 @@ spgemm_status numeric_launch(spgemm_plan *p, hipStream_t st) {
             continue;
         }
         launch_num_group(g, p->dprods, p->map_num + p->num_start[g],
-                         p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st);
+                         p->num_start[g + 1] - p->num_start[g], p->rptv, p->flags, st, nullptr,
+                         0, max_b_cols(p));
     }
     for (int g = 5; g <= 6; ++g) {
         if (p->num_start[g + 1] == p->num_start[g]) continue;

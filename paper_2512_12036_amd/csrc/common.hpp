@@ -263,9 +263,12 @@ void launch_sym_chunk(int wmax, bool fast, const ProdDev *prods, const ChunkDesc
                       const uint32_t *sabs, int64_t nitems, int kper, int64_t *chunk_cnt,
                       int64_t *row_nnz, uint32_t *sbits, int wpc, int wgs_per_cu, int threads,
                       int *err, hipStream_t s);
+// max_ncols: the most columns of any product's B in the batch; when every B
+// fits the group's direct-mapped table, a launch without a key table runs.
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s,
-                      const int64_t *gstart = nullptr, int gsel = 0);
+                      const int64_t *gstart = nullptr, int gsel = 0,
+                      int64_t max_ncols = INT64_MAX);
 void launch_num_block(int g, int64_t upper, const ProdDev *prods, const uint64_t *items,
                       int64_t count, const int64_t *rptv, int *err, hipStream_t s,
                       const int64_t *gstart = nullptr, int gsel = 0);

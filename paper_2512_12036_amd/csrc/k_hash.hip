@@ -149,6 +149,50 @@ __device__ __forceinline__ void lds_add_direct_many(int *tab, float *vals, const
     lds_fadd_many<U>(vals, slot, v);
 }
 
+// Direct-mapped accumulation without keys, for the group kernels: a value
+// slot that no product reached holds the bit pattern kEmptyVal.  The first
+// product of a slot adds to 0 (as a zero-initialised slot would), and a sum
+// whose bits happen to equal kEmptyVal (a NaN) is stored as the canonical
+// quiet NaN, so a slot is occupied exactly when its bits differ from
+// kEmptyVal.  This saves the key store of every product.  Unused entries
+// (ok false) add 0 to the lane's dummy slot, which starts at 0.
+constexpr uint32_t kEmptyVal = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t fold_slot(uint32_t cur, float add) {
+    const float base = cur == kEmptyVal ? 0.f : __uint_as_float(cur);
+    const uint32_t r = __float_as_uint(base + add);
+    return r == kEmptyVal ? 0x7FC00000u : r;
+}
+
+template <int U>
+__device__ __forceinline__ void lds_add_direct_nokey(float *vals, const int *cc, const float *add,
+                                                     const bool *ok, int dummy) {
+    uint32_t *q = reinterpret_cast<uint32_t *>(vals);
+    int slot[U];
+    float v[U];
+    uint32_t cur[U], prev[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        slot[u] = ok[u] ? cc[u] : dummy;
+        v[u] = ok[u] ? add[u] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        cur[u] = __hip_atomic_load(q + slot[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int u = 0; u < U; ++u) prev[u] = atomicCAS(q + slot[u], cur[u], fold_slot(cur[u], v[u]));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        uint32_t c = prev[u];
+        bool pending = prev[u] != cur[u];
+        while (pending) {
+            const uint32_t p = atomicCAS(q + slot[u], c, fold_slot(c, v[u]));
+            pending = p != c;
+            c = p;
+        }
+    }
+}
+
 template <int N>
 struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
 template <>
@@ -311,32 +355,42 @@ __global__ __launch_bounds__(256) void k_sym_group(const ProdDev *__restrict__ p
     sym_group_rows<G>(prods, items, count, row_nnz, err, blk);
 }
 
-// TB threads per workgroup: TB / G rows, each a group of G lanes.
-template <int G, int TB>
+// TB threads per workgroup: TB / G rows, each a group of G lanes.  DONLY:
+// every product's B fits the direct-mapped table (the launcher checked), so
+// no key table is held and the workgroup needs less LDS.
+template <int G, int TB, bool DONLY>
 __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods,
                                                const uint64_t *__restrict__ items, int64_t count,
                                                const int64_t *__restrict__ rptv,
                                                int *__restrict__ err, int64_t blk) {
     constexpr int T = 8 * G, R = TB / G, LOG2T = Log2<T>::v, PER = T / G;
-    __shared__ int keys[R * T];
+    __shared__ int keys[DONLY ? 1 : R * T];
     __shared__ float vals[R * (T + G)];  // per group: T slots + G dummy slots
     __shared__ int64_t st_s[TB];
     __shared__ int st_e[R * (G + 1)];
     __shared__ float st_a[TB];
-    for (int s = threadIdx.x; s < R * T; s += TB) keys[s] = kEmptyKey;
-    for (int s = threadIdx.x; s < R * (T + G); s += TB) vals[s] = 0.f;
-    __syncthreads();
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t it = blk * R + gi;
     const bool active = it < count;
     int *tab = keys + gi * T;
     float *tv = vals + gi * (T + G);
+    uint32_t *tvb = reinterpret_cast<uint32_t *>(tv);
     uint64_t e = 0;
-    bool direct = false;
+    bool direct = DONLY;
     if (active) {
         e = items[it];
+        direct = DONLY || prods[item_prod(e)].n <= T;
+    }
+    // each group clears its own table: direct-mapped ones hold no keys and
+    // mark untouched value slots with kEmptyVal
+    if (!direct)
+        for (int s = lane; s < T; s += G) tab[s] = kEmptyKey;
+    const uint32_t fill = direct ? kEmptyVal : 0u;
+    for (int s = lane; s < T; s += G) tvb[s] = fill;
+    tvb[T + lane] = 0u;
+    __syncthreads();
+    if (active) {
         const ProdDev &P = prods[item_prod(e)];
-        direct = P.n <= T;
         group_products<G, 4, true>(
             P, item_row(e), lane, st_s + gi * G, st_e + gi * (G + 1), st_a + gi * G,
             [&](const int *cc, const float *aa, const float *vb, const bool *ok) {
@@ -344,7 +398,7 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
 #pragma unroll
                 for (int u = 0; u < 4; ++u) add[u] = aa[u] * vb[u];
                 if (direct)
-                    lds_add_direct_many<4>(tab, tv, cc, add, ok, T + lane);
+                    lds_add_direct_nokey<4>(tv, cc, add, ok, T + lane);
                 else
                     lds_add_many<4>(tab, tv, T - 1, LOG2T, cc, add, ok, T + lane, err);
             });
@@ -357,9 +411,16 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
     int mine = 0;
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const int q = direct ? lane * PER + r : lane + G * r;
-        kk[r] = tab[q];
-        vv[r] = tv[q];
+        if (direct) {
+            const int q = lane * PER + r;
+            const uint32_t b = tvb[q];
+            kk[r] = b != kEmptyVal ? q : kEmptyKey;
+            vv[r] = __uint_as_float(b);
+        } else {
+            const int q = lane + G * r;
+            kk[r] = tab[q];
+            vv[r] = tv[q];
+        }
         mine += kk[r] != kEmptyKey;
     }
     const int incl = seg_incl_scan<G>(mine);
@@ -410,7 +471,7 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
     }
 }
 
-template <int G, bool DEV, int TB>
+template <int G, bool DEV, int TB, bool DONLY>
 __global__ __launch_bounds__(TB) void k_num_group(const ProdDev *__restrict__ prods,
                                                    const uint64_t *__restrict__ items,
                                                    int64_t count, const int64_t *__restrict__ rptv,
@@ -423,7 +484,7 @@ __global__ __launch_bounds__(TB) void k_num_group(const ProdDev *__restrict__ pr
         if (blk * R >= count) return;  // block-uniform
         if (*err & kErrCapacity) return;  // C does not fit its arena (block-uniform)
     }
-    num_group_rows<G, TB>(prods, items, count, rptv, err, blk);
+    num_group_rows<G, TB, DONLY>(prods, items, count, rptv, err, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -743,23 +804,27 @@ void launch_sym_group(int g, const ProdDev *prods, const uint64_t *items, int64_
 template <int G>
 static void num_group_launch(const ProdDev *prods, const uint64_t *items, int64_t count,
                              const int64_t *rptv, int *err, hipStream_t s, const int64_t *gstart,
-                             int gsel) {
+                             int gsel, int64_t max_ncols) {
     constexpr int TB = G == 64 ? 64 : 256;
     constexpr int R = TB / G;
     const int64_t nb = (count + R - 1) / R;
-    launch_rows(k_num_group<G, false, TB>, k_num_group<G, true, TB>, nb, nb, TB, s, gstart,
-                prods, items, count, rptv, err, gstart, gsel);
+    if (max_ncols <= 8 * G)
+        launch_rows(k_num_group<G, false, TB, true>, k_num_group<G, true, TB, true>, nb, nb, TB,
+                    s, gstart, prods, items, count, rptv, err, gstart, gsel);
+    else
+        launch_rows(k_num_group<G, false, TB, false>, k_num_group<G, true, TB, false>, nb, nb,
+                    TB, s, gstart, prods, items, count, rptv, err, gstart, gsel);
 }
 
 void launch_num_group(int g, const ProdDev *prods, const uint64_t *items, int64_t count,
                       const int64_t *rptv, int *err, hipStream_t s, const int64_t *gstart,
-                      int gsel) {
+                      int gsel, int64_t max_ncols) {
     if (count <= 0) return;
     switch (g) {
-        case 1: num_group_launch<8>(prods, items, count, rptv, err, s, gstart, gsel); break;
-        case 2: num_group_launch<16>(prods, items, count, rptv, err, s, gstart, gsel); break;
-        case 3: num_group_launch<32>(prods, items, count, rptv, err, s, gstart, gsel); break;
-        case 4: num_group_launch<64>(prods, items, count, rptv, err, s, gstart, gsel); break;
+        case 1: num_group_launch<8>(prods, items, count, rptv, err, s, gstart, gsel, max_ncols); break;
+        case 2: num_group_launch<16>(prods, items, count, rptv, err, s, gstart, gsel, max_ncols); break;
+        case 3: num_group_launch<32>(prods, items, count, rptv, err, s, gstart, gsel, max_ncols); break;
+        case 4: num_group_launch<64>(prods, items, count, rptv, err, s, gstart, gsel, max_ncols); break;
         default: break;
     }
 }
