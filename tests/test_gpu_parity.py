@@ -436,3 +436,39 @@ def test_row_bitmap_counts(group, ncols):
     opt = None if group is None else forced_options(group)
     run_and_compare(a, b, options=opt, exact=True, b_sorted=False,
                     label=f"bitmap g{group} n{ncols}")
+
+
+@pytest.mark.parametrize("group", [1, 2, 3, 4, None])
+def test_direct_mapped_nan_values(group):
+    """The group kernels' direct-mapped tables mark an untouched value slot
+    with the all-ones bit pattern (a NaN) instead of a key.  B values that
+    are NaN, and B values with exactly that bit pattern, must still leave
+    their outputs in the structure (the structure never depends on values):
+    row pointers and columns equal the oracle's, NaN outputs sit where the
+    oracle's are, and every other (integer-valued) output is exact."""
+    import torch
+    ncols = 8 * (8, 16, 32, 64)[(group or 4) - 1]   # fits the table: direct-mapped
+    rng = np.random.default_rng(100 + (group or 0))
+    a = gen.int_valued(gen.skewed_csr(1300, 700, seed=110 + (group or 0), max_len=25,
+                                      heavy_rows=0), 6)
+    b = gen.int_valued(gen.random_csr(700, ncols, min(0.5, 24.0 / ncols), 120 + (group or 0)),
+                       7)
+    bv = b.val.copy()
+    pick = rng.random(bv.size)
+    bv[pick < 0.02] = np.float32("nan")
+    bits = bv.view(np.uint32)
+    bits[(pick >= 0.02) & (pick < 0.04)] = np.uint32(0xFFFFFFFF)
+    b = b.with_values(bv)
+    opts = forced_options(group) if group else None
+    log(f"[gpu] direct nan g{group}: B {b.nrows}x{b.ncols} nnz {b.nnz}, "
+        f"{int((pick < 0.04).sum())} NaN values")
+    c = spgemm.matmul(spgemm.to_device(a), spgemm.to_device(b), opts)
+    torch.cuda.synchronize()
+    ref = oracle.product(a, b)
+    rpt, col, val = c.rpt.cpu().numpy(), c.col.cpu().numpy(), c.val.cpu().numpy()
+    assert np.array_equal(rpt, ref.rpt), "row pointers"
+    assert np.array_equal(col, ref.col), "columns"
+    gnan, rnan = np.isnan(val), np.isnan(ref.val)
+    assert rnan.any(), "the case holds NaN outputs"
+    assert np.array_equal(gnan, rnan), "NaN outputs"
+    assert np.array_equal(val[~gnan].astype(np.float64), ref.val[~rnan]), "values"
