@@ -878,7 +878,7 @@ def _read_counter_pass(folder):
 
 
 def _short_name(name):
-    n = name.replace("spg::", "").replace("void ", "")
+    n = name.replace("spg::", "").replace("void ", "").replace("(anonymous namespace)::", "")
     return n.split("(")[0]
 
 
@@ -1039,38 +1039,66 @@ def summarize_counters(root, copy_mib):
     print("\n".join(lines))
 
 
-def summarize_kernel_stats(path):
-    """profiles/rmat18_kernel_stats.md from a rocprofv3 --stats kernel_stats.csv
-    of bench.py --steps 5 --warmup 2 --no-cpu --serve-requests 0 --no-configs."""
+KERNEL_STATS = {
+    "rmat18": {
+        "file": "rmat18_kernel_stats.md",
+        "title": "Kernel time, R-MAT scale 18 self-product (bench.py default workload)",
+        "what": "one MI355X, 5 timed + 2 warm-up steps, so 7 launches of each per-step kernel; "
+                "the symbolic-phase kernels run once more, for the group statistics",
+        "args": "--steps 5 --warmup 2 --no-cpu --serve-requests 0 --no-configs",
+        "note": "Launch groups named in bench.py's `phases_ms`: `num.g7` = `k_num_chunk_pipe` "
+                "(dense chunks), `num.g7r` = `k_num_chunk_rank` (four launches: single light "
+                "chunks, 8192 columns, and merged light chunks, 16384 columns, each with a "
+                "2048- and a 1024-slot accumulator), `sym.g7` = `k_sym_chunk_pipe`, "
+                "`num.g5`/`num.g6` = `k_num_block`, `sym.g5`/`sym.g6` = `k_sym_block`, "
+                "`plan.ipcount` = `k_ipcount` + `k_ip_groups`, `plan.split` = `k_bsplit` + "
+                "`k_sabs` + `k_chunk_items` + item descriptors and scans."},
+    "served": {
+        "file": "served_gnn_kernel_stats.md",
+        "title": "Kernel time, served GNN aggregation trace (1,024 requests C = A_hat X)",
+        "what": "one MI355X; the plain loop (one warm-up and three timed passes) and the three "
+                "server configurations (each a warm-up, three timed backlogged passes and a "
+                "Poisson pass) over the same 1,024 requests, so every request's product runs "
+                "20 times; the graph store's generation runs once",
+        "args": "--only served --no-cpu --serve-requests 1024",
+        "note": "Every B (X) of this trace has at most 512 columns, so every row takes the "
+                "group kernels with direct-mapped tables: `k_num_group<G, ..., true>` is the "
+                "instantiation without a key table, and the symbolic phase counts from B's row "
+                "bitmaps (`k_sym_group`, built by `k_brow_bitmap_batch`).  `k_gnn_features` "
+                "builds each X when its request is admitted.  Batches on the server's four "
+                "streams overlap, so a dispatch's duration includes time shared with other "
+                "streams' kernels, and the totals add up to more than the run's wall time."},
+}
+
+
+def summarize_kernel_stats(path, workload="rmat18"):
+    """profiles/<workload>_kernel_stats.md from a rocprofv3 --stats
+    kernel_stats.csv of the bench command named in KERNEL_STATS."""
     import csv
+    k = KERNEL_STATS[workload]
     with open(path) as fh:
         rows = list(csv.DictReader(fh))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    lines = ["# Kernel time, R-MAT scale 18 self-product (bench.py default workload)", "",
-             "Command (one MI355X, 5 timed + 2 warm-up steps, so 7 launches of each per-step "
-             "kernel; the symbolic-phase kernels run once more, for the group statistics):", "",
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {k['title']}", "", f"Command ({k['what']}):", "",
              "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d <out> -o run "
-             "--output-format csv -- python3 /root/repo/bench.py --steps 5 --warmup 2 --no-cpu "
-             "--serve-requests 0 --no-configs", "",
+             f"--output-format csv -- python3 /root/repo/bench.py {k['args']}", "",
              "reduced by", "",
-             "    python3 bench.py --summarize-kernel-stats <out>/run_kernel_stats.csv", "",
-             "`rocprofv3 --stats` summary, kernels above 0.05 % of GPU time:", "",
-             "| kernel | calls | average (ms) | min (ms) | max (ms) | share |",
-             "|---|---|---|---|---|---|"]
+             f"    python3 bench.py --summarize-kernel-stats <out>/run_kernel_stats.csv "
+             f"--kernel-stats-workload {workload}", "",
+             f"`rocprofv3 --stats` summary, kernels above 0.05 % of GPU time "
+             f"({total / 1e6:.1f} ms of kernel time in all):", "",
+             "| kernel | calls | total (ms) | average (ms) | min (ms) | max (ms) | share |",
+             "|---|---|---|---|---|---|---|"]
     for r in rows:
         if float(r["Percentage"]) < 0.05:
             continue
         lines.append(f"| `{_short_name(r['Name'])[:140]}` | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
                      f"{float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} % |")
-    lines += ["", "Launch groups named in bench.py's `phases_ms`: `num.g7` = `k_num_chunk_pipe` "
-                  "(dense chunks), `num.g7r` = `k_num_chunk_rank` (four launches: single light "
-                  "chunks, 8192 columns, and merged light chunks, 16384 columns, each with a "
-                  "2048- and a 1024-slot accumulator), `sym.g7` = `k_sym_chunk_pipe`, "
-                  "`num.g5`/`num.g6` = `k_num_block`, `sym.g5`/`sym.g6` = `k_sym_block`, "
-                  "`plan.ipcount` = `k_ipcount` + `k_ip_groups`, `plan.split` = `k_bsplit` + "
-                  "`k_sabs` + `k_chunk_items` + item descriptors and scans.", ""]
-    with open(os.path.join(ROOT, "profiles", "rmat18_kernel_stats.md"), "w") as fh:
+    lines += ["", k["note"], ""]
+    with open(os.path.join(ROOT, "profiles", k["file"]), "w") as fh:
         fh.write("\n".join(lines))
     print("\n".join(lines))
 
@@ -1098,11 +1126,13 @@ def main():
                          "(subfolders fetch, write, req, tcc, td) to the traffic summary in "
                          "profiles/")
     ap.add_argument("--summarize-kernel-stats", default="",
-                    help="no GPU work: write profiles/rmat18_kernel_stats.md from this "
+                    help="no GPU work: write profiles/<workload>_kernel_stats.md from this "
                          "rocprofv3 kernel_stats.csv")
+    ap.add_argument("--kernel-stats-workload", default="rmat18", choices=sorted(KERNEL_STATS),
+                    help="which profiled command the kernel_stats.csv comes from")
     args = ap.parse_args()
     if args.summarize_kernel_stats:
-        summarize_kernel_stats(args.summarize_kernel_stats)
+        summarize_kernel_stats(args.summarize_kernel_stats, args.kernel_stats_workload)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.calib_copy_mib or 1024)

@@ -19,3 +19,19 @@ def test_kept_columns_match_reference_generator():
         n, f, nk = gen.gnn_features_shape(seed, n=20)
         x = gen.gnn_features_t(seed, "cpu", n=n)
         assert np.array_equal(gen.gnn_kept_columns(seed, f, nk), x.col[:nk].numpy())
+
+
+
+def test_feature_values_from_the_stream():
+    """X's values, restated from the stream definition with numpy: entry e
+    (row-major over the n x nk block) is (bits 63..40 of hash e of stream 4,
+    plus one) / 2^24, and the row pointers step by nk."""
+    for seed, n in ((5, 7), (77, 20), (4095, 33)):
+        _, f, nk = gen.gnn_features_shape(seed, n=n)
+        x = gen.gnn_features_t(seed, "cpu", n=n)
+        h = gen._stream_np(seed, 4, n * nk).view(np.uint64)
+        k = (h >> np.uint64(40)) + np.uint64(1)
+        want = (k.astype(np.float64) / float(1 << 24)).astype(np.float32)
+        assert np.array_equal(x.val.numpy(), want)
+        assert x.val.numpy().min() > 0 and x.val.numpy().max() <= 1
+        assert np.array_equal(x.rpt.numpy(), np.arange(n + 1) * nk)

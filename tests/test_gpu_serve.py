@@ -174,8 +174,11 @@ def test_device_feature_generator_matches_host():
     """The one-kernel feature generator of the served requests equals the
     reference generator run on the host, bit for bit."""
     import torch
-    for seed in (3, 900, 4095):
-        n, f, nk = gen.gnn_features_shape(seed, n=5000)
+    odd = 0
+    for seed, n in ((3, 5000), (900, 5000), (4095, 5000), (17, 4999), (18, 4999), (19, 1),
+                    (20, 0)):
+        n, f, nk = gen.gnn_features_shape(seed, n=n)
+        odd += (n * nk) % 2
         kept = torch.from_numpy(gen.gnn_kept_columns(seed, f, nk)).cuda()
         xd = gen.gnn_features_device(seed, kept, n, f)
         xh = gen.gnn_features_t(seed, "cpu", n=n)
@@ -183,6 +186,7 @@ def test_device_feature_generator_matches_host():
         assert torch.equal(xd.rpt.cpu(), xh.rpt)
         assert torch.equal(xd.col.cpu(), xh.col)
         assert torch.equal(xd.val.cpu(), xh.val)
+    assert odd > 0, "no case with an odd entry count"
 
 
 def test_device_driven_server_same_results():
