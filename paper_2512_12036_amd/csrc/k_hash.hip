@@ -372,7 +372,7 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
     const int gi = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t it = blk * R + gi;
     const bool active = it < count;
-    int *tab = keys + gi * T;
+    int *tab = keys + (DONLY ? 0 : gi * T);  // not used when DONLY
     float *tv = vals + gi * (T + G);
     uint32_t *tvb = reinterpret_cast<uint32_t *>(tv);
     uint64_t e = 0;
