@@ -404,15 +404,15 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
             });
     }
     __syncthreads();
-    // gather: in hash mode each lane owns slots lane + G*r; direct-mapped, the
-    // contiguous slots lane*PER + r, so the scan below yields column order
+    // gather: each lane owns slots lane + G*r (round r of the group covers
+    // slots r*G .. r*G + G - 1, in lane order)
     int kk[PER];
     float vv[PER];
     int mine = 0;
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         if (direct) {
-            const int q = lane * PER + r;
+            const int q = lane + G * r;
             const uint32_t b = tvb[q];
             kk[r] = b != kEmptyVal ? q : kEmptyKey;
             vv[r] = __uint_as_float(b);
@@ -438,17 +438,28 @@ __device__ __forceinline__ void num_group_rows(const ProdDev *__restrict__ prods
     const int64_t g = P.row_base + item_row(e);
     const int64_t expect = rptv[g + 1] - rptv[g];
     if (lane == 0 && n != expect) atomicOr(err, kErrCount);
-    if (direct) {  // already in column order
+    if (direct) {
+        // slot = column, so the rounds are in column order: an entry's
+        // place is the entries of the earlier rounds plus the group's lanes
+        // below it in its round (a ballot over the group's lanes), and each
+        // round's stores are consecutive
         const int64_t base = c_base(P, rptv, g);
+        const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);  // group's first lane in the wave
+        const uint64_t below = (1ull << lane) - 1ull;
+        int run = 0;
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            if (kk[r] != kEmptyKey) {
-                if (pos < expect) {
-                    gst(P.colC + base + pos, kk[r]);
-                    gst(P.valC + base + pos, vv[r]);
+            const bool occ = kk[r] != kEmptyKey;
+            uint64_t b = __ballot(occ);
+            if (G < 64) b = (b >> gbase) & ((1ull << (G & 63)) - 1ull);
+            if (occ) {
+                const int q = run + __popcll(b & below);
+                if (q < expect) {
+                    gst(P.colC + base + q, kk[r]);
+                    gst(P.valC + base + q, vv[r]);
                 }
-                ++pos;
             }
+            run += __popcll(b);
         }
         return;
     }
